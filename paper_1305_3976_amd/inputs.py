@@ -1,0 +1,246 @@
+"""Seeded synthetic inputs for the IB-GM path (membranes, link networks and
+initial velocity fields).
+
+This module holds no arithmetic of the method itself: it only builds initial
+positions, connectivity, per-point weights and initial fluid fields.  Both the
+HIP path and the CPU oracle consume what it returns, so it lives on its own.
+
+Conventions: grid arrays have shape (n2, n1, n0) (x fastest; n2 = 1 in 2D) and
+the MAC component c lives on the faces normal to axis c (integer index along c,
+half-integer along the others).  Lagrangian arrays have shape (dim, np).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass
+class Structure:
+    """Lagrangian points joined by elastic links.
+
+    X       (dim, np) float64 initial positions
+    links   (a, b, kappa, l0): int32, int32, float64, float64 arrays; each link
+            pulls a and b together with kappa (X_b - X_a)(1 - l0/|X_b - X_a|)
+    w       (np,) float64 spreading weight of each point (h_s for a fiber
+            force density, 1 for a total nodal force)
+    """
+    X: np.ndarray
+    links: tuple
+    w: np.ndarray
+
+    @property
+    def np(self) -> int:
+        return int(self.X.shape[1])
+
+    @property
+    def nlinks(self) -> int:
+        return int(len(self.links[0]))
+
+
+def closed_fiber_links(npts: int, sigma: float, L: float = 0.0, offset: int = 0):
+    """Links of one closed fiber with points offset..offset+npts-1 and
+    parameter spacing h_s = 1/npts.  The fiber force density
+    sigma D_s^-(D_s^+ X (1 - L/|D_s^+ X|)) equals the link form with
+    kappa = sigma/h_s^2 and l0 = L h_s (force-connection form)."""
+    hs = 1.0 / npts
+    a = np.arange(npts, dtype=np.int32) + offset
+    b = (np.arange(npts, dtype=np.int32) + 1) % npts + offset
+    k = np.full(npts, sigma / hs ** 2)
+    l0 = np.full(npts, L * hs)
+    return a, b.astype(np.int32), k, l0
+
+
+def ellipse(npts: int, r1: float, r2: float, sigma: float, L: float = 0.0,
+            center=(0.5, 0.5)) -> Structure:
+    """Closed elliptical fiber X(s) = (c_x + r1 cos 2 pi s, c_y + r2 sin 2 pi s),
+    s_k = k/npts (thin-ellipse problem of the paper), spread with w = h_s."""
+    s = np.arange(npts) / npts
+    X = np.stack([center[0] + r1 * np.cos(2 * np.pi * s),
+                  center[1] + r2 * np.sin(2 * np.pi * s)])
+    w = np.full(npts, 1.0 / npts)
+    return Structure(X, closed_fiber_links(npts, sigma, L), w)
+
+
+def thick_ellipse(ns: int, nr: int, r1: float, r2: float, gamma: float,
+                  center=(0.5, 0.5)) -> Structure:
+    """Nested closed fibers r_l = (l + 1/2)/nr of the thick elliptical shell,
+    stiffness sigma(r) = 1 - cos(2 pi r), spread with w = h_s h_r."""
+    Xs, A, B, K, L0 = [], [], [], [], []
+    s = np.arange(ns) / ns
+    for l in range(nr):
+        r = (l + 0.5) / nr
+        Xs.append(np.stack([center[0] + (r1 + gamma * (r - 0.5)) * np.cos(2 * np.pi * s),
+                            center[1] + (r2 + gamma * (r - 0.5)) * np.sin(2 * np.pi * s)]))
+        a, b, k, l0 = closed_fiber_links(ns, 1.0 - math.cos(2 * math.pi * r),
+                                         0.0, offset=l * ns)
+        A.append(a); B.append(b); K.append(k); L0.append(l0)
+    X = np.concatenate(Xs, axis=1)
+    w = np.full(ns * nr, (1.0 / ns) * (1.0 / nr))
+    return Structure(X, (np.concatenate(A), np.concatenate(B),
+                         np.concatenate(K), np.concatenate(L0)), w)
+
+
+def fibonacci_sphere(npts: int) -> np.ndarray:
+    """Quasi-uniform unit-sphere points (golden-angle spiral), shape (3, np)."""
+    i = np.arange(npts) + 0.5
+    z = 1.0 - 2.0 * i / npts
+    r = np.sqrt(np.maximum(0.0, 1.0 - z * z))
+    th = np.pi * (3.0 - math.sqrt(5.0)) * np.arange(npts)
+    return np.stack([r * np.cos(th), r * np.sin(th), z])
+
+
+def ellipsoid_shell(npts: int, axes=(0.3, 0.25, 0.2), kappa: float = 1.0,
+                    center=(0.5, 0.5, 0.5)) -> Structure:
+    """Triangulated ellipsoidal shell: Fibonacci-sphere points, their convex
+    hull's edges as zero-rest-length links of stiffness kappa (a total-force
+    network, so w = 1), scaled to the semi-axes and centred."""
+    from scipy.spatial import ConvexHull
+
+    P = fibonacci_sphere(npts)
+    hull = ConvexHull(P.T)
+    e = set()
+    for t in hull.simplices:
+        for u, v in ((t[0], t[1]), (t[1], t[2]), (t[0], t[2])):
+            e.add((min(u, v), max(u, v)))
+    E = np.array(sorted(e), dtype=np.int32)
+    X = np.stack([center[a] + axes[a] * P[a] for a in range(3)])
+    links = (E[:, 0].copy(), E[:, 1].copy(), np.full(len(E), float(kappa)),
+             np.zeros(len(E)))
+    return Structure(X, links, np.ones(npts))
+
+
+def cylinder_shell(N: int, r1: float = 5 / 28, r2: float = 7 / 20,
+                   sigma_s: float = 1.0, sigma_r: float = 1.0, L: float = 1.0):
+    """3-D cylindrical shell of the paper's performance test: N_s = 19N/4
+    circumferential fibers around the x axis crossed by N_r = 3N axial fibers,
+    X(s, r) = (r, 1/2 + r1 cos 2 pi s, 1/2 + r2 sin 2 pi s); periodic in r.
+    Fiber sheet weights w = h_s h_r."""
+    ns, nr = 19 * N // 4, 3 * N
+    hs, hr = 1.0 / ns, 1.0 / nr
+    s = np.arange(ns) * hs
+    r = np.arange(nr) * hr
+    S, R = np.meshgrid(s, r)  # (nr, ns): point id = l*ns + k
+    X = np.stack([R.ravel(), 0.5 + r1 * np.cos(2 * np.pi * S.ravel()),
+                  0.5 + r2 * np.sin(2 * np.pi * S.ravel())])
+    ids = np.arange(nr * ns, dtype=np.int32).reshape(nr, ns)
+    a_s = ids.ravel()
+    b_s = np.roll(ids, -1, axis=1).ravel()
+    a_r = ids.ravel()
+    b_r = np.roll(ids, -1, axis=0).ravel()
+    A = np.concatenate([a_s, a_r]).astype(np.int32)
+    B = np.concatenate([b_s, b_r]).astype(np.int32)
+    K = np.concatenate([np.full(a_s.size, sigma_s / hs ** 2),
+                        np.full(a_r.size, sigma_r / hr ** 2)])
+    L0 = np.concatenate([np.zeros(a_s.size), np.full(a_r.size, L * hr)])
+    return Structure(X, (A, B, K, L0), np.full(nr * ns, hs * hr))
+
+
+# ----------------------------------------------------------- fluid fields --
+
+def zero_velocity(dim: int, n) -> list:
+    shp = (n[2] if dim == 3 else 1, n[1], n[0])
+    return [np.zeros(shp) for _ in range(dim)]
+
+
+def random_streamfunction_velocity_2d(n: int, kmax: int = 4, amp: float = 0.1,
+                                      seed: int = 2):
+    """Smooth, discretely divergence-free 2-D velocity: a streamfunction s at
+    the cell corners built from integer wave vectors 1 <= |k|_inf <= kmax with
+    N(0,1) cosine/sine coefficients, then u = (s[j+1] - s[j])/h on x-faces and
+    v = -(s[i+1] - s[i])/h on y-faces, scaled so max |u|, |v| = amp."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n
+    x = np.arange(n) * h
+    Xn, Yn = np.meshgrid(x, x)  # (j, i)
+    s = np.zeros((n, n))
+    for kx in range(-kmax, kmax + 1):
+        for ky in range(0, kmax + 1):
+            if max(abs(kx), abs(ky)) == 0 or (ky == 0 and kx < 0):
+                continue
+            a, b = rng.standard_normal(2)
+            ph = 2 * np.pi * (kx * Xn + ky * Yn)
+            s += a * np.cos(ph) + b * np.sin(ph)
+    u = (np.roll(s, -1, axis=0) - s) / h
+    v = -(np.roll(s, -1, axis=1) - s) / h
+    scale = amp / max(np.abs(u).max(), np.abs(v).max())
+    return [(u * scale)[None], (v * scale)[None]]
+
+
+def random_vector_potential_velocity_3d(n: int, kmax: int = 4, amp: float = 0.1,
+                                        seed: int = 5):
+    """3-D analogue: a vector potential A on the cell edges (A_c at integer
+    indices except along c), u = curl A with one-cell differences, which is
+    discretely divergence-free on the MAC grid; scaled to max |u| = amp."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n
+    g = np.arange(n) * h
+    Z, Y, Xg = np.meshgrid(g, g, g, indexing="ij")
+    A = []
+    for c in range(3):
+        off = [0.0, 0.0, 0.0]
+        off[c] = 0.5 * h
+        acc = np.zeros((n, n, n))
+        for _ in range(6):
+            k = rng.integers(-kmax, kmax + 1, size=3)
+            if not k.any():
+                continue
+            a, b = rng.standard_normal(2)
+            ph = 2 * np.pi * (k[0] * (Xg + off[0]) + k[1] * (Y + off[1]) + k[2] * (Z + off[2]))
+            acc += a * np.cos(ph) + b * np.sin(ph)
+        A.append(acc)
+    # axis numbering: array axes (2, 1, 0) = (z, y, x)
+    def d(q, ax):  # forward difference along grid axis ax (0 = x)
+        return (np.roll(q, -1, axis=2 - ax) - q) / h
+    u = d(A[2], 1) - d(A[1], 2)
+    v = d(A[0], 2) - d(A[2], 0)
+    w = d(A[1], 0) - d(A[0], 1)
+    scale = amp / max(np.abs(u).max(), np.abs(v).max(), np.abs(w).max())
+    return [u * scale, v * scale, w * scale]
+
+
+# ---------------------------------------------------------- named configs --
+
+@dataclass
+class Workload:
+    name: str
+    dim: int
+    n: tuple
+    rho: float
+    mu: float
+    dt: float
+    steps: int
+    structure: Structure
+    u0: list
+    chi: float = 0.6
+
+    @property
+    def h(self) -> float:
+        return 1.0 / self.n[0]
+
+
+def config_ellipse_64(steps: int = 100) -> Workload:
+    """2-D periodic unit square, 64^2, rho=1, mu=0.1, dt=1e-3; closed ellipse
+    (semi-axes 0.3/0.2, centred), 256 points, sigma=1, L=0, fluid at rest."""
+    n = 64
+    return Workload("ellipse2d_64", 2, (n, n, 1), 1.0, 0.1, 1e-3, steps,
+                    ellipse(256, 0.3, 0.2, 1.0), zero_velocity(2, (n, n, 1)))
+
+
+def config_ellipse_512(steps: int = 1000, seed: int = 2) -> Workload:
+    """2-D periodic, 512^2, mu=0.01, dt=1e-4; ellipse with 2048 points and
+    sigma=10, plus a seeded random smooth velocity (|k| <= 4, amplitude 0.1)."""
+    n = 512
+    return Workload("ellipse2d_512", 2, (n, n, 1), 1.0, 0.01, 1e-4, steps,
+                    ellipse(2048, 0.3, 0.2, 10.0),
+                    random_streamfunction_velocity_2d(n, 4, 0.1, seed))
+
+
+def config_shell_256(steps: int = 200, n: int = 256, npts: int = 65536) -> Workload:
+    """3-D periodic unit cube, 256^3, mu=0.01, dt=5e-4; ellipsoidal shell
+    (semi-axes 0.3/0.25/0.2) triangulated into 65,536 points, zero-rest-length
+    links of stiffness 1, fluid at rest."""
+    return Workload("shell3d_%d" % n, 3, (n, n, n), 1.0, 0.01, 5e-4, steps,
+                    ellipsoid_shell(npts), zero_velocity(3, (n, n, n)))

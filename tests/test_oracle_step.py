@@ -1,0 +1,164 @@
+"""Pins of the oracle's full IB-GM step (Sec. "IB-GM Algorithm", Steps 1a-3f)
+against what the mathematics fixes: invariants (rest stays at rest, uniform
+flow is preserved, the split order does not matter, the mean pressure stays
+zero), the closed-form amplification factor of a single Stokes mode, second
+order decay of Taylor-Green flow, the Laplace pressure jump of a circular
+membrane at rest and the relaxation of the ellipse to the equal-area circle."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1305_3976_amd import inputs
+
+NO_LINKS = (np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0), np.zeros(0))
+
+
+def make_sim(dim, N, u, structure=None, mu=0.05, dt=1e-3, rho=1.0, rotate=True,
+             no_advection=False, p=None):
+    n = (N, N, N if dim == 3 else 1)
+    P = oracle.make_params(dim, n, 1.0 / N, rho=rho, mu=mu, dt=dt,
+                           rotate=rotate, no_advection=no_advection)
+    if structure is None:
+        X = np.full((dim, 1), 0.5)
+        return oracle.Sim(P, u, X, NO_LINKS, np.ones(1), p=p)
+    return oracle.Sim(P, u, structure.X, structure.links, structure.w, p=p)
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_rest_stays_at_rest_and_uniform_flow_is_preserved(dim):
+    N = 8
+    shp = (N if dim == 3 else 1, N, N)
+    s = make_sim(dim, N, [np.zeros(shp)] * dim).advance(3)
+    assert max(np.abs(c).max() for c in s.u[:dim]) == 0.0
+    assert np.abs(s.p).max() == 0.0
+    vel = [0.3, -0.2, 0.1][:dim]
+    s = make_sim(dim, N, [np.full(shp, v) for v in vel]).advance(5)
+    for c in range(dim):
+        assert np.abs(s.u[c] - vel[c]).max() < 1e-14
+    assert np.abs(s.p).max() < 1e-12
+    # the single marker rides with the flow
+    assert np.abs(s.X[:, 0] - (0.5 + 5 * 1e-3 * np.array(vel))).max() < 1e-14
+
+
+@pytest.mark.parametrize("dim,k", [(2, (1, 2)), (3, (1, 2, 3))])
+def test_stokes_mode_amplification(dim, k):
+    """No advection, no structure, one discretely divergence-free Fourier
+    mode: every sub-step is diagonal, psi stays 0 and
+    u^{n+1} = (1 + 2 sum a_a / prod (1 - a_a)) u^n, a_a = -(4 nu/h^2) sin^2(pi k_a h)."""
+    N = 16
+    h = 1.0 / N
+    mu, dt = 0.07, 2e-3
+    x = np.arange(N) * h
+    if dim == 2:
+        Yn, Xn = np.meshgrid(x, x, indexing="ij")
+        sfun = np.sin(2 * np.pi * (k[0] * Xn + k[1] * Yn) + 0.3)
+        u = [((np.roll(sfun, -1, 0) - sfun) / h)[None], (-(np.roll(sfun, -1, 1) - sfun) / h)[None]]
+    else:
+        Z, Yn, Xn = np.meshgrid(x, x, x, indexing="ij")
+        A = np.sin(2 * np.pi * (k[0] * Xn + k[1] * Yn + k[2] * Z) + 0.3)
+        # u = curl (0, 0, A) + curl (A, 0, 0): two divergence-free parts
+        d = lambda q, ax: (np.roll(q, -1, axis=2 - ax) - q) / h
+        u = [d(A, 1), d(A, 2) - d(A, 0), -d(A, 1)]
+    nu = mu * dt / 2
+    a = [-(4 * nu / h ** 2) * math.sin(math.pi * kk * h) ** 2 for kk in k]
+    G = 1 + 2 * sum(a) / np.prod([1 - aa for aa in a])
+    s = make_sim(dim, N, u, mu=mu, dt=dt, no_advection=True)
+    nsteps = 4
+    s.advance(nsteps)
+    for c in range(dim):
+        ref = u[c] * G ** nsteps
+        assert np.abs(s.u[c] - ref).max() < 1e-13 * np.abs(ref).max() + 1e-15
+    assert np.abs(s.psi).max() < 1e-10
+    assert np.abs(s.p).max() < 1e-10
+
+
+def test_split_rotation_is_immaterial():
+    """The 1-D factors commute on a periodic uniform grid: rotating the split
+    order changes results only at rounding level."""
+    N = 32
+    u = inputs.random_streamfunction_velocity_2d(N, 3, 0.2, seed=1)
+    S = inputs.ellipse(96, 0.3, 0.2, 1.0)
+    a = make_sim(2, N, u, S, rotate=True).advance(20)
+    b = make_sim(2, N, u, S, rotate=False).advance(20)
+    for c in range(2):
+        assert rel(a.u[c], b.u[c]) < 1e-11
+    assert rel(a.p, b.p) < 1e-11
+    assert rel(a.X, b.X) < 1e-13
+
+
+def test_mean_pressure_stays_zero():
+    N = 32
+    u = inputs.random_streamfunction_velocity_2d(N, 3, 0.2, seed=4)
+    S = inputs.ellipse(128, 0.3, 0.2, 2.0)
+    s = make_sim(2, N, u, S).advance(15)
+    assert abs(s.p.mean()) < 1e-12 * np.abs(s.p).max()
+    assert abs(s.psi.mean()) < 1e-12 * np.abs(s.psi).max()
+
+
+def _taylor_green_error(N, T=0.25, mu=0.05):
+    """Decaying Taylor-Green vortex u = sin 2 pi x cos 2 pi y F(t),
+    v = -cos 2 pi x sin 2 pi y F(t), p = (rho/4)(cos 4 pi x + cos 4 pi y) F^2,
+    F = exp(-8 pi^2 mu t / rho); p^{-1/2} seeded with the exact pressure."""
+    h = 1.0 / N
+    dt = 0.25 * h
+    steps = int(round(T / dt))
+    i = np.arange(N)
+    Yc, Xf = np.meshgrid((i + 0.5) * h, i * h, indexing="ij")   # u faces
+    Yf, Xc = np.meshgrid(i * h, (i + 0.5) * h, indexing="ij")   # v faces
+    Ycc, Xcc = np.meshgrid((i + 0.5) * h, (i + 0.5) * h, indexing="ij")
+    F = lambda t: math.exp(-8 * math.pi ** 2 * mu * t)
+    u0 = [(np.sin(2 * np.pi * Xf) * np.cos(2 * np.pi * Yc))[None],
+          (-np.cos(2 * np.pi * Xc) * np.sin(2 * np.pi * Yf))[None]]
+    pex = lambda t: 0.25 * (np.cos(4 * np.pi * Xcc) + np.cos(4 * np.pi * Ycc)) * F(t) ** 2
+    s = make_sim(2, N, u0, mu=mu, dt=dt, p=pex(-0.5 * dt)[None])
+    s.advance(steps)
+    t = steps * dt
+    eu = np.sqrt(h * h * sum(((s.u[c] - u0[c] * F(t)) ** 2).sum() for c in range(2)))
+    ep = np.sqrt(h * h * ((s.p[0] - pex(t - 0.5 * dt)) ** 2).sum())
+    return eu, ep
+
+
+def test_taylor_green_second_order():
+    e = [_taylor_green_error(N) for N in (16, 32, 64)]
+    ru = [math.log2(e[i][0] / e[i + 1][0]) for i in range(2)]
+    rp = [math.log2(e[i][1] / e[i + 1][1]) for i in range(2)]
+    assert min(ru) > 1.7, (e, ru)
+    assert min(rp) > 1.5, (e, rp)
+
+
+def test_circle_at_rest_laplace_jump():
+    """A zero-rest-length circular fiber has tension sigma 2 pi R, so the
+    pressure jump at equilibrium is 2 pi sigma, independent of R."""
+    N, R, sigma = 32, 0.25, 1.0
+    S = inputs.ellipse(128, R, R, sigma)
+    s = make_sim(2, N, inputs.zero_velocity(2, (N, N, 1)), S, mu=0.5, dt=2e-3)
+    s.advance(300)
+    h = 1.0 / N
+    c = (np.arange(N) + 0.5) * h
+    Y, X = np.meshgrid(c, c, indexing="ij")
+    r = np.hypot(X - 0.5, Y - 0.5)
+    p = s.p[0]
+    jump = p[r < R - 3 * h].mean() - p[r > R + 3 * h].mean()
+    assert abs(jump - 2 * np.pi * sigma) < 0.05 * 2 * np.pi * sigma, jump
+    assert max(np.abs(q).max() for q in s.u[:2]) < 0.05
+
+
+def test_ellipse_relaxes_to_equal_area_circle():
+    """Thin-ellipse problem: the damped membrane tends to a circle of radius
+    sqrt(r1 r2) (area conserved up to the method's small leak)."""
+    N = 32
+    r1, r2 = 0.3, 0.2
+    S = inputs.ellipse(128, r1, r2, 1.0)
+    s = make_sim(2, N, inputs.zero_velocity(2, (N, N, 1)), S, mu=0.1, dt=2e-3)
+    s.advance(1000)
+    X = s.X
+    c = X.mean(axis=1, keepdims=True)
+    r = np.linalg.norm(X - c, axis=0)
+    assert (r.max() - r.min()) / r.mean() < 0.02
+    assert abs(r.mean() - math.sqrt(r1 * r2)) / math.sqrt(r1 * r2) < 0.03
