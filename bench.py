@@ -1,0 +1,229 @@
+#!/usr/bin/env python3
+"""Throughput of the IB-GM step on one MI355X.
+
+Workload: 3-D periodic unit cube, 256^3 MAC grid, rho = 1, mu = 0.01,
+dt = 5e-4; an ellipsoidal shell (semi-axes 0.3/0.25/0.2) triangulated into
+65,536 points joined by zero-rest-length links of stiffness 1; fluid at rest.
+One step = Steps 1a-3f of the method (interpolate, evolve, link force, spread,
+explicit momentum, three momentum sweeps, three pressure-increment sweeps and
+the pressure update), all in the library's HIP kernels, inputs resident in HBM.
+
+Prints ONE JSON line: IB steps/s under the mixed policy (FP32 grid, FP64
+positions and pressure) as `value`, the FP64 run beside it, per-kernel times
+from HIP events recorded on the library's stream over the timed region, the
+roofline of the dominant kernel, the error of each precision against the
+FP64 oracle after the oracle's sample steps, and the oracle's own rate on the
+host cores as `cpu_baseline`.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--points", type=int, default=65536)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="approximate CPU budget of the oracle sample")
+    return ap.parse_args()
+
+
+def kernel_bytes(name: str, b: int, ncell: int, dim: int) -> float:
+    """Algorithmic HBM bytes of one launch: every grid array the kernel must
+    read or write, once (b = bytes per grid value; p is always FP64)."""
+    per_cell = {
+        # u, nl, f, psi read; delta, nl written; f cleared; p read
+        "explicit": (5 * dim + 1) * b + 8,
+        # momentum sweeps carry all dim components
+        "mom_x_plain": 2 * b * dim, "mom_s_plain": 2 * b * dim,
+        "mom_x_final": 3 * b * dim, "mom_s_final": 3 * b * dim,
+        # psi: first sweep reads u and writes div, psi; last reads psi, div
+        # pair, p and writes psi, p, div
+        "psi_x_div": (dim + 2) * b, "psi_s_div": (dim + 2) * b,
+        "psi_x_plain": 2 * b, "psi_s_plain": 2 * b,
+        "psi_x_pfinal": 5 * b + 16, "psi_s_pfinal": 5 * b + 16,
+    }.get(name)
+    return None if per_cell is None else per_cell * ncell
+
+
+def step_bytes(b: int, ncell: int, dim: int) -> float:
+    mom = (dim - 1) * 2 * b * dim + 3 * b * dim
+    psi = (dim + 2) * b + (dim - 2) * 2 * b + 5 * b + 16
+    return ((5 * dim + 1) * b + 8 + mom + psi) * ncell
+
+
+def run_gpu(w, precision, steps, warmup):
+    import torch
+    from paper_1305_3976_amd import ibgm
+    cfg = ibgm.Config(w.dim, w.n, w.h, rho=w.rho, mu=w.mu, dt=w.dt, chi=w.chi,
+                      precision=precision)
+    sim = ibgm.Simulation(cfg, w.u0, w.structure)
+    stream = sim.stream
+    sim.step(warmup)
+    sim.sync()
+    # timed region: K steps with per-kernel HIP events on the library's stream
+    sim.profile(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    sim.step(steps)
+    e1.record(stream)
+    sim.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    kern = sim.profile_read()
+    sim.profile(False)
+    # same K steps with no per-kernel events (the library launches only)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    sim.step(steps)
+    e1.record(stream)
+    sim.sync()
+    ms_plain = e0.elapsed_time(e1)
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return ms, ms_plain, wall, kern
+
+
+def oracle_sample(w, budget_s):
+    import oracle
+    P = oracle.make_params(w.dim, w.n, w.h, rho=w.rho, mu=w.mu, dt=w.dt, chi=w.chi)
+    S = w.structure
+    sim = oracle.Sim(P, [np.asarray(c, dtype=np.float64) for c in w.u0], S.X, S.links, S.w)
+    t0 = time.perf_counter()
+    n = 0
+    while True:
+        sim.advance(1)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or n >= 5 or el / n * (n + 1) > 2.5 * budget_s:
+            break
+    return sim, n, el, oracle.num_threads()
+
+
+def gpu_errors(w, precision, nsteps, ref):
+    from paper_1305_3976_amd import ibgm
+    cfg = ibgm.Config(w.dim, w.n, w.h, rho=w.rho, mu=w.mu, dt=w.dt, chi=w.chi,
+                      precision=precision)
+    sim = ibgm.Simulation(cfg, w.u0, w.structure)
+    sim.step(nsteps)
+    sim.sync()
+    st = sim.state()
+    sim.close()
+    rel = lambda a, b: float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+    out = {"u%d" % c: rel(st["u"][c], ref.u[c]) for c in range(w.dim)}
+    out["p"] = rel(st["p"], ref.p)
+    out["X"] = rel(st["X"], ref.X)
+    return out
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(requested --gpus %d, WORLD_SIZE %d)" % (args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs an MI355X (no GPU visible)", file=sys.stderr)
+        sys.exit(2)
+    from paper_1305_3976_amd import inputs
+    w = inputs.config_shell_256(steps=args.steps, n=args.n, npts=args.points)
+    ncell = w.n[0] * w.n[1] * w.n[2]
+    print("# workload %s: %d cells, %d points, %d links" % (
+        w.name, ncell, w.structure.np, w.structure.nlinks), file=sys.stderr, flush=True)
+
+    res = {}
+    for prec, tag in ((1, "mixed"), (0, "fp64")):
+        if prec == 0 and args.no_fp64:
+            continue
+        ms, ms_plain, wall, kern = run_gpu(w, prec, args.steps, args.warmup)
+        res[tag] = (ms, ms_plain, wall, kern)
+        print("# %s: %.3f ms/step (profiled), %.3f ms/step (plain)" % (
+            tag, ms / args.steps, ms_plain / args.steps), file=sys.stderr, flush=True)
+
+    ms, ms_plain, wall, kern = res["mixed"]
+    b = 4
+    rows = {}
+    for name, (tot, cnt) in kern.items():
+        by = kernel_bytes(name, b, ncell, w.dim)
+        avg_ms = tot / cnt
+        rows[name] = {"avg_us": round(avg_ms * 1e3, 2), "launches": cnt,
+                      "share": round(tot / sum(t for t, _ in kern.values()), 4)}
+        if by is not None:
+            rows[name]["alg_GB_per_launch"] = round(by / 1e9, 4)
+            rows[name]["GB_s"] = round(by / (avg_ms * 1e-3) / 1e9, 1)
+    # dominant kernel = largest total time among the grid kernels with a byte model
+    dom = max((n for n in rows if "GB_s" in rows[n]), key=lambda n: kern[n][0])
+    ach = rows[dom]["GB_s"]
+    steps_s = args.steps / (ms_plain * 1e-3)
+    line = {
+        "metric": "IB steps/s and Gcell-updates/s at 256^3, FP32 vs FP64, % of HBM roofline",
+        "value": round(steps_s, 3),
+        "unit": "IB steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_plain / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 grid / f64 positions+pressure",
+        "data": "synthetic",
+        "config": {"workload": "shell3d_256: 256^3 periodic MAC grid, mu=0.01, dt=5e-4, "
+                               "ellipsoidal shell 0.3/0.25/0.2 with %d points, membrane modulus 1 (cotangent links)"
+                               % w.structure.np,
+                   "cells": ncell, "points": w.structure.np, "links": w.structure.nlinks},
+        "gcell_updates_per_s": round(ncell * steps_s / 1e9, 3),
+        "ms_per_step_profiled": round(ms / args.steps, 4),
+        "wall_s_timed_region": round(wall, 3),
+        "step_alg_bytes_GB": round(step_bytes(b, ncell, w.dim) / 1e9, 4),
+        "step_GB_s": round(step_bytes(b, ncell, w.dim) / (ms_plain / args.steps * 1e-3) / 1e9, 1),
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None},
+        "kernels": rows,
+    }
+    if "fp64" in res:
+        ms64, ms64_plain, _, kern64 = res["fp64"]
+        s64 = args.steps / (ms64_plain * 1e-3)
+        line["fp64"] = {"value": round(s64, 3), "unit": "IB steps/s",
+                        "ms_per_step": round(ms64_plain / args.steps, 4),
+                        "gcell_updates_per_s": round(ncell * s64 / 1e9, 3),
+                        "step_GB_s": round(step_bytes(8, ncell, w.dim) / (ms64_plain / args.steps * 1e-3) / 1e9, 1),
+                        "kernels_avg_us": {k: round(t / c * 1e3, 2) for k, (t, c) in kern64.items()}}
+        line["mixed_vs_fp64_speedup"] = round(steps_s / s64, 3)
+    if not args.no_cpu_baseline:
+        ref, n, el, thr = oracle_sample(w, args.cpu_seconds)
+        line["cpu_baseline"] = {"value": round(n / el, 5), "unit": "IB steps/s", "cores": thr,
+                                "kind": "oracle",
+                                "sample": "%d step(s) of the same 256^3 workload from rest, FP64 "
+                                          "oracle, OpenMP over independent lines/cells" % n}
+        errs = {"mixed": gpu_errors(w, 1, n, ref)}
+        if not args.no_fp64:
+            errs["fp64"] = gpu_errors(w, 0, n, ref)
+        line["error_vs_fp64_oracle"] = {"steps": n, "rel_l2": errs}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

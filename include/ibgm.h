@@ -1,0 +1,178 @@
+/*
+ * ibgm.h -- C ABI of libibgm.so, the MI355X (gfx950) IB-GM time-step library.
+ *
+ * The method is the immersed-boundary algorithm built on the Guermond-Minev
+ * direction-split, pseudo-compressible Navier-Stokes solver of Wiens &
+ * Stockie ("An efficient parallel immersed boundary algorithm using a
+ * pseudo-compressible fluid solver"): a periodic box of side n[a]*h, constant
+ * density rho and viscosity mu, a MAC (staggered) grid, Lagrangian points
+ * joined by elastic links, a fixed time step dt (Sec. "Immersed Boundary
+ * Equations", Sec. "Discretization of Fluid and IB Domains").
+ *
+ * Conventions shared by every entry point
+ *   Pointers.   Every array argument is a DEVICE pointer (hipMalloc / torch
+ *               CUDA tensor) unless the comment says "host".  The caller
+ *               owns every buffer; the library never frees caller memory.
+ *   Layout.     Grid arrays are dense [n2][n1][n0] (x fastest, n2 = 1 in 2D).
+ *               Velocity component c lives on the faces normal to axis c:
+ *               integer index along c, half-integer along the others; cell
+ *               centred arrays (p, psi, div) sit at half-integers.  Lagrangian
+ *               arrays are structure-of-arrays [dim][n_points] FP64, with
+ *               positions unwrapped (grid indices are taken mod n).
+ *   Precision.  IB_PREC_FP64: every grid array is FP64.  IB_PREC_MIXED: the
+ *               velocity-like grid arrays (u, nl_prev, psi, div_prev, the
+ *               workspace and spread forces) are FP32, while p, X, U stay
+ *               FP64; line-solve recurrences always run in FP64 registers.
+ *   Streams.    Work is enqueued on the hipStream_t given to ib_init (or to
+ *               ib_line_solve) and returns before it completes.  Device faults
+ *               surface at the next call that synchronises (ib_sync).
+ *   Errors.     Every call returns an ib_status.  IB_E_INVALID means nothing
+ *               was enqueued and no state changed; ib_last_error() holds a
+ *               message for the calling thread.  No C++ exception crosses
+ *               this boundary.  One ib_ctx is used by one host thread at a
+ *               time.
+ */
+#ifndef IBGM_H
+#define IBGM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ib_ctx ib_ctx;
+
+typedef enum {
+  IB_OK = 0,
+  IB_E_INVALID = 1,     /* bad argument; nothing enqueued */
+  IB_E_UNSUPPORTED = 2, /* valid but not built (e.g. a line longer than 1024) */
+  IB_E_DEVICE = 3,      /* a HIP runtime call failed */
+  IB_E_NONFINITE = 4,   /* a Lagrangian position became NaN/Inf (ib_sync) */
+  IB_E_STATE = 5        /* call out of order (e.g. null context) */
+} ib_status;
+
+typedef enum { IB_F64 = 0, IB_F32 = 1 } ib_dtype;
+typedef enum { IB_PREC_FP64 = 0, IB_PREC_MIXED = 1 } ib_precision;
+
+/* flags */
+#define IB_FLAG_NO_ADVECTION 1 /* drop the advection term (Stokes flow) */
+
+typedef struct {
+  int32_t dim;          /* 2 or 3 */
+  int32_t n[3];         /* cells per axis, each >= 4 and <= 1024; n[2] = 1 in 2D */
+  double h;             /* mesh width > 0 (the paper's h = H/N) */
+  double rho;           /* density > 0 */
+  double mu;            /* dynamic viscosity >= 0 */
+  double dt;            /* time step > 0; the pseudo-compressibility eps = dt */
+  double chi;           /* pressure-correction weight chi in (0, 1]; 0.6 in the paper */
+  int32_t precision;    /* ib_precision */
+  int32_t rotate_split; /* 1: rotate the split order every step (Sec.
+                           "Partitioning of the Eulerian and Lagrangian Grids",
+                           GM modifications); step n uses the n-th cyclic shift
+                           of (x, y[, z]) for momentum and psi sweeps alike */
+  int32_t flags;        /* IB_FLAG_* */
+  int64_t step0;        /* index n of the state handed in; 0 = fresh start, which
+                           applies the paper's n = 0 rules (forward Euler for X,
+                           N^{1/2} = N(u^0)) and computes div_prev = D.u^0 */
+} ib_grid_params;
+
+/* Device state, caller-owned, borrowed by the context until ib_destroy.
+ * "grid dtype" = FP64 (IB_PREC_FP64) or FP32 (IB_PREC_MIXED). */
+typedef struct {
+  void *u[3];       /* u^n per component, grid dtype, [n2][n1][n0]; updated in place */
+  void *nl_prev[3]; /* N(u^{n-1}) (skew advection), grid dtype; overwritten each step */
+  void *psi;        /* psi^{n-1/2}, grid dtype, cell centred */
+  void *div_prev;   /* D.u^n, grid dtype, cell centred (written by ib_init if step0 == 0) */
+  double *p;        /* p^{n-1/2}, FP64, cell centred */
+  double *X;        /* X^n, FP64 [dim][n_points] */
+  double *U_prev;   /* U^{n-1}, FP64 [dim][n_points] */
+  int64_t n_points;
+  void *workspace;  /* device scratch of ib_workspace_size() bytes, 256-B aligned */
+  size_t workspace_bytes;
+} ib_buffers;
+
+/* Elastic structure: HOST arrays, copied at ib_init (force-connection form of
+ * Step 2a: link e pulls a[e], b[e] together with
+ * kappa[e] (X_b - X_a)(1 - l0[e]/|X_b - X_a|); a fiber of the paper with
+ * stiffness sigma, rest strain L and spacing h_s has kappa = sigma/h_s^2,
+ * l0 = L h_s and spreading weight w = h_s). */
+typedef struct {
+  int64_t n_links;
+  const int32_t *a, *b;      /* host, point indices in [0, n_points) */
+  const double *kappa, *l0;  /* host, kappa finite, l0 >= 0 */
+  const double *w;           /* host [n_points], spreading weight (Step 2b) */
+} ib_structure;
+
+/* Bytes of device workspace a context with these parameters needs. */
+ib_status ib_workspace_size(const ib_grid_params *prm, int64_t n_points,
+                            size_t *bytes);
+
+/* Validate, upload the structure (the library allocates only its link table),
+ * precompute the line-solve factors in FP64 on the host and, for step0 == 0,
+ * compute div_prev = D.u^0 and clear the workspace (on `hip_stream`, a
+ * hipStream_t; NULL = default stream). */
+ib_status ib_init(ib_ctx **out, const ib_grid_params *prm,
+                  const ib_buffers *buf, const ib_structure *st,
+                  void *hip_stream);
+
+/* Advance `nsteps` IB-GM steps (Steps 1a-3f of Sec. "IB-GM Algorithm"):
+ * interpolate u to the points, evolve X (AB2; forward Euler at n = 0),
+ * link force at X^{n+1/2}, spread, explicit momentum with AB2 skew advection
+ * (eq:nonlinear), one implicit sweep per axis (eq:umacstep1/2), the psi
+ * sweeps (eq:PenaltyStepPart1/2) and the pressure update.  Asynchronous. */
+ib_status ib_step(ib_ctx *ctx, int32_t nsteps);
+
+/* Wait for the stream; report the step index and IB_E_NONFINITE if any
+ * position became non-finite since init. */
+ib_status ib_sync(ib_ctx *ctx, int64_t *step_index);
+
+/* Step 2b on given buffers: f_out[c] (+)= sum_k F[c][k] w[k] delta_h(x - X_k)
+ * for the context's grid.  X, F, w: FP64 device [dim][npts], [npts];
+ * f_out[c]: grid dtype.  accumulate = 0 clears f_out first.  Grid cells are
+ * summed with device atomics, so the order of additions varies run to run. */
+ib_status ib_spread(ib_ctx *ctx, const double *X, const double *F,
+                    const double *w, int64_t npts, void *const f_out[3],
+                    int32_t accumulate);
+
+/* Step 1a on given buffers: U[c][k] = sum_ij u_in[c]_ij delta_h(x - X_k) h^d.
+ * X, U: FP64 device [dim][npts]; u_in[c]: grid dtype. */
+ib_status ib_interp(ib_ctx *ctx, const double *X, int64_t npts,
+                    void *const u_in[3], double *U);
+
+/* Step 2a on given buffers: F = link force of the context's structure at
+ * positions X (FP64 device [dim][n_points] -> [dim][n_points]). */
+ib_status ib_force(ib_ctx *ctx, const double *X, double *F);
+
+/* eq:TriDiagX, batched and in place: every line along `axis` (0 = x) of the
+ * `nfields` arrays data + f*field_stride (elements) of shape [n2][n1][n0] is
+ * replaced by the solution of the periodic system
+ *     off x[i-1] + diag x[i] + off x[i+1] = rhs[i]     (indices mod n[axis]).
+ * Requires |diag| > 2|off| (strict diagonal dominance, true of every matrix of
+ * the method), 3 <= n[axis] <= 1024.  dtype: ib_dtype of the data; the
+ * recurrence runs in FP64.  Enqueued on hip_stream. */
+ib_status ib_line_solve(void *data, int32_t dtype, const int32_t n[3],
+                        int32_t axis, int32_t nfields, int64_t field_stride,
+                        double diag, double off, void *hip_stream);
+
+/* Release the context's own allocations (not the caller's buffers). */
+ib_status ib_destroy(ib_ctx *ctx);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *ib_last_error(void);
+
+/* Per-kernel timing with HIP events recorded on the context's stream around
+ * every launch while enabled.  ib_profile_read returns the summed duration
+ * in milliseconds and the number of launches of kernel `id` (0 <=
+ * id < ib_profile_count()) since the last reset, after synchronising. */
+ib_status ib_profile_enable(ib_ctx *ctx, int32_t enable);
+int32_t ib_profile_count(void);
+const char *ib_profile_name(int32_t id);
+ib_status ib_profile_read(ib_ctx *ctx, int32_t id, double *total_ms,
+                          int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

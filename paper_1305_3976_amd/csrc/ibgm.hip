@@ -1,0 +1,711 @@
+// ibgm.hip -- host side of libibgm.so: the C ABI declared in include/ibgm.h.
+//
+// One translation unit: the device code lives in kernels.h.  The host only
+// validates, precomputes the factored line-solve coefficients in extended
+// precision, carves the caller's workspace and enqueues kernels on the
+// caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ibgm.h"
+#include "kernels.h"
+
+using namespace ibgm;
+
+// ------------------------------------------------------------- errors --
+
+static thread_local std::string g_err;
+
+static ib_status fail(ib_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                     \
+  do {                                                                    \
+    hipError_t e_ = (expr);                                               \
+    if (e_ != hipSuccess)                                                 \
+      return fail(IB_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+extern "C" const char *ib_last_error(void) { return g_err.c_str(); }
+
+// --------------------------------------------------------- profiling --
+
+enum KernelId {
+  KP_INTERP_EVOLVE = 0, KP_FORCE, KP_SPREAD, KP_EXPLICIT, KP_DIVERGENCE,
+  KP_MOM_X_PLAIN, KP_MOM_S_PLAIN, KP_MOM_X_FINAL, KP_MOM_S_FINAL,
+  KP_PSI_X_DIV, KP_PSI_S_DIV, KP_PSI_X_PLAIN, KP_PSI_S_PLAIN,
+  KP_PSI_X_PFINAL, KP_PSI_S_PFINAL, KP_LINE_X, KP_LINE_S, KP_INTERP, KP_COUNT
+};
+static const char *kKernelNames[KP_COUNT] = {
+    "interp_evolve", "force", "spread", "explicit", "divergence",
+    "mom_x_plain", "mom_s_plain", "mom_x_final", "mom_s_final",
+    "psi_x_div", "psi_s_div", "psi_x_plain", "psi_s_plain",
+    "psi_x_pfinal", "psi_s_pfinal", "line_x", "line_s", "interp"};
+
+struct PendingEvent {
+  int id;
+  hipEvent_t a, b;
+};
+
+// ------------------------------------------------------------ context --
+
+struct ib_ctx {
+  ib_grid_params prm;
+  ib_buffers buf;
+  hipStream_t stream;
+  int64_t step;
+  int dim;
+  Grid g;
+  int64_t np;
+  bool f32;
+  size_t tsz;  // bytes per grid value
+  // workspace
+  void *delta[3], *f[3], *divn;
+  double *Xn1, *Xh, *F;
+  int *flag;
+  // structure (library allocation)
+  int32_t *ptr, *nbr;
+  double *kap, *l0, *w;
+  int64_t nlinks;
+  // factored coefficients
+  double mom_alpha, mom_invc, psi_alpha, psi_invc;
+  // profiling
+  bool prof;
+  std::vector<PendingEvent> pending;
+  std::vector<hipEvent_t> pool;
+  double prof_ms[KP_COUNT];
+  int64_t prof_n[KP_COUNT];
+};
+
+static hipEvent_t take_event(ib_ctx *c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Enqueue one kernel launch, bracketed by events while profiling.
+template <class Fn>
+static void launch(ib_ctx *c, int id, Fn &&fn) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (c && c->prof) {
+    a = take_event(c);
+    b = take_event(c);
+    if (a) hipEventRecord(a, c->stream);
+  }
+  fn();
+  if (c && c->prof && a && b) {
+    hipEventRecord(b, c->stream);
+    c->pending.push_back({id, a, b});
+  }
+}
+
+static void drain_events(ib_ctx *c) {
+  for (auto &p : c->pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(p.b) == hipSuccess &&
+        hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      c->prof_ms[p.id] += ms;
+      c->prof_n[p.id] += 1;
+    }
+    c->pool.push_back(p.a);
+    c->pool.push_back(p.b);
+  }
+  c->pending.clear();
+}
+
+// ------------------------------------------------- factored coefficients --
+
+// A = d I + e (L + U) = c (I - alpha L)(I - alpha U) with |alpha| < 1:
+// alpha + 1/alpha = -d/e.  With g = |d/e| - 2 > 0 (strict dominance), the
+// smaller root is |alpha| = 2 / (2 + g + sqrt(g (g + 4))) (no cancellation
+// for small or large g), sign(alpha) = sign(-d/e), c = -e/alpha.  Computed in
+// long double from the given (d, e).
+static ib_status factor(double d, double e, double *alpha, double *inv_c) {
+  if (!std::isfinite(d) || !std::isfinite(e))
+    return fail(IB_E_INVALID, "non-finite line-solve coefficients (%g, %g)", d, e);
+  if (e == 0.0) {
+    if (d == 0.0) return fail(IB_E_INVALID, "singular line-solve matrix (diag 0)");
+    *alpha = 0.0;
+    *inv_c = 1.0 / d;
+    return IB_OK;
+  }
+  if (!(std::fabs(d) > 2.0 * std::fabs(e)))
+    return fail(IB_E_INVALID,
+                "line solve needs |diag| > 2|off| (got diag %g, off %g)", d, e);
+  long double D = d, E = e;
+  long double g = (fabsl(D) - 2.0L * fabsl(E)) / fabsl(E);
+  long double aa = 2.0L / (2.0L + g + sqrtl(g * (g + 4.0L)));
+  long double al = (-D / E) > 0 ? aa : -aa;
+  long double c = -E / al;
+  *alpha = (double)al;
+  *inv_c = (double)(1.0L / c);
+  return IB_OK;
+}
+
+// ----------------------------------------------------------- sweeps --
+
+static int x_chunk(int64_t N) {
+  if (N <= 64) return 1;
+  if (N <= 128) return 2;
+  if (N <= 192) return 3;
+  if (N <= 256) return 4;
+  if (N <= 384) return 6;
+  if (N <= 512) return 8;
+  return 16;
+}
+static int next_pow2(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+template <typename T, int M, int MODE>
+static void go_x(SweepArgs<T> a, int nf, hipStream_t st) {
+  int64_t nlines = (int64_t)a.g.n1 * a.g.n2;
+  int lpb = 256 / a.G;
+  dim3 grid((unsigned)((nlines + lpb - 1) / lpb), nf);
+  hipLaunchKernelGGL((k_sweep_x<T, M, MODE>), grid, dim3(256), 0, st, a);
+}
+
+template <typename T, int MODE>
+static void dispatch_x(SweepArgs<T> a, int nf, hipStream_t st) {
+  const int64_t N = a.g.n0;
+  const int M = x_chunk(N);
+  a.G = next_pow2((int)((N + M - 1) / M));
+  switch (M) {
+    case 1: go_x<T, 1, MODE>(a, nf, st); break;
+    case 2: go_x<T, 2, MODE>(a, nf, st); break;
+    case 3: go_x<T, 3, MODE>(a, nf, st); break;
+    case 4: go_x<T, 4, MODE>(a, nf, st); break;
+    case 6: go_x<T, 6, MODE>(a, nf, st); break;
+    case 8: go_x<T, 8, MODE>(a, nf, st); break;
+    default: go_x<T, 16, MODE>(a, nf, st); break;
+  }
+}
+
+// Strided lines: chunks of 32 elements (8 for lines of at most 64), TX
+// consecutive x per block row, ceil(N/M) rows; launch bound by block size.
+template <typename T, int M, int MODE, int LB>
+static void go_s(SweepArgs<T> a, int axis, int nf, int TX, hipStream_t st) {
+  const int64_t N = axis == 1 ? a.g.n1 : a.g.n2;
+  const int G = (int)((N + M - 1) / M);
+  const int64_t other = axis == 1 ? a.g.n2 : a.g.n1;
+  dim3 grid((unsigned)((a.g.n0 + TX - 1) / TX), (unsigned)other, nf);
+  hipLaunchKernelGGL((k_sweep_s<T, M, MODE, LB>), grid, dim3(TX, G), 0, st, a, axis);
+}
+
+template <typename T, int MODE>
+static void dispatch_s(SweepArgs<T> a, int axis, int nf, hipStream_t st) {
+  const int64_t N = axis == 1 ? a.g.n1 : a.g.n2;
+  const int TX = a.g.n0 >= 32 ? 32 : (a.g.n0 >= 16 ? 16 : 8);
+  if (N <= 64) {
+    const int G = (int)((N + 7) / 8);
+    if (TX * G <= 256) go_s<T, 8, MODE, 256>(a, axis, nf, TX, st);
+    else go_s<T, 8, MODE, 512>(a, axis, nf, TX, st);
+    return;
+  }
+  const int threads = TX * (int)((N + 31) / 32);
+  if (threads <= 256) go_s<T, 32, MODE, 256>(a, axis, nf, TX, st);
+  else if (threads <= 512) go_s<T, 32, MODE, 512>(a, axis, nf, TX, st);
+  else go_s<T, 32, MODE, 1024>(a, axis, nf, TX, st);
+}
+
+// Launch one sweep along `axis`; `id_x` / `id_s` name it for profiling (the
+// strided id is id_x + 1).
+template <typename T, int MODE>
+static void sweep(ib_ctx *c, int id_x, SweepArgs<T> a, int axis, int nf, hipStream_t st) {
+  if (axis == 0)
+    launch(c, id_x, [&] { dispatch_x<T, MODE>(a, nf, st); });
+  else
+    launch(c, id_x + 1, [&] { dispatch_s<T, MODE>(a, axis, nf, st); });
+}
+
+// ------------------------------------------------------------ validation --
+
+static bool finite_pos(double v) { return std::isfinite(v) && v > 0; }
+
+static ib_status check_params(const ib_grid_params *p) {
+  if (!p) return fail(IB_E_INVALID, "null parameters");
+  if (p->dim != 2 && p->dim != 3) return fail(IB_E_INVALID, "dim must be 2 or 3 (got %d)", p->dim);
+  for (int a = 0; a < p->dim; a++)
+    if (p->n[a] < 4 || p->n[a] > 1024)
+      return fail(IB_E_INVALID, "n[%d] = %d outside [4, 1024]", a, p->n[a]);
+  if (p->dim == 2 && p->n[2] != 1) return fail(IB_E_INVALID, "2-D grids need n[2] == 1");
+  if (!finite_pos(p->h)) return fail(IB_E_INVALID, "h must be finite and > 0");
+  if (!finite_pos(p->rho)) return fail(IB_E_INVALID, "rho must be finite and > 0");
+  if (!finite_pos(p->dt)) return fail(IB_E_INVALID, "dt must be finite and > 0");
+  if (!(std::isfinite(p->mu) && p->mu >= 0)) return fail(IB_E_INVALID, "mu must be finite and >= 0");
+  if (!(std::isfinite(p->chi) && p->chi >= 0 && p->chi <= 1))
+    return fail(IB_E_INVALID, "chi must lie in [0, 1]");
+  if (p->precision != IB_PREC_FP64 && p->precision != IB_PREC_MIXED)
+    return fail(IB_E_INVALID, "unknown precision %d", p->precision);
+  if (p->step0 < 0) return fail(IB_E_INVALID, "step0 must be >= 0");
+  if (p->flags & ~IB_FLAG_NO_ADVECTION) return fail(IB_E_INVALID, "unknown flags 0x%x", p->flags);
+  return IB_OK;
+}
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+static size_t workspace_bytes(const ib_grid_params *p, int64_t np) {
+  const size_t nc = (size_t)p->n[0] * p->n[1] * p->n[2];
+  const size_t t = p->precision == IB_PREC_MIXED ? 4 : 8;
+  const size_t lag = sizeof(double) * (size_t)p->dim * (size_t)(np > 0 ? np : 1);
+  return 7 * align256(nc * t) + 3 * align256(lag) + 256;
+}
+
+extern "C" ib_status ib_workspace_size(const ib_grid_params *prm, int64_t n_points,
+                                       size_t *bytes) {
+  ib_status st = check_params(prm);
+  if (st != IB_OK) return st;
+  if (n_points < 0) return fail(IB_E_INVALID, "n_points < 0");
+  if (!bytes) return fail(IB_E_INVALID, "null output");
+  *bytes = workspace_bytes(prm, n_points);
+  return IB_OK;
+}
+
+// ---------------------------------------------------------- launches --
+
+template <typename T, int DIM>
+static void launch_interp(ib_ctx *c, int id, const double *X, int64_t np,
+                          void *const u[3], double *U, bool evolve, bool first) {
+  InterpArgs<T, DIM> a{};
+  for (int i = 0; i < 3; i++) a.u[i] = (const T *)(i < DIM ? u[i] : nullptr);
+  a.X = X;
+  a.U = U;
+  a.Xn1 = c->Xn1;
+  a.Xh = c->Xh;
+  a.flag = c->flag;
+  a.np = np;
+  a.g = c->g;
+  a.inv_h = 1.0 / c->prm.h;
+  a.dt = c->prm.dt;
+  a.evolve = evolve;
+  a.first = first;
+  dim3 grid((unsigned)((np + 255) / 256), DIM);
+  launch(c, id, [&] { hipLaunchKernelGGL((k_interp<T, DIM>), grid, dim3(256), 0, c->stream, a); });
+}
+
+template <int DIM>
+static void launch_force(ib_ctx *c, const double *Xh, double *F, bool commit) {
+  ForceArgs<DIM> a{};
+  a.ptr = c->ptr;
+  a.nbr = c->nbr;
+  a.kap = c->kap;
+  a.l0 = c->l0;
+  a.Xh = Xh;
+  a.F = F;
+  a.Xn1 = commit ? c->Xn1 : nullptr;
+  a.X = c->buf.X;
+  a.np = c->np;
+  launch(c, KP_FORCE, [&] {
+    hipLaunchKernelGGL((k_force<DIM>), dim3((unsigned)((c->np + 255) / 256)), dim3(256), 0,
+                       c->stream, a);
+  });
+}
+
+template <typename T, int DIM>
+static void launch_spread(ib_ctx *c, const double *X, const double *F, const double *w,
+                          int64_t np, void *const f[3]) {
+  SpreadArgs<T, DIM> a{};
+  a.X = X;
+  a.F = F;
+  a.w = w;
+  for (int i = 0; i < 3; i++) a.f[i] = (T *)(i < DIM ? f[i] : nullptr);
+  a.np = np;
+  a.g = c->g;
+  a.inv_h = 1.0 / c->prm.h;
+  a.inv_hd = 1.0 / std::pow(c->prm.h, DIM);
+  const int64_t nthreads = np * (DIM == 3 ? 16 : 4);
+  launch(c, KP_SPREAD, [&] {
+    hipLaunchKernelGGL((k_spread<T, DIM>), dim3((unsigned)((nthreads + 255) / 256)), dim3(256),
+                       0, c->stream, a);
+  });
+}
+
+template <typename T, int DIM>
+static void launch_explicit(ib_ctx *c, bool first) {
+  ExplicitArgs<T, DIM> a{};
+  for (int i = 0; i < 3; i++) {
+    a.u[i] = (const T *)(i < DIM ? c->buf.u[i] : nullptr);
+    a.nl[i] = (T *)(i < DIM ? c->buf.nl_prev[i] : nullptr);
+    a.f[i] = (T *)(i < DIM ? c->f[i] : nullptr);
+    a.delta[i] = (T *)(i < DIM ? c->delta[i] : nullptr);
+  }
+  a.p = c->buf.p;
+  a.psi = (const T *)c->buf.psi;
+  a.g = c->g;
+  a.inv_h = 1.0 / c->prm.h;
+  a.inv_h2 = 1.0 / (c->prm.h * c->prm.h);
+  a.dt = c->prm.dt;
+  a.mu = c->prm.mu;
+  a.inv_rho = 1.0 / c->prm.rho;
+  a.first = first;
+  a.advect = !(c->prm.flags & IB_FLAG_NO_ADVECTION);
+  launch(c, KP_EXPLICIT, [&] {
+    hipLaunchKernelGGL((k_explicit<T, DIM>), dim3((unsigned)((c->g.ncell + 255) / 256)),
+                       dim3(256), 0, c->stream, a);
+  });
+}
+
+template <typename T, int DIM>
+static void launch_divergence(ib_ctx *c, void *out) {
+  launch(c, KP_DIVERGENCE, [&] {
+    hipLaunchKernelGGL((k_divergence<T, DIM>), dim3((unsigned)((c->g.ncell + 255) / 256)),
+                       dim3(256), 0, c->stream, (const T *)c->buf.u[0],
+                       (const T *)c->buf.u[1], (const T *)(DIM == 3 ? c->buf.u[2] : nullptr),
+                       (T *)out, c->g, 1.0 / c->prm.h);
+  });
+}
+
+// One full IB-GM step (Steps 1a-3f) at step index n.
+template <typename T, int DIM>
+static void enqueue_step(ib_ctx *c) {
+  const int64_t n = c->step;
+  const bool first = n == 0;
+  // Steps 1a-1c
+  launch_interp<T, DIM>(c, KP_INTERP_EVOLVE, c->buf.X, c->np, c->buf.u, c->buf.U_prev,
+                        true, first);
+  // Step 2a (+ commit X^{n+1}) and Step 2b
+  launch_force<DIM>(c, c->Xh, c->F, true);
+  launch_spread<T, DIM>(c, c->Xh, c->F, c->w, c->np, c->f);
+  // Steps 3a-3b
+  launch_explicit<T, DIM>(c, first);
+  // split order of this step
+  int order[3];
+  const int shift = c->prm.rotate_split ? (int)(n % DIM) : 0;
+  for (int s = 0; s < DIM; s++) order[s] = (s + shift) % DIM;
+  // Steps 3c-3d (+z): delta form (1 - nu D_aa) d_a = d_{a-1}, u += d_last
+  SweepArgs<T> m{};
+  m.g = c->g;
+  m.dim = DIM;
+  m.alpha = c->mom_alpha;
+  m.inv_c = c->mom_invc;
+  for (int i = 0; i < 3; i++) {
+    m.f[i] = (T *)(i < DIM ? c->delta[i] : nullptr);
+    m.u[i] = (T *)(i < DIM ? c->buf.u[i] : nullptr);
+  }
+  for (int s = 0; s < DIM; s++) {
+    if (s < DIM - 1) sweep<T, SW_PLAIN>(c, KP_MOM_X_PLAIN, m, order[s], DIM, c->stream);
+    else sweep<T, SW_FINAL>(c, KP_MOM_X_FINAL, m, order[s], DIM, c->stream);
+  }
+  // Step 3e-3f: psi sweeps, the first forming -(rho/dt) D.u^{n+1}, the last
+  // updating p
+  SweepArgs<T> q{};
+  q.g = c->g;
+  q.dim = DIM;
+  q.alpha = c->psi_alpha;
+  q.inv_c = c->psi_invc;
+  q.f[0] = (T *)c->buf.psi;
+  for (int i = 0; i < 3; i++) q.u[i] = (T *)(i < DIM ? c->buf.u[i] : nullptr);
+  q.divn = (T *)c->divn;
+  q.divp = (T *)c->buf.div_prev;
+  q.p = c->buf.p;
+  q.inv_h = 1.0 / c->prm.h;
+  q.div_scale = -(c->prm.rho / c->prm.dt) / c->prm.h;
+  q.half_chi_mu = 0.5 * c->prm.chi * c->prm.mu;
+  sweep<T, SW_DIV>(c, KP_PSI_X_DIV, q, order[0], 1, c->stream);
+  for (int s = 1; s < DIM - 1; s++) sweep<T, SW_PLAIN>(c, KP_PSI_X_PLAIN, q, order[s], 1, c->stream);
+  sweep<T, SW_PFINAL>(c, KP_PSI_X_PFINAL, q, order[DIM - 1], 1, c->stream);
+  c->step = n + 1;
+}
+
+// ---------------------------------------------------------------- API --
+
+extern "C" ib_status ib_init(ib_ctx **out, const ib_grid_params *prm, const ib_buffers *buf,
+                             const ib_structure *st, void *hip_stream) {
+  if (!out) return fail(IB_E_INVALID, "null context output");
+  *out = nullptr;
+  ib_status s = check_params(prm);
+  if (s != IB_OK) return s;
+  if (!buf || !st) return fail(IB_E_INVALID, "null buffers / structure");
+  const int d = prm->dim;
+  for (int c = 0; c < d; c++)
+    if (!buf->u[c] || !buf->nl_prev[c]) return fail(IB_E_INVALID, "null velocity buffer %d", c);
+  if (!buf->psi || !buf->div_prev || !buf->p) return fail(IB_E_INVALID, "null p / psi / div_prev");
+  const int64_t np = buf->n_points;
+  if (np < 1) return fail(IB_E_INVALID, "n_points must be >= 1");
+  if (!buf->X || !buf->U_prev) return fail(IB_E_INVALID, "null X / U_prev");
+  if (!buf->workspace || ((uintptr_t)buf->workspace & 255))
+    return fail(IB_E_INVALID, "workspace must be non-null and 256-byte aligned");
+  const size_t need = workspace_bytes(prm, np);
+  if (buf->workspace_bytes < need)
+    return fail(IB_E_INVALID, "workspace too small (%zu < %zu bytes)", buf->workspace_bytes, need);
+  if (st->n_links < 0 || (st->n_links > 0 && (!st->a || !st->b || !st->kappa || !st->l0)))
+    return fail(IB_E_INVALID, "bad link arrays");
+  if (!st->w) return fail(IB_E_INVALID, "null spreading weights");
+  for (int64_t i = 0; i < np; i++)
+    if (!std::isfinite(st->w[i])) return fail(IB_E_INVALID, "non-finite weight at point %lld", (long long)i);
+  // CSR by point, both directions of every link
+  std::vector<int32_t> deg(np + 1, 0);
+  for (int64_t e = 0; e < st->n_links; e++) {
+    const int64_t a = st->a[e], b = st->b[e];
+    if (a < 0 || a >= np || b < 0 || b >= np || a == b)
+      return fail(IB_E_INVALID, "link %lld has bad endpoints (%lld, %lld)", (long long)e,
+                  (long long)a, (long long)b);
+    if (!std::isfinite(st->kappa[e]) || !std::isfinite(st->l0[e]) || st->l0[e] < 0)
+      return fail(IB_E_INVALID, "link %lld has bad kappa / l0", (long long)e);
+    deg[a + 1]++;
+    deg[b + 1]++;
+  }
+  if (2 * st->n_links > INT32_MAX) return fail(IB_E_UNSUPPORTED, "too many links");
+  for (int64_t i = 0; i < np; i++) deg[i + 1] += deg[i];
+  std::vector<int32_t> nbr(std::max<int64_t>(1, 2 * st->n_links));
+  std::vector<double> kap(nbr.size()), l0(nbr.size());
+  {
+    std::vector<int32_t> fill(deg.begin(), deg.end() - 1);
+    for (int64_t e = 0; e < st->n_links; e++) {
+      const int32_t a = st->a[e], b = st->b[e];
+      int32_t ia = fill[a]++, ib = fill[b]++;
+      nbr[ia] = b; kap[ia] = st->kappa[e]; l0[ia] = st->l0[e];
+      nbr[ib] = a; kap[ib] = st->kappa[e]; l0[ib] = st->l0[e];
+    }
+  }
+  double ma, mi, pa, pi;
+  const double h2 = prm->h * prm->h;
+  const double nu = prm->mu * prm->dt / (2.0 * prm->rho);
+  if ((s = factor(1.0 + 2.0 * nu / h2, -nu / h2, &ma, &mi)) != IB_OK) return s;
+  if ((s = factor(1.0 + 2.0 / h2, -1.0 / h2, &pa, &pi)) != IB_OK) return s;
+
+  ib_ctx *c = new ib_ctx();
+  c->prm = *prm;
+  c->buf = *buf;
+  c->stream = (hipStream_t)hip_stream;
+  c->step = prm->step0;
+  c->dim = d;
+  c->g.n0 = prm->n[0];
+  c->g.n1 = prm->n[1];
+  c->g.n2 = d == 3 ? prm->n[2] : 1;
+  c->g.ncell = (int64_t)c->g.n0 * c->g.n1 * c->g.n2;
+  c->np = np;
+  c->f32 = prm->precision == IB_PREC_MIXED;
+  c->tsz = c->f32 ? 4 : 8;
+  c->mom_alpha = ma; c->mom_invc = mi; c->psi_alpha = pa; c->psi_invc = pi;
+  c->nlinks = st->n_links;
+  // carve the workspace
+  char *w = (char *)buf->workspace;
+  const size_t fb = align256((size_t)c->g.ncell * c->tsz);
+  const size_t lb = align256(sizeof(double) * d * np);
+  for (int i = 0; i < 3; i++) { c->delta[i] = i < d ? (void *)w : nullptr; if (i < d) w += fb; }
+  for (int i = 0; i < 3; i++) { c->f[i] = i < d ? (void *)w : nullptr; if (i < d) w += fb; }
+  c->divn = w; w += fb;
+  c->Xn1 = (double *)w; w += lb;
+  c->Xh = (double *)w; w += lb;
+  c->F = (double *)w; w += lb;
+  c->flag = (int *)w;
+  // upload the structure
+  auto bail = [&](ib_status e) { ib_destroy(c); return e; };
+  if (hipMalloc(&c->ptr, sizeof(int32_t) * (np + 1)) != hipSuccess ||
+      hipMalloc(&c->nbr, sizeof(int32_t) * nbr.size()) != hipSuccess ||
+      hipMalloc(&c->kap, sizeof(double) * kap.size()) != hipSuccess ||
+      hipMalloc(&c->l0, sizeof(double) * l0.size()) != hipSuccess ||
+      hipMalloc(&c->w, sizeof(double) * np) != hipSuccess)
+    return bail(fail(IB_E_DEVICE, "hipMalloc of the link table failed"));
+  if (hipMemcpyAsync(c->ptr, deg.data(), sizeof(int32_t) * (np + 1), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+      hipMemcpyAsync(c->nbr, nbr.data(), sizeof(int32_t) * nbr.size(), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+      hipMemcpyAsync(c->kap, kap.data(), sizeof(double) * kap.size(), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+      hipMemcpyAsync(c->l0, l0.data(), sizeof(double) * l0.size(), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+      hipMemcpyAsync(c->w, st->w, sizeof(double) * np, hipMemcpyHostToDevice, c->stream) != hipSuccess)
+    return bail(fail(IB_E_DEVICE, "upload of the link table failed"));
+  // clear spread targets and the flag; seed div_prev at a fresh start
+  for (int i = 0; i < d; i++)
+    if (hipMemsetAsync(c->f[i], 0, fb, c->stream) != hipSuccess)
+      return bail(fail(IB_E_DEVICE, "clearing the workspace failed"));
+  if (hipMemsetAsync(c->flag, 0, 256, c->stream) != hipSuccess)
+    return bail(fail(IB_E_DEVICE, "clearing the workspace failed"));
+  if (prm->step0 == 0) {
+    if (c->f32) {
+      if (d == 2) launch_divergence<float, 2>(c, buf->div_prev);
+      else launch_divergence<float, 3>(c, buf->div_prev);
+    } else {
+      if (d == 2) launch_divergence<double, 2>(c, buf->div_prev);
+      else launch_divergence<double, 3>(c, buf->div_prev);
+    }
+  }
+  // the host arrays above go out of scope: wait for the uploads
+  if (hipStreamSynchronize(c->stream) != hipSuccess)
+    return bail(fail(IB_E_DEVICE, "initialisation on the stream failed"));
+  if (hipGetLastError() != hipSuccess) return bail(fail(IB_E_DEVICE, "kernel launch failed"));
+  *out = c;
+  return IB_OK;
+}
+
+extern "C" ib_status ib_step(ib_ctx *c, int32_t nsteps) {
+  if (!c) return fail(IB_E_STATE, "null context");
+  if (nsteps < 0) return fail(IB_E_INVALID, "nsteps < 0");
+  for (int32_t i = 0; i < nsteps; i++) {
+    if (c->f32) {
+      if (c->dim == 2) enqueue_step<float, 2>(c);
+      else enqueue_step<float, 3>(c);
+    } else {
+      if (c->dim == 2) enqueue_step<double, 2>(c);
+      else enqueue_step<double, 3>(c);
+    }
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(IB_E_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+  return IB_OK;
+}
+
+extern "C" ib_status ib_sync(ib_ctx *c, int64_t *step_index) {
+  if (!c) return fail(IB_E_STATE, "null context");
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  if (step_index) *step_index = c->step;
+  int flag = 0;
+  HIP_TRY(hipMemcpy(&flag, c->flag, sizeof(int), hipMemcpyDeviceToHost));
+  if (flag) return fail(IB_E_NONFINITE, "a Lagrangian position became non-finite (step <= %lld)",
+                        (long long)c->step);
+  return IB_OK;
+}
+
+extern "C" ib_status ib_spread(ib_ctx *c, const double *X, const double *F, const double *w,
+                               int64_t npts, void *const f_out[3], int32_t accumulate) {
+  if (!c) return fail(IB_E_STATE, "null context");
+  if (npts < 0 || (npts > 0 && (!X || !F || !w)) || !f_out)
+    return fail(IB_E_INVALID, "bad spread arguments");
+  for (int i = 0; i < c->dim; i++)
+    if (!f_out[i]) return fail(IB_E_INVALID, "null output component %d", i);
+  if (!accumulate)
+    for (int i = 0; i < c->dim; i++)
+      HIP_TRY(hipMemsetAsync(f_out[i], 0, (size_t)c->g.ncell * c->tsz, c->stream));
+  if (npts == 0) return IB_OK;
+  if (c->f32) {
+    if (c->dim == 2) launch_spread<float, 2>(c, X, F, w, npts, f_out);
+    else launch_spread<float, 3>(c, X, F, w, npts, f_out);
+  } else {
+    if (c->dim == 2) launch_spread<double, 2>(c, X, F, w, npts, f_out);
+    else launch_spread<double, 3>(c, X, F, w, npts, f_out);
+  }
+  HIP_TRY(hipGetLastError());
+  return IB_OK;
+}
+
+extern "C" ib_status ib_interp(ib_ctx *c, const double *X, int64_t npts, void *const u_in[3],
+                               double *U) {
+  if (!c) return fail(IB_E_STATE, "null context");
+  if (npts < 0 || (npts > 0 && (!X || !U)) || !u_in)
+    return fail(IB_E_INVALID, "bad interp arguments");
+  for (int i = 0; i < c->dim; i++)
+    if (!u_in[i]) return fail(IB_E_INVALID, "null input component %d", i);
+  if (npts == 0) return IB_OK;
+  if (c->f32) {
+    if (c->dim == 2) launch_interp<float, 2>(c, KP_INTERP, X, npts, u_in, U, false, false);
+    else launch_interp<float, 3>(c, KP_INTERP, X, npts, u_in, U, false, false);
+  } else {
+    if (c->dim == 2) launch_interp<double, 2>(c, KP_INTERP, X, npts, u_in, U, false, false);
+    else launch_interp<double, 3>(c, KP_INTERP, X, npts, u_in, U, false, false);
+  }
+  HIP_TRY(hipGetLastError());
+  return IB_OK;
+}
+
+extern "C" ib_status ib_force(ib_ctx *c, const double *X, double *F) {
+  if (!c) return fail(IB_E_STATE, "null context");
+  if (!X || !F) return fail(IB_E_INVALID, "bad force arguments");
+  if (c->dim == 2) launch_force<2>(c, X, F, false);
+  else launch_force<3>(c, X, F, false);
+  HIP_TRY(hipGetLastError());
+  return IB_OK;
+}
+
+extern "C" ib_status ib_line_solve(void *data, int32_t dtype, const int32_t n[3], int32_t axis,
+                                   int32_t nfields, int64_t field_stride, double diag,
+                                   double off, void *hip_stream) {
+  if (!data || !n) return fail(IB_E_INVALID, "null data / shape");
+  if (dtype != IB_F64 && dtype != IB_F32) return fail(IB_E_INVALID, "unknown dtype %d", dtype);
+  if (axis < 0 || axis > 2) return fail(IB_E_INVALID, "axis must be 0, 1 or 2");
+  for (int a = 0; a < 3; a++)
+    if (n[a] < 1) return fail(IB_E_INVALID, "n[%d] < 1", a);
+  if (n[axis] < 3) return fail(IB_E_INVALID, "lines must have >= 3 points");
+  if (n[axis] > 1024) return fail(IB_E_UNSUPPORTED, "lines longer than 1024 are not built");
+  if (n[0] > 65535 * 64LL || (int64_t)n[1] * n[2] > ((int64_t)1 << 40))
+    return fail(IB_E_UNSUPPORTED, "array too large");
+  if (nfields < 1) return fail(IB_E_INVALID, "nfields < 1");
+  const int64_t ncell = (int64_t)n[0] * n[1] * n[2];
+  if (nfields > 1 && field_stride < ncell)
+    return fail(IB_E_INVALID, "field_stride < n0 n1 n2 would overlap fields");
+  double al, ic;
+  ib_status s = factor(diag, off, &al, &ic);
+  if (s != IB_OK) return s;
+  hipStream_t st = (hipStream_t)hip_stream;
+  Grid g{n[0], n[1], n[2], ncell};
+  for (int f0 = 0; f0 < nfields; f0 += 3) {
+    const int nf = std::min(3, nfields - f0);
+    if (dtype == IB_F64) {
+      SweepArgs<double> a{};
+      a.g = g; a.alpha = al; a.inv_c = ic;
+      for (int i = 0; i < nf; i++) a.f[i] = (double *)data + (f0 + i) * field_stride;
+      sweep<double, SW_PLAIN>(nullptr, KP_LINE_X, a, axis, nf, st);
+    } else {
+      SweepArgs<float> a{};
+      a.g = g; a.alpha = al; a.inv_c = ic;
+      for (int i = 0; i < nf; i++) a.f[i] = (float *)data + (f0 + i) * field_stride;
+      sweep<float, SW_PLAIN>(nullptr, KP_LINE_X, a, axis, nf, st);
+    }
+  }
+  HIP_TRY(hipGetLastError());
+  return IB_OK;
+}
+
+extern "C" ib_status ib_destroy(ib_ctx *c) {
+  if (!c) return IB_OK;
+  hipStreamSynchronize(c->stream);
+  for (auto &p : c->pending) {
+    hipEventDestroy(p.a);
+    hipEventDestroy(p.b);
+  }
+  for (auto e : c->pool) hipEventDestroy(e);
+  if (c->ptr) hipFree(c->ptr);
+  if (c->nbr) hipFree(c->nbr);
+  if (c->kap) hipFree(c->kap);
+  if (c->l0) hipFree(c->l0);
+  if (c->w) hipFree(c->w);
+  delete c;
+  return IB_OK;
+}
+
+extern "C" ib_status ib_profile_enable(ib_ctx *c, int32_t enable) {
+  if (!c) return fail(IB_E_STATE, "null context");
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  drain_events(c);
+  for (int i = 0; i < KP_COUNT; i++) {
+    c->prof_ms[i] = 0;
+    c->prof_n[i] = 0;
+  }
+  c->prof = enable != 0;
+  return IB_OK;
+}
+
+extern "C" int32_t ib_profile_count(void) { return KP_COUNT; }
+
+extern "C" const char *ib_profile_name(int32_t id) {
+  return (id >= 0 && id < KP_COUNT) ? kKernelNames[id] : "";
+}
+
+extern "C" ib_status ib_profile_read(ib_ctx *c, int32_t id, double *total_ms,
+                                     int64_t *launches) {
+  if (!c) return fail(IB_E_STATE, "null context");
+  if (id < 0 || id >= KP_COUNT) return fail(IB_E_INVALID, "kernel id out of range");
+  drain_events(c);
+  if (total_ms) *total_ms = c->prof_ms[id];
+  if (launches) *launches = c->prof_n[id];
+  return IB_OK;
+}

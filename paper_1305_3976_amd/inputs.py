@@ -92,11 +92,44 @@ def fibonacci_sphere(npts: int) -> np.ndarray:
     return np.stack([r * np.cos(th), r * np.sin(th), z])
 
 
+def _cotan_weights(P: np.ndarray, tris: np.ndarray, E: np.ndarray) -> np.ndarray:
+    """Cotangent weights (cot a + cot b)/2 of each edge of a triangulated unit
+    sphere, a and b being the angles opposite the edge in its two triangles
+    (measured on the flat triangles of the parameter mesh)."""
+    pts = P.T
+    tris = np.asarray(tris)
+    n = pts.shape[0]
+    keys, vals = [], []
+    for k in range(3):
+        i, j, o = tris[:, k], tris[:, (k + 1) % 3], tris[:, (k + 2) % 3]
+        a, b = pts[i] - pts[o], pts[j] - pts[o]
+        cot = np.einsum("ij,ij->i", a, b) / np.linalg.norm(np.cross(a, b), axis=1)
+        keys.append(np.minimum(i, j).astype(np.int64) * n + np.maximum(i, j))
+        vals.append(0.5 * cot)
+    keys = np.concatenate(keys)
+    vals = np.concatenate(vals)
+    ekeys = E[:, 0].astype(np.int64) * n + E[:, 1]
+    order = np.argsort(keys)
+    sk, sv = keys[order], vals[order]
+    uk, start = np.unique(sk, return_index=True)
+    sums = np.add.reduceat(sv, start)
+    pos = np.searchsorted(uk, ekeys)
+    assert np.array_equal(uk[pos], ekeys)
+    return sums[pos]
+
+
 def ellipsoid_shell(npts: int, axes=(0.3, 0.25, 0.2), kappa: float = 1.0,
-                    center=(0.5, 0.5, 0.5)) -> Structure:
-    """Triangulated ellipsoidal shell: Fibonacci-sphere points, their convex
-    hull's edges as zero-rest-length links of stiffness kappa (a total-force
-    network, so w = 1), scaled to the semi-axes and centred."""
+                    center=(0.5, 0.5, 0.5), weights: str = "uniform") -> Structure:
+    """Triangulated ellipsoidal shell: Fibonacci-sphere points and the edges
+    of their convex hull as zero-rest-length links, scaled to the semi-axes
+    and centred; the links carry a total nodal force (w = 1).
+
+    weights = "uniform": every link has stiffness kappa.
+    weights = "cotan":   kappa is the modulus sigma of the membrane energy
+        (sigma/2) int |grad X|^2 over the unit-sphere parameterisation -- the
+        triangulated analogue of the fiber-sheet energy behind the paper's
+        force density sigma (X_ss + X_rr) -- discretised with cotangent
+        weights, so link ij has stiffness sigma (cot a_ij + cot b_ij)/2."""
     from scipy.spatial import ConvexHull
 
     P = fibonacci_sphere(npts)
@@ -107,8 +140,11 @@ def ellipsoid_shell(npts: int, axes=(0.3, 0.25, 0.2), kappa: float = 1.0,
             e.add((min(u, v), max(u, v)))
     E = np.array(sorted(e), dtype=np.int32)
     X = np.stack([center[a] + axes[a] * P[a] for a in range(3)])
-    links = (E[:, 0].copy(), E[:, 1].copy(), np.full(len(E), float(kappa)),
-             np.zeros(len(E)))
+    if weights == "cotan":
+        k = kappa * _cotan_weights(P, hull.simplices, E)
+    else:
+        k = np.full(len(E), float(kappa))
+    links = (E[:, 0].copy(), E[:, 1].copy(), k, np.zeros(len(E)))
     return Structure(X, links, np.ones(npts))
 
 
@@ -241,6 +277,7 @@ def config_ellipse_512(steps: int = 1000, seed: int = 2) -> Workload:
 def config_shell_256(steps: int = 200, n: int = 256, npts: int = 65536) -> Workload:
     """3-D periodic unit cube, 256^3, mu=0.01, dt=5e-4; ellipsoidal shell
     (semi-axes 0.3/0.25/0.2) triangulated into 65,536 points, zero-rest-length
-    links of stiffness 1, fluid at rest."""
+    links whose stiffness 1 is the modulus of the membrane energy (cotangent
+    link weights, see ellipsoid_shell), fluid at rest."""
     return Workload("shell3d_%d" % n, 3, (n, n, n), 1.0, 0.01, 5e-4, steps,
-                    ellipsoid_shell(npts), zero_velocity(3, (n, n, n)))
+                    ellipsoid_shell(npts, weights="cotan"), zero_velocity(3, (n, n, n)))

@@ -1,0 +1,35 @@
+"""Shared test helpers: build oracle and GPU simulations from one seeded
+workload and compare fields with the paper's discrete l2 norms."""
+import numpy as np
+
+import oracle
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def oracle_sim(w, rotate=True, no_advection=False):
+    P = oracle.make_params(w.dim, w.n, w.h, rho=w.rho, mu=w.mu, dt=w.dt, chi=w.chi,
+                           rotate=rotate, no_advection=no_advection)
+    S = w.structure
+    return oracle.Sim(P, [np.asarray(c, dtype=np.float64) for c in w.u0], S.X, S.links, S.w)
+
+
+def gpu_sim(w, precision, rotate=True, no_advection=False):
+    from paper_1305_3976_amd import ibgm
+    cfg = ibgm.Config(w.dim, w.n, w.h, rho=w.rho, mu=w.mu, dt=w.dt, chi=w.chi,
+                      precision=precision, rotate_split=rotate, no_advection=no_advection)
+    return ibgm.Simulation(cfg, w.u0, w.structure)
+
+
+def field_errors(gpu_state, orc, dim):
+    errs = {}
+    for c in range(dim):
+        errs["u%d" % c] = rel_l2(gpu_state["u"][c], orc.u[c])
+    errs["p"] = rel_l2(gpu_state["p"], orc.p)
+    errs["psi"] = rel_l2(gpu_state["psi"], orc.psi)
+    errs["X"] = rel_l2(gpu_state["X"], orc.X)
+    return errs

@@ -1,0 +1,73 @@
+"""The C-ABI library loads, exports every entry point include/ibgm.h
+declares, and rejects bad arguments on the host before touching a device
+(no compute call is made here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "ibgm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ib_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def ib():
+    from paper_1305_3976_amd import build, ibgm
+    if not os.path.exists(ibgm.LIB_PATH):
+        build.build()
+    return ibgm
+
+
+def test_every_declared_symbol_is_exported(ib):
+    names = declared_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(ib.lib, n), n
+    assert set(ib.EXPORTED) == set(names)
+
+
+def test_workspace_size_and_validation(ib):
+    P = ib.Config(3, (256, 256, 256), 1 / 256, mu=0.01, dt=5e-4, precision=ib.IB_PREC_MIXED).params()
+    n = ctypes.c_size_t()
+    assert ib.lib.ib_workspace_size(ctypes.byref(P), 65536, ctypes.byref(n)) == ib.IB_OK
+    assert n.value >= 7 * 256 ** 3 * 4 + 3 * 3 * 65536 * 8
+    bad = [("dim", 1), ("h", 0.0), ("rho", -1.0), ("dt", float("nan")), ("mu", -0.1),
+           ("chi", 1.5), ("precision", 7), ("flags", 0x100), ("step0", -1)]
+    for field, val in bad:
+        Q = ib.Config(2, (64, 64), 1 / 64).params()
+        setattr(Q, field, val)
+        assert ib.lib.ib_workspace_size(ctypes.byref(Q), 10, ctypes.byref(n)) == ib.IB_E_INVALID
+        assert ib.lib.ib_last_error()
+    Q = ib.Config(2, (64, 3), 1 / 64).params()
+    assert ib.lib.ib_workspace_size(ctypes.byref(Q), 10, ctypes.byref(n)) == ib.IB_E_INVALID
+    assert b"n[1]" in ib.lib.ib_last_error()
+
+
+def test_line_solve_argument_errors(ib):
+    n = (ctypes.c_int32 * 3)(8, 8, 1)
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    assert ib.lib.ib_line_solve(fake, 0, n, 0, 1, 64, 1.0, -0.6, None) == ib.IB_E_INVALID
+    assert b"|diag| > 2|off|" in ib.lib.ib_last_error()
+    assert ib.lib.ib_line_solve(fake, 5, n, 0, 1, 64, 3.0, -1.0, None) == ib.IB_E_INVALID
+    assert ib.lib.ib_line_solve(fake, 0, n, 3, 1, 64, 3.0, -1.0, None) == ib.IB_E_INVALID
+    assert ib.lib.ib_line_solve(fake, 0, n, 2, 1, 64, 3.0, -1.0, None) == ib.IB_E_INVALID
+    assert ib.lib.ib_line_solve(fake, 0, n, 0, 2, 10, 3.0, -1.0, None) == ib.IB_E_INVALID
+    assert ib.lib.ib_line_solve(None, 0, n, 0, 1, 64, 3.0, -1.0, None) == ib.IB_E_INVALID
+
+
+def test_init_argument_errors(ib):
+    P = ib.Config(2, (16, 16), 1 / 16).params()
+    B = ib.Buffers()
+    S = ib.Structure()
+    ctx = ctypes.c_void_p()
+    assert ib.lib.ib_init(ctypes.byref(ctx), ctypes.byref(P), ctypes.byref(B), ctypes.byref(S),
+                          None) == ib.IB_E_INVALID
+    assert not ctx.value
+    assert ib.lib.ib_step(None, 1) == ib.IB_E_STATE
+    assert ib.lib.ib_sync(None, None) == ib.IB_E_STATE
