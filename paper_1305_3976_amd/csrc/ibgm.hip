@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -48,13 +49,13 @@ enum KernelId {
   KP_INTERP_EVOLVE = 0, KP_FORCE, KP_SPREAD, KP_EXPLICIT, KP_DIVERGENCE,
   KP_MOM_X_PLAIN, KP_MOM_S_PLAIN, KP_MOM_X_FINAL, KP_MOM_S_FINAL,
   KP_PSI_X_DIV, KP_PSI_S_DIV, KP_PSI_X_PLAIN, KP_PSI_S_PLAIN,
-  KP_PSI_X_PFINAL, KP_PSI_S_PFINAL, KP_LINE_X, KP_LINE_S, KP_INTERP, KP_COUNT
+  KP_PSI_X_PFINAL, KP_PSI_S_PFINAL, KP_LINE_X, KP_LINE_S, KP_INTERP, KP_SORT, KP_COUNT
 };
 static const char *kKernelNames[KP_COUNT] = {
     "interp_evolve", "force", "spread", "explicit", "divergence",
     "mom_x_plain", "mom_s_plain", "mom_x_final", "mom_s_final",
     "psi_x_div", "psi_s_div", "psi_x_plain", "psi_s_plain",
-    "psi_x_pfinal", "psi_s_pfinal", "line_x", "line_s", "interp"};
+    "psi_x_pfinal", "psi_s_pfinal", "line_x", "line_s", "interp", "spread_sort"};
 
 struct PendingEvent {
   int id;
@@ -77,6 +78,10 @@ struct ib_ctx {
   void *delta[3], *f[3], *divn;
   double *Xn1, *Xh, *F;
   int *flag;
+  // spreading tiles
+  TileGrid tg;
+  int *t_count, *t_start, *t_flag, *t_bsum, *t_list, *t_nlist, *tile_of, *rank_of;
+  double *Xs, *Fs, *ws;
   // structure (library allocation)
   int32_t *ptr, *nbr;
   double *kap, *l0, *w;
@@ -109,11 +114,11 @@ static void launch(ib_ctx *c, int id, Fn &&fn) {
   if (c && c->prof) {
     a = take_event(c);
     b = take_event(c);
-    if (a) hipEventRecord(a, c->stream);
+    if (a) (void)hipEventRecord(a, c->stream);
   }
   fn();
   if (c && c->prof && a && b) {
-    hipEventRecord(b, c->stream);
+    (void)hipEventRecord(b, c->stream);
     c->pending.push_back({id, a, b});
   }
 }
@@ -178,12 +183,39 @@ static int next_pow2(int v) {
   return p;
 }
 
-template <typename T, int M, int MODE>
+template <typename T, int M, int MODE, bool VEC>
 static void go_x(SweepArgs<T> a, int nf, hipStream_t st) {
   int64_t nlines = (int64_t)a.g.n1 * a.g.n2;
   int lpb = 256 / a.G;
   dim3 grid((unsigned)((nlines + lpb - 1) / lpb), nf);
-  hipLaunchKernelGGL((k_sweep_x<T, M, MODE>), grid, dim3(256), 0, st, a);
+  hipLaunchKernelGGL((k_sweep_x<T, M, MODE, VEC>), grid, dim3(256), 0, st, a);
+}
+
+static bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
+
+// Full, aligned chunks move as 16-byte vectors.
+template <typename T, int MODE>
+static bool x_vectorizable(const SweepArgs<T> &a, int nf, int M) {
+  if ((int64_t)a.G * M != a.g.n0 || (M * (int)sizeof(T)) % 16 != 0 || (M * 8) % 16 != 0)
+    return false;
+  for (int i = 0; i < nf; i++) {
+    if (!aligned16(a.f[i])) return false;
+    if (MODE == SW_FINAL && !aligned16(a.u[i])) return false;
+  }
+  if (MODE == SW_PFINAL && !(aligned16(a.divn) && aligned16(a.divp) && aligned16(a.p)))
+    return false;
+  return true;
+}
+
+template <typename T, int M, int MODE>
+static void go_x_any(SweepArgs<T> a, int nf, hipStream_t st) {
+  if constexpr ((M * sizeof(T)) % 16 == 0 && (M * 8) % 16 == 0) {
+    if (x_vectorizable<T, MODE>(a, nf, M)) {
+      go_x<T, M, MODE, true>(a, nf, st);
+      return;
+    }
+  }
+  go_x<T, M, MODE, false>(a, nf, st);
 }
 
 template <typename T, int MODE>
@@ -192,13 +224,13 @@ static void dispatch_x(SweepArgs<T> a, int nf, hipStream_t st) {
   const int M = x_chunk(N);
   a.G = next_pow2((int)((N + M - 1) / M));
   switch (M) {
-    case 1: go_x<T, 1, MODE>(a, nf, st); break;
-    case 2: go_x<T, 2, MODE>(a, nf, st); break;
-    case 3: go_x<T, 3, MODE>(a, nf, st); break;
-    case 4: go_x<T, 4, MODE>(a, nf, st); break;
-    case 6: go_x<T, 6, MODE>(a, nf, st); break;
-    case 8: go_x<T, 8, MODE>(a, nf, st); break;
-    default: go_x<T, 16, MODE>(a, nf, st); break;
+    case 1: go_x_any<T, 1, MODE>(a, nf, st); break;
+    case 2: go_x_any<T, 2, MODE>(a, nf, st); break;
+    case 3: go_x_any<T, 3, MODE>(a, nf, st); break;
+    case 4: go_x_any<T, 4, MODE>(a, nf, st); break;
+    case 6: go_x_any<T, 6, MODE>(a, nf, st); break;
+    case 8: go_x_any<T, 8, MODE>(a, nf, st); break;
+    default: go_x_any<T, 16, MODE>(a, nf, st); break;
   }
 }
 
@@ -213,9 +245,49 @@ static void go_s(SweepArgs<T> a, int axis, int nf, int TX, hipStream_t st) {
   hipLaunchKernelGGL((k_sweep_s<T, M, MODE, LB>), grid, dim3(TX, G), 0, st, a, axis);
 }
 
+// Chunk length of the buffer-addressed strided sweep (16 or 32 line elements
+// per thread); IBGM_S_CHUNK overrides the default for tuning runs.
+static int s_chunk_choice() {
+  static int v = -1;
+  if (v < 0) {
+    const char *e = getenv("IBGM_S_CHUNK");
+    v = (e && atoi(e) == 32) ? 32 : 16;
+  }
+  return v;
+}
+
+template <typename T, int M, int MODE, int LB>
+static void go_sb(SweepArgs<T> a, int axis, int nf, hipStream_t st) {
+  const int64_t N = axis == 1 ? a.g.n1 : a.g.n2;
+  const int G = (int)((N + M - 1) / M);
+  const int64_t other = axis == 1 ? a.g.n2 : a.g.n1;
+  dim3 grid((unsigned)((a.g.n0 + 63) / 64), (unsigned)other, nf);
+  hipLaunchKernelGGL((k_sweep_sb<T, M, MODE, LB>), grid, dim3(64, G), 0, st, a, axis);
+}
+
 template <typename T, int MODE>
 static void dispatch_s(SweepArgs<T> a, int axis, int nf, hipStream_t st) {
   const int64_t N = axis == 1 ? a.g.n1 : a.g.n2;
+  const int64_t stride = axis == 1 ? a.g.n0 : a.g.n0 * a.g.n1;
+  const bool buf_ok = MODE != SW_DIV && N >= 64 && N <= 512 && a.g.n0 >= 64 &&
+                      ((N - 1) * stride + 64) * (int64_t)sizeof(double) < 0x7fffffff;
+  if (buf_ok) {
+    const int M = s_chunk_choice();
+    const int threads = 64 * (int)((N + M - 1) / M);
+    if constexpr (MODE != SW_DIV) {
+      if (M == 16) {
+        if (threads <= 512) go_sb<T, 16, MODE, 512>(a, axis, nf, st);
+        else if (threads <= 1024) go_sb<T, 16, MODE, 1024>(a, axis, nf, st);
+        else go_sb<T, 32, MODE, 1024>(a, axis, nf, st);
+        return;
+      }
+    }
+    {
+      if (threads <= 512) go_sb<T, 32, MODE, 512>(a, axis, nf, st);
+      else go_sb<T, 32, MODE, 1024>(a, axis, nf, st);
+    }
+    return;
+  }
   const int TX = a.g.n0 >= 32 ? 32 : (a.g.n0 >= 16 ? 16 : 8);
   if (N <= 64) {
     const int G = (int)((N + 7) / 8);
@@ -265,11 +337,27 @@ static ib_status check_params(const ib_grid_params *p) {
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+static TileGrid tile_grid(const ib_grid_params *p) {
+  TileGrid tg{};
+  for (int a = 0; a < 3; a++) tg.nt[a] = a < p->dim ? (p->n[a] + TS - 1) / TS : 1;
+  tg.ntiles = (int64_t)tg.nt[0] * tg.nt[1] * tg.nt[2];
+  return tg;
+}
+
+// Workspace: delta[3], f[3], div_new (grid dtype); X^{n+1}, X^{n+1/2}, F and
+// the sorted copies of X^{n+1/2}, F (FP64 [dim][np]) and w (FP64 [np]); the
+// spreading tile tables (counts, starts, flags, touched list, block sums),
+// the point sort (tile, rank); the touched-list length; one status word.
 static size_t workspace_bytes(const ib_grid_params *p, int64_t np) {
   const size_t nc = (size_t)p->n[0] * p->n[1] * p->n[2];
   const size_t t = p->precision == IB_PREC_MIXED ? 4 : 8;
-  const size_t lag = sizeof(double) * (size_t)p->dim * (size_t)(np > 0 ? np : 1);
-  return 7 * align256(nc * t) + 3 * align256(lag) + 256;
+  const size_t npp = (size_t)(np > 0 ? np : 1);
+  const size_t lag = sizeof(double) * (size_t)p->dim * npp;
+  const TileGrid tg = tile_grid(p);
+  const size_t nb = (size_t)((tg.ntiles + SCAN_TILE - 1) / SCAN_TILE);
+  return 7 * align256(nc * t) + 5 * align256(lag) + align256(sizeof(double) * npp) +
+         3 * align256(sizeof(int) * tg.ntiles) + align256(sizeof(int) * (tg.ntiles + 1)) +
+         align256(sizeof(int) * nb) + 2 * align256(sizeof(int) * npp) + 256 + 256;
 }
 
 extern "C" ib_status ib_workspace_size(const ib_grid_params *prm, int64_t n_points,
@@ -322,22 +410,58 @@ static void launch_force(ib_ctx *c, const double *Xh, double *F, bool commit) {
   });
 }
 
-template <typename T, int DIM>
+// Step 2b: sort the points into spreading tiles (gathering them in sorted
+// order), list the tiles their stencils reach, then gather per tile.
+// ADD = false: f = spread force on listed tiles and flags for the explicit
+// step (the step's own buffers); ADD = true: f += spread force (the public
+// entry point).
+template <typename T, int DIM, bool ADD>
 static void launch_spread(ib_ctx *c, const double *X, const double *F, const double *w,
                           int64_t np, void *const f[3]) {
+  const double inv_h = 1.0 / c->prm.h;
+  const unsigned pb = (unsigned)((np + 255) / 256);
+  const unsigned nb = (unsigned)((c->tg.ntiles + SCAN_TILE - 1) / SCAN_TILE);
+  launch(c, KP_SORT, [&] {
+    hipLaunchKernelGGL((k_bin<DIM>), dim3(pb), dim3(256), 0, c->stream, X, np, c->g, c->tg,
+                       inv_h, c->t_count, c->tile_of, c->rank_of);
+  });
+  launch(c, KP_SORT, [&] {
+    hipLaunchKernelGGL(k_scan_sums, dim3(nb), dim3(256), 0, c->stream, c->t_count, c->t_bsum,
+                       c->tg.ntiles);
+  });
+  launch(c, KP_SORT, [&] {
+    hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(256), 0, c->stream, c->t_bsum, (int)nb,
+                       c->t_nlist);
+  });
+  launch(c, KP_SORT, [&] {
+    hipLaunchKernelGGL(k_scan_write, dim3(nb), dim3(256), 0, c->stream, c->t_count,
+                       c->t_start, c->t_bsum, c->tg.ntiles);
+  });
+  launch(c, KP_SORT, [&] {
+    hipLaunchKernelGGL((k_scatter<DIM>), dim3(pb), dim3(256), 0, c->stream, c->tile_of,
+                       c->rank_of, c->t_start, X, F, w, c->Xs, c->Fs, c->ws, np);
+  });
+  launch(c, KP_SORT, [&] {
+    hipLaunchKernelGGL((k_touch<DIM>), dim3((unsigned)((c->tg.ntiles + 255) / 256)), dim3(256),
+                       0, c->stream, c->t_start, ADD ? nullptr : c->t_flag, c->t_list,
+                       c->t_nlist, c->g, c->tg);
+  });
   SpreadArgs<T, DIM> a{};
-  a.X = X;
-  a.F = F;
-  a.w = w;
+  a.Xs = c->Xs;
+  a.Fs = c->Fs;
+  a.ws = c->ws;
   for (int i = 0; i < 3; i++) a.f[i] = (T *)(i < DIM ? f[i] : nullptr);
+  a.start = c->t_start;
+  a.list = c->t_list;
+  a.nlist = c->t_nlist;
   a.np = np;
   a.g = c->g;
-  a.inv_h = 1.0 / c->prm.h;
+  a.tg = c->tg;
+  a.inv_h = inv_h;
   a.inv_hd = 1.0 / std::pow(c->prm.h, DIM);
-  const int64_t nthreads = np * (DIM == 3 ? 16 : 4);
+  const unsigned grid = (unsigned)std::min<int64_t>(c->tg.ntiles, 4096);
   launch(c, KP_SPREAD, [&] {
-    hipLaunchKernelGGL((k_spread<T, DIM>), dim3((unsigned)((nthreads + 255) / 256)), dim3(256),
-                       0, c->stream, a);
+    hipLaunchKernelGGL((k_spread_tiles<T, DIM, ADD>), dim3(grid), dim3(256), 0, c->stream, a);
   });
 }
 
@@ -347,12 +471,14 @@ static void launch_explicit(ib_ctx *c, bool first) {
   for (int i = 0; i < 3; i++) {
     a.u[i] = (const T *)(i < DIM ? c->buf.u[i] : nullptr);
     a.nl[i] = (T *)(i < DIM ? c->buf.nl_prev[i] : nullptr);
-    a.f[i] = (T *)(i < DIM ? c->f[i] : nullptr);
+    a.f[i] = (const T *)(i < DIM ? c->f[i] : nullptr);
     a.delta[i] = (T *)(i < DIM ? c->delta[i] : nullptr);
   }
   a.p = c->buf.p;
   a.psi = (const T *)c->buf.psi;
+  a.flag = c->t_flag;
   a.g = c->g;
+  a.tg = c->tg;
   a.inv_h = 1.0 / c->prm.h;
   a.inv_h2 = 1.0 / (c->prm.h * c->prm.h);
   a.dt = c->prm.dt;
@@ -386,7 +512,7 @@ static void enqueue_step(ib_ctx *c) {
                         true, first);
   // Step 2a (+ commit X^{n+1}) and Step 2b
   launch_force<DIM>(c, c->Xh, c->F, true);
-  launch_spread<T, DIM>(c, c->Xh, c->F, c->w, c->np, c->f);
+  launch_spread<T, DIM, false>(c, c->Xh, c->F, c->w, c->np, c->f);
   // Steps 3a-3b
   launch_explicit<T, DIM>(c, first);
   // split order of this step
@@ -510,6 +636,20 @@ extern "C" ib_status ib_init(ib_ctx **out, const ib_grid_params *prm, const ib_b
   c->Xn1 = (double *)w; w += lb;
   c->Xh = (double *)w; w += lb;
   c->F = (double *)w; w += lb;
+  c->tg = tile_grid(prm);
+  const size_t tb = align256(sizeof(int) * c->tg.ntiles);
+  const size_t pb = align256(sizeof(int) * np);
+  c->Xs = (double *)w; w += lb;
+  c->Fs = (double *)w; w += lb;
+  c->ws = (double *)w; w += align256(sizeof(double) * np);
+  c->t_count = (int *)w; w += tb;
+  c->t_flag = (int *)w; w += tb;
+  c->t_list = (int *)w; w += tb;
+  c->t_start = (int *)w; w += align256(sizeof(int) * (c->tg.ntiles + 1));
+  c->t_bsum = (int *)w; w += align256(sizeof(int) * ((c->tg.ntiles + SCAN_TILE - 1) / SCAN_TILE));
+  c->tile_of = (int *)w; w += pb;
+  c->rank_of = (int *)w; w += pb;
+  c->t_nlist = (int *)w; w += 256;
   c->flag = (int *)w;
   // upload the structure
   auto bail = [&](ib_status e) { ib_destroy(c); return e; };
@@ -525,11 +665,11 @@ extern "C" ib_status ib_init(ib_ctx **out, const ib_grid_params *prm, const ib_b
       hipMemcpyAsync(c->l0, l0.data(), sizeof(double) * l0.size(), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
       hipMemcpyAsync(c->w, st->w, sizeof(double) * np, hipMemcpyHostToDevice, c->stream) != hipSuccess)
     return bail(fail(IB_E_DEVICE, "upload of the link table failed"));
-  // clear spread targets and the flag; seed div_prev at a fresh start
-  for (int i = 0; i < d; i++)
-    if (hipMemsetAsync(c->f[i], 0, fb, c->stream) != hipSuccess)
-      return bail(fail(IB_E_DEVICE, "clearing the workspace failed"));
-  if (hipMemsetAsync(c->flag, 0, 256, c->stream) != hipSuccess)
+  // clear the tile counts / flags and the status word; seed div_prev at a
+  // fresh start
+  if (hipMemsetAsync(c->t_count, 0, tb, c->stream) != hipSuccess ||
+      hipMemsetAsync(c->t_flag, 0, tb, c->stream) != hipSuccess ||
+      hipMemsetAsync(c->flag, 0, 256, c->stream) != hipSuccess)
     return bail(fail(IB_E_DEVICE, "clearing the workspace failed"));
   if (prm->step0 == 0) {
     if (c->f32) {
@@ -581,6 +721,9 @@ extern "C" ib_status ib_spread(ib_ctx *c, const double *X, const double *F, cons
   if (!c) return fail(IB_E_STATE, "null context");
   if (npts < 0 || (npts > 0 && (!X || !F || !w)) || !f_out)
     return fail(IB_E_INVALID, "bad spread arguments");
+  if (npts > c->np)
+    return fail(IB_E_INVALID, "npts %lld exceeds the context's %lld points", (long long)npts,
+                (long long)c->np);
   for (int i = 0; i < c->dim; i++)
     if (!f_out[i]) return fail(IB_E_INVALID, "null output component %d", i);
   if (!accumulate)
@@ -588,11 +731,11 @@ extern "C" ib_status ib_spread(ib_ctx *c, const double *X, const double *F, cons
       HIP_TRY(hipMemsetAsync(f_out[i], 0, (size_t)c->g.ncell * c->tsz, c->stream));
   if (npts == 0) return IB_OK;
   if (c->f32) {
-    if (c->dim == 2) launch_spread<float, 2>(c, X, F, w, npts, f_out);
-    else launch_spread<float, 3>(c, X, F, w, npts, f_out);
+    if (c->dim == 2) launch_spread<float, 2, true>(c, X, F, w, npts, f_out);
+    else launch_spread<float, 3, true>(c, X, F, w, npts, f_out);
   } else {
-    if (c->dim == 2) launch_spread<double, 2>(c, X, F, w, npts, f_out);
-    else launch_spread<double, 3>(c, X, F, w, npts, f_out);
+    if (c->dim == 2) launch_spread<double, 2, true>(c, X, F, w, npts, f_out);
+    else launch_spread<double, 3, true>(c, X, F, w, npts, f_out);
   }
   HIP_TRY(hipGetLastError());
   return IB_OK;
@@ -667,17 +810,17 @@ extern "C" ib_status ib_line_solve(void *data, int32_t dtype, const int32_t n[3]
 
 extern "C" ib_status ib_destroy(ib_ctx *c) {
   if (!c) return IB_OK;
-  hipStreamSynchronize(c->stream);
+  (void)hipStreamSynchronize(c->stream);
   for (auto &p : c->pending) {
-    hipEventDestroy(p.a);
-    hipEventDestroy(p.b);
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
   }
-  for (auto e : c->pool) hipEventDestroy(e);
-  if (c->ptr) hipFree(c->ptr);
-  if (c->nbr) hipFree(c->nbr);
-  if (c->kap) hipFree(c->kap);
-  if (c->l0) hipFree(c->l0);
-  if (c->w) hipFree(c->w);
+  for (auto e : c->pool) (void)hipEventDestroy(e);
+  if (c->ptr) (void)hipFree(c->ptr);
+  if (c->nbr) (void)hipFree(c->nbr);
+  if (c->kap) (void)hipFree(c->kap);
+  if (c->l0) (void)hipFree(c->l0);
+  if (c->w) (void)hipFree(c->w);
   delete c;
   return IB_OK;
 }

@@ -12,11 +12,6 @@ namespace ibgm {
 
 // ---------------------------------------------------------------- helpers --
 
-__device__ __forceinline__ int64_t floor_mod(int64_t i, int64_t n) {
-  int64_t r = i % n;
-  return r < 0 ? r + n : r;
-}
-
 // Weights of the 4-point kernel of eq:discretedelta for the stencil
 // floor(xi)-1 .. floor(xi)+2 given q = xi - floor(xi) in [0, 1).  The four
 // branches collapse to one square root s = sqrt(1 + 4q - 4q^2):
@@ -31,19 +26,100 @@ __device__ __forceinline__ void delta_weights(C q, C w[4]) {
   w[3] = (C(1) + C(2) * q - s) * C(0.125);
 }
 
+// Periodic wrap of a cell index b (any sign, |b| < 2^24) into [0, n).
+__device__ __forceinline__ int wrap_cell(int b, int n) {
+  b -= n * (int)floorf((float)b / (float)n);
+  b += b < 0 ? n : 0;
+  b -= b >= n ? n : 0;
+  return b;
+}
+
 // Stencil start (wrapped) and weights along one axis for a point coordinate
 // x (physical, unwrapped) and staggering offset s (0 on the face axis of a
 // velocity component, 1/2 otherwise).
 template <typename C>
-__device__ __forceinline__ int64_t axis_stencil(double x, double inv_h, double s,
-                                                int64_t n, C w[4]) {
+__device__ __forceinline__ int axis_stencil(double x, double inv_h, double s, int n, C w[4]) {
   double xi = x * inv_h - s;
   // A non-finite or absurdly large coordinate must not become an index: it
   // is pinned to cell 0 and its NaN weights carry the failure forward.
-  if (!(fabs(xi) < 1e15)) xi = __builtin_nan("");
+  if (!(fabs(xi) < 1e7)) xi = __builtin_nan("");
   double fl = isnan(xi) ? 0.0 : floor(xi);
   delta_weights<C>((C)(xi - fl), w);
-  return floor_mod((int64_t)fl - 1, n);
+  return wrap_cell((int)fl - 1, n);
+}
+
+// ----------------------------------------------------- wave-level scans --
+//
+// Affine maps v -> A v + B, the chunk summaries of the line-solve scans.
+// after(f, g) is "f, then g".
+
+struct Aff {
+  double A, B;
+};
+
+__device__ __forceinline__ Aff after(Aff f, Aff g) { return {g.A * f.A, g.A * f.B + g.B}; }
+
+// Move a double across lanes with a DPP row shift (CTRL = 0x110|n: row_shr n,
+// 0x100|n: row_shl n); lanes whose source falls outside their 16-lane row
+// receive `ident`.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v, double ident) {
+  const int lo = __builtin_amdgcn_update_dpp(__double2loint(ident), __double2loint(v), CTRL,
+                                             0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(__double2hiint(ident), __double2hiint(v), CTRL,
+                                             0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ Aff dpp_aff(Aff f) {
+  return {dpp_move<CTRL>(f.A, 1.0), dpp_move<CTRL>(f.B, 0.0)};
+}
+
+__device__ __forceinline__ Aff readlane_aff(Aff f, int lane) {
+  const int alo = __builtin_amdgcn_readlane(__double2loint(f.A), lane);
+  const int ahi = __builtin_amdgcn_readlane(__double2hiint(f.A), lane);
+  const int blo = __builtin_amdgcn_readlane(__double2loint(f.B), lane);
+  const int bhi = __builtin_amdgcn_readlane(__double2hiint(f.B), lane);
+  return {__hiloint2double(ahi, alo), __hiloint2double(bhi, blo)};
+}
+
+// Over the 64 lanes of a wave, lane l holding chunk l's map: the composite of
+// the chunks before l (chunk 0 acting first) and of all 64.  Row-local
+// Hillis-Steele steps use DPP row shifts; the four row totals are read back
+// with readlane and chained.  Requires all 64 lanes active.
+__device__ __forceinline__ void wave_prefix64(Aff f, Aff &excl, Aff &tot) {
+  Aff x = f;
+  x = after(dpp_aff<0x111>(x), x);
+  x = after(dpp_aff<0x112>(x), x);
+  x = after(dpp_aff<0x114>(x), x);
+  x = after(dpp_aff<0x118>(x), x);
+  const Aff r0 = readlane_aff(x, 15), r1 = readlane_aff(x, 31), r2 = readlane_aff(x, 47),
+            r3 = readlane_aff(x, 63);
+  const Aff p1 = r0, p2 = after(r0, r1), p3 = after(p2, r2);
+  tot = after(p3, r3);
+  const Aff e = dpp_aff<0x111>(x);  // exclusive within the row
+  const int row = __lane_id() >> 4;
+  const Aff pr = row == 0 ? Aff{1.0, 0.0} : (row == 1 ? p1 : (row == 2 ? p2 : p3));
+  excl = after(pr, e);
+}
+
+// Mirror image for maps acting right to left (chunk 63 first): the composite
+// of the chunks after l, and of all 64.
+__device__ __forceinline__ void wave_suffix64(Aff f, Aff &excl, Aff &tot) {
+  Aff x = f;
+  x = after(dpp_aff<0x101>(x), x);
+  x = after(dpp_aff<0x102>(x), x);
+  x = after(dpp_aff<0x104>(x), x);
+  x = after(dpp_aff<0x108>(x), x);
+  const Aff t0 = readlane_aff(x, 0), t1 = readlane_aff(x, 16), t2 = readlane_aff(x, 32),
+            t3 = readlane_aff(x, 48);
+  const Aff q2 = t3, q1 = after(t3, t2), q0 = after(q1, t1);
+  tot = after(q0, t0);
+  const Aff e = dpp_aff<0x101>(x);  // exclusive within the row
+  const int row = __lane_id() >> 4;
+  const Aff qr = row == 3 ? Aff{1.0, 0.0} : (row == 2 ? q2 : (row == 1 ? q1 : q0));
+  excl = after(qr, e);
 }
 
 struct Grid {
@@ -77,7 +153,7 @@ __global__ void __launch_bounds__(256) k_interp(InterpArgs<T, DIM> a) {
   if (k >= a.np) return;
   const int32_t nn[3] = {a.g.n0, a.g.n1, a.g.n2};
   C w[3][4];
-  int64_t b[3];
+  int b[3];
   for (int ax = 0; ax < DIM; ax++)
     b[ax] = axis_stencil<C>(a.X[ax * a.np + k], a.inv_h, ax == c ? 0.0 : 0.5,
                             nn[ax], w[ax]);
@@ -174,58 +250,292 @@ __global__ void __launch_bounds__(256) k_force(ForceArgs<DIM> a) {
 }
 
 // ----------------------------------------------------- Lagrangian: Step 2b --
+//
+// Spreading is an owner-computes gather over cubic tiles of TS cells:
+//  1. k_bin / k_scan_* / k_scatter counting-sort the points by the tile
+//     of their anchor cell a = floor(X/h - 1/2) - 1 (per axis).  Every MAC
+//     component's 4-point stencil starts at a or a + 1, so a point touches
+//     cells a .. a+4 along each axis.
+//  2. k_touch lists the tiles some stencil reaches (and flags them for the
+//     explicit step); k_spread_tiles then collects, for each listed tile,
+//     every (point, stencil row) of the tiles whose anchors lie within 4
+//     cells below it that lands in the tile, accumulates in LDS and writes
+//     the tile's cells (store mode: f = sum; add mode: f += sum).  No
+//     global atomics on f; unlisted tiles are flagged empty, never read.
 
-// One thread per (point, stencil row): the row is a (y[, z]) offset of the
-// 4^DIM support; the thread adds the 4 x-neighbours of every component with
-// device atomics.  val = F_c w_k / h^d times the tensor-product weights.
-template <typename T, int DIM>
-struct SpreadArgs {
-  const double *X, *F, *w;
-  T *f[3];
-  int64_t np;
-  Grid g;
-  double inv_h, inv_hd;
+constexpr int TS = 8;
+
+struct TileGrid {
+  int32_t nt[3];    // tiles per axis
+  int64_t ntiles;
 };
 
-template <typename T>
-__device__ __forceinline__ void atomic_add_grid(T *p, T v) {
-  unsafeAtomicAdd(p, v);
+__device__ __forceinline__ int anchor_cell(double x, double inv_h, int n) {
+  double xi = x * inv_h - 0.5;
+  if (!(fabs(xi) < 1e7)) xi = 0.0;  // non-finite positions land in cell 0
+  return wrap_cell((int)floor(xi) - 1, n);
+}
+
+template <int DIM>
+__global__ void __launch_bounds__(256) k_bin(const double *X, int64_t np, Grid g,
+                                              TileGrid tg, double inv_h, int *count,
+                                              int *tile_of, int *rank_of) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= np) return;
+  const int32_t nn[3] = {g.n0, g.n1, g.n2};
+  int64_t t = 0, mul = 1;
+  for (int ax = 0; ax < DIM; ax++) {
+    t += (anchor_cell(X[ax * np + k], inv_h, nn[ax]) / TS) * mul;
+    mul *= tg.nt[ax];
+  }
+  tile_of[k] = (int)t;
+  rank_of[k] = atomicAdd(&count[t], 1);
+}
+
+// Exclusive scan of the per-tile counts into start[0..ntiles] in three
+// passes over blocks of SCAN_TILE counts (4 per thread): block sums, a scan
+// of the block sums, then each block's own scan; the counts are cleared for
+// the next step.
+constexpr int SCAN_TILE = 1024;
+
+__device__ __forceinline__ int block_exclusive_scan256(int v, int *sh, int &total) {
+  const int tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const int add = tid >= off ? sh[tid - off] : 0;
+    __syncthreads();
+    sh[tid] += add;
+    __syncthreads();
+  }
+  total = sh[255];
+  const int incl = sh[tid];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ void __launch_bounds__(256) k_scan_sums(const int *count, int *bsum, int64_t ntiles) {
+  __shared__ int sh[256];
+  const int64_t b = (int64_t)blockIdx.x * SCAN_TILE + 4 * threadIdx.x;
+  int v = 0;
+  for (int q = 0; q < 4; q++)
+    if (b + q < ntiles) v += count[b + q];
+  int total;
+  block_exclusive_scan256(v, sh, total);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(256) k_scan_bsums(int *bsum, int nb, int *nlist) {
+  __shared__ int sh[256];
+  if (threadIdx.x == 0) *nlist = 0;
+  const int per = (nb + 255) / 256;
+  const int b = threadIdx.x * per;
+  int v = 0;
+  for (int q = 0; q < per; q++)
+    if (b + q < nb) v += bsum[b + q];
+  int total;
+  int run = block_exclusive_scan256(v, sh, total);
+  for (int q = 0; q < per; q++)
+    if (b + q < nb) {
+      const int c = bsum[b + q];
+      bsum[b + q] = run;
+      run += c;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_scan_write(int *count, int *start, const int *bsum,
+                                                    int64_t ntiles) {
+  __shared__ int sh[256];
+  const int64_t b = (int64_t)blockIdx.x * SCAN_TILE + 4 * threadIdx.x;
+  int c[4], v = 0;
+  for (int q = 0; q < 4; q++) {
+    c[q] = b + q < ntiles ? count[b + q] : 0;
+    v += c[q];
+  }
+  int total;
+  int run = block_exclusive_scan256(v, sh, total) + bsum[blockIdx.x];
+  for (int q = 0; q < 4; q++)
+    if (b + q < ntiles) {
+      start[b + q] = run;
+      run += c[q];
+      count[b + q] = 0;
+    }
+  if (b < ntiles && b + 4 >= ntiles) start[ntiles] = run;
+}
+
+// Place every point at its sorted slot and gather its position, force and
+// weight there, so that a tile reads its points contiguously.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_scatter(const int *tile_of, const int *rank_of,
+                                                  const int *start, const double *X,
+                                                  const double *F, const double *w, double *Xs,
+                                                  double *Fs, double *ws, int64_t np) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= np) return;
+  const int64_t d = start[tile_of[k]] + rank_of[k];
+  for (int c = 0; c < DIM; c++) {
+    Xs[c * np + d] = X[c * np + k];
+    Fs[c * np + d] = F[c * np + k];
+  }
+  ws[d] = w[k];
+}
+
+// Tiles whose cells lie within 4 cells above an anchor tile, per axis: the
+// tiles holding the cells lo-4 .. hi-1 (cyclic), at most 3 distinct.
+__device__ __forceinline__ int source_tiles(int lo, int hi, int n, int list[3]) {
+  int len = 0;
+  for (int cell = lo - 4; cell < hi; cell++) {
+    const int tt = wrap_cell(cell, n) / TS;
+    bool seen = false;
+    for (int q = 0; q < len; q++) seen |= list[q] == tt;
+    if (!seen && len < 3) list[len++] = tt;
+  }
+  return len;
+}
+
+// One thread per tile: does any point's stencil reach the tile?  Touched
+// tiles are appended to `list` (order arbitrary) and, in store mode, every
+// tile's flag records whether f holds force there.
+template <int DIM>
+__global__ void __launch_bounds__(256) k_touch(const int *start, int *flag, int *list,
+                                                int *nlist, Grid g, TileGrid tg) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= tg.ntiles) return;
+  const int32_t nn[3] = {g.n0, g.n1, g.n2};
+  const int tc[3] = {(int)(t % tg.nt[0]), (int)((t / tg.nt[0]) % tg.nt[1]),
+                     DIM == 3 ? (int)(t / ((int64_t)tg.nt[0] * tg.nt[1])) : 0};
+  int lst[3][3], len[3];
+  for (int ax = 0; ax < 3; ax++) {
+    if (ax >= DIM) {
+      lst[ax][0] = 0;
+      len[ax] = 1;
+    } else {
+      len[ax] = source_tiles(tc[ax] * TS, min(nn[ax], tc[ax] * TS + TS), nn[ax], lst[ax]);
+    }
+  }
+  int total = 0;
+  for (int i2 = 0; i2 < len[2]; i2++)
+    for (int i1 = 0; i1 < len[1]; i1++)
+      for (int i0 = 0; i0 < len[0]; i0++) {
+        const int64_t tt = lst[0][i0] + (int64_t)tg.nt[0] * (lst[1][i1] + (int64_t)tg.nt[1] * lst[2][i2]);
+        total += start[tt + 1] - start[tt];
+      }
+  if (flag) flag[t] = total > 0;
+  if (total > 0) list[atomicAdd(nlist, 1)] = (int)t;
 }
 
 template <typename T, int DIM>
-__global__ void __launch_bounds__(256) k_spread(SpreadArgs<T, DIM> a) {
+struct SpreadArgs {
+  const double *Xs, *Fs, *ws;  // points in sorted order
+  T *f[3];
+  const int *start, *list, *nlist;
+  int64_t np;
+  Grid g;
+  TileGrid tg;
+  double inv_h, inv_hd;
+};
+
+// Workgroups loop over the touched tiles (a bounded loop: at most ntiles
+// entries).  For each tile: gather (point, stencil row) items of the source
+// tiles into LDS, then write the tile's cells (f = sum, or f += sum).
+template <typename T, int DIM, bool ADD>
+__global__ void __launch_bounds__(256) k_spread_tiles(SpreadArgs<T, DIM> a) {
   using C = T;
   constexpr int ROWS = DIM == 3 ? 16 : 4;
-  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t k = tid / ROWS;
-  const int row = (int)(tid % ROWS);
-  if (k >= a.np) return;
-  const int t1 = row & 3, t2 = row >> 2;
+  constexpr int CELLS = DIM == 3 ? TS * TS * TS : TS * TS;
+  __shared__ C acc[DIM][CELLS];
+  __shared__ int c_start[27], c_pref[28], s_list[3][3], s_len[3], s_cnt[27];
   const int32_t nn[3] = {a.g.n0, a.g.n1, a.g.n2};
-  double xk[DIM];
-  for (int ax = 0; ax < DIM; ax++) xk[ax] = a.X[ax * a.np + k];
-  const double wk = a.w[k] * a.inv_hd;
-  for (int c = 0; c < DIM; c++) {
-    C w0[4], w1[4], w2[4];
-    int64_t b0 = axis_stencil<C>(xk[0], a.inv_h, c == 0 ? 0.0 : 0.5, nn[0], w0);
-    int64_t b1 = axis_stencil<C>(xk[1], a.inv_h, c == 1 ? 0.0 : 0.5, nn[1], w1);
-    int64_t jj = b1 + t1;
-    jj -= jj >= nn[1] ? nn[1] : 0;
-    C rw = w1[t1];
-    int64_t kk = 0;
-    if (DIM == 3) {
-      int64_t b2 = axis_stencil<C>(xk[2], a.inv_h, c == 2 ? 0.0 : 0.5, nn[2], w2);
-      kk = b2 + t2;
-      kk -= kk >= nn[2] ? nn[2] : 0;
-      rw *= w2[t2];
+  int ntodo = *a.nlist;
+  ntodo = ntodo < a.tg.ntiles ? ntodo : (int)a.tg.ntiles;
+  for (int e = blockIdx.x; e < ntodo; e += gridDim.x) {
+    const int64_t t = a.list[e];
+    const int tc[3] = {(int)(t % a.tg.nt[0]), (int)((t / a.tg.nt[0]) % a.tg.nt[1]),
+                       DIM == 3 ? (int)(t / ((int64_t)a.tg.nt[0] * a.tg.nt[1])) : 0};
+    int lo[3], hi[3];
+    for (int ax = 0; ax < 3; ax++) {
+      lo[ax] = ax < DIM ? tc[ax] * TS : 0;
+      hi[ax] = ax < DIM ? min(nn[ax], lo[ax] + TS) : 1;
     }
-    const C val = (C)(a.F[c * a.np + k] * wk) * rw;
-    T *row_ptr = a.f[c] + (kk * nn[1] + jj) * nn[0];
-    for (int t0 = 0; t0 < 4; t0++) {
-      int64_t ii = b0 + t0;
-      ii -= ii >= nn[0] ? nn[0] : 0;
-      atomic_add_grid<T>(row_ptr + ii, (T)(val * w0[t0]));
+    if (threadIdx.x < 3) {
+      const int ax = threadIdx.x;
+      if (ax >= DIM) {
+        s_list[ax][0] = 0;
+        s_len[ax] = 1;
+      } else {
+        int l3[3];
+        const int len = source_tiles(lo[ax], hi[ax], nn[ax], l3);
+        for (int q = 0; q < len; q++) s_list[ax][q] = l3[q];
+        s_len[ax] = len;
+      }
     }
+    for (int i = threadIdx.x; i < DIM * CELLS; i += blockDim.x) (&acc[0][0])[i] = C(0);
+    __syncthreads();
+    const int ncomb = s_len[0] * s_len[1] * s_len[2];
+    if (threadIdx.x < ncomb) {
+      const int m = threadIdx.x;
+      const int i0 = m % s_len[0], i1 = (m / s_len[0]) % s_len[1], i2 = m / (s_len[0] * s_len[1]);
+      const int64_t tt = s_list[0][i0] + (int64_t)a.tg.nt[0] *
+                                             (s_list[1][i1] + (int64_t)a.tg.nt[1] * s_list[2][i2]);
+      const int s0 = a.start[tt];
+      c_start[m] = s0;
+      s_cnt[m] = a.start[tt + 1] - s0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int pref = 0;
+      for (int m = 0; m < ncomb; m++) {
+        c_pref[m] = pref;
+        pref += s_cnt[m];
+      }
+      c_pref[ncomb] = pref;
+    }
+    __syncthreads();
+    const int items = c_pref[ncomb] * ROWS;
+    for (int it = threadIdx.x; it < items; it += blockDim.x) {
+      const int pi = it / ROWS, row = it % ROWS;
+      int slot = 0;
+      while (c_pref[slot + 1] <= pi) slot++;
+      const int64_t k = c_start[slot] + (pi - c_pref[slot]);
+      const int t1 = row & 3, t2 = row >> 2;
+      double xk[DIM];
+      for (int ax = 0; ax < DIM; ax++) xk[ax] = a.Xs[ax * a.np + k];
+      const double wk = a.ws[k] * a.inv_hd;
+      for (int c = 0; c < DIM; c++) {
+        C w0[4], w1[4], w2[4];
+        int jj = axis_stencil<C>(xk[1], a.inv_h, c == 1 ? 0.0 : 0.5, nn[1], w1) + t1;
+        jj -= jj >= nn[1] ? nn[1] : 0;
+        if (jj < lo[1] || jj >= hi[1]) continue;
+        C rw = w1[t1];
+        int kk = 0;
+        if (DIM == 3) {
+          kk = axis_stencil<C>(xk[2], a.inv_h, c == 2 ? 0.0 : 0.5, nn[2], w2) + t2;
+          kk -= kk >= nn[2] ? nn[2] : 0;
+          if (kk < lo[2] || kk >= hi[2]) continue;
+          rw *= w2[t2];
+        }
+        const int b0 = axis_stencil<C>(xk[0], a.inv_h, c == 0 ? 0.0 : 0.5, nn[0], w0);
+        const C val = (C)(a.Fs[c * a.np + k] * wk) * rw;
+        const int lrow = ((kk - lo[2]) * TS + (jj - lo[1])) * TS;
+        for (int t0 = 0; t0 < 4; t0++) {
+          int ii = b0 + t0;
+          ii -= ii >= nn[0] ? nn[0] : 0;
+          if (ii >= lo[0] && ii < hi[0]) atomicAdd(&acc[c][lrow + ii - lo[0]], val * w0[t0]);
+        }
+      }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < CELLS; i += blockDim.x) {
+      const int li = i % TS, lj = (i / TS) % TS, lk = DIM == 3 ? i / (TS * TS) : 0;
+      const int gi = lo[0] + li, gj = lo[1] + lj, gk = lo[2] + lk;
+      if (gi >= hi[0] || gj >= hi[1] || gk >= hi[2]) continue;
+      const int64_t idx = gi + (int64_t)nn[0] * (gj + (int64_t)nn[1] * gk);
+      for (int c = 0; c < DIM; c++) {
+        if (ADD) a.f[c][idx] = (T)((C)a.f[c][idx] + acc[c][i]);
+        else a.f[c][idx] = (T)acc[c][i];
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -236,17 +546,20 @@ __global__ void __launch_bounds__(256) k_spread(SpreadArgs<T, DIM> a) {
 //          + 1/2 advective form),
 //   Nh   = 3/2 N_c - 1/2 N_c^{n-1}   (N_c alone at n = 0),
 //   d*_c = dt ( -Nh + (mu Lap u_c - G_c p* + f_c)/rho ),  p* = p + psi (FP64),
-// and stores d*_c (the delta-form right-hand side of the first sweep),
-// N_c into nl (for the next step) and clears f_c for the next spreading.
+// and stores d*_c (the delta-form right-hand side of the first sweep) and
+// N_c into nl (for the next step).  f_c is read only in tiles the spreading
+// flagged as holding force (zero elsewhere).
 template <typename T, int DIM>
 struct ExplicitArgs {
   const T *u[3];
   T *nl[3];
-  T *f[3];
+  const T *f[3];
   T *delta[3];
   const double *p;
   const T *psi;
+  const int *flag;  // per spreading tile: 1 if f holds force there
   Grid g;
+  TileGrid tg;
   double inv_h, inv_h2, dt, mu, inv_rho;
   int first, advect;
 };
@@ -271,6 +584,8 @@ __global__ void __launch_bounds__(256) k_explicit(ExplicitArgs<T, DIM> a) {
     dp[2] = dm[2] = 0;
   }
   const double ps0 = a.p[idx] + (double)a.psi[idx];
+  const int64_t tile = i / TS + (int64_t)a.tg.nt[0] * (j / TS + (int64_t)a.tg.nt[1] * (k / TS));
+  const bool forced = a.flag[tile] != 0;
 #pragma unroll
   for (int ci = 0; ci < DIM; ci++) {
     const T *__restrict__ ui = a.u[ci];
@@ -297,11 +612,10 @@ __global__ void __launch_bounds__(256) k_explicit(ExplicitArgs<T, DIM> a) {
     const double psm = a.p[idx + dm[ci]] + (double)a.psi[idx + dm[ci]];
     const C gp = (C)((ps0 - psm) * a.inv_h);
     const C Nh = a.first ? N : C(1.5) * N - C(0.5) * (C)a.nl[ci][idx];
-    const C fc = (C)a.f[ci][idx];
+    const C fc = forced ? (C)a.f[ci][idx] : C(0);
     const C d = (C)a.dt * (-Nh + ((C)a.mu * lap * (C)a.inv_h2 - gp + fc) * (C)a.inv_rho);
     a.delta[ci][idx] = (T)d;
     a.nl[ci][idx] = (T)N;
-    a.f[ci][idx] = (T)0;
   }
 }
 
@@ -391,10 +705,54 @@ __device__ __forceinline__ void sweep_store(const SweepArgs<T> &a, int fld,
   }
 }
 
+// 16-byte vector access to a full chunk of M consecutive values (host
+// guarantees 16-byte alignment and M * sizeof(T) a multiple of 16).
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+  using type = float4;
+  static constexpr int n = 4;
+};
+template <>
+struct Vec16<double> {
+  using type = double2;
+  static constexpr int n = 2;
+};
+
+template <typename T, int M>
+__device__ __forceinline__ void vload(const T *p, double *r) {
+  using V = typename Vec16<T>::type;
+  constexpr int K = Vec16<T>::n;
+#pragma unroll
+  for (int v = 0; v < M / K; v++) {
+    const V x = reinterpret_cast<const V *>(p)[v];
+    const T *e = reinterpret_cast<const T *>(&x);
+#pragma unroll
+    for (int q = 0; q < K; q++) r[v * K + q] = (double)e[q];
+  }
+}
+
+template <typename T, int M>
+__device__ __forceinline__ void vstore(T *p, const double *r) {
+  using V = typename Vec16<T>::type;
+  constexpr int K = Vec16<T>::n;
+#pragma unroll
+  for (int v = 0; v < M / K; v++) {
+    V x;
+    T *e = reinterpret_cast<T *>(&x);
+#pragma unroll
+    for (int q = 0; q < K; q++) e[q] = (T)r[v * K + q];
+    reinterpret_cast<V *>(p)[v] = x;
+  }
+}
+
 // Contiguous (x) lines.  blockDim = 256; G lanes per line (power of two
 // <= 64), each with a chunk of M consecutive elements; 256/G lines per block;
 // blockIdx.y = field.  Chunks beyond the line end are empty (identity maps).
-template <typename T, int M, int MODE>
+// VEC: every chunk is full and 16-byte aligned (N = G M), so chunks move
+// with 16-byte vector loads and stores.
+template <typename T, int M, int MODE, bool VEC>
 __global__ void __launch_bounds__(256) k_sweep_x(SweepArgs<T> a) {
   const int G = a.G;
   const int lane = threadIdx.x & (G - 1);
@@ -411,16 +769,20 @@ __global__ void __launch_bounds__(256) k_sweep_x(SweepArgs<T> a) {
   const double al = a.alpha, ic = a.inv_c;
 
   double r[M];
+  if (VEC && MODE != SW_DIV) {
+    vload<T, M>(a.f[fld] + base + s, r);
+  } else {
 #pragma unroll
-  for (int q = 0; q < M; q++) {
-    r[q] = 0.0;
-    if (q < cnt) {
-      double v = sweep_load<T, MODE>(a, fld, base + s + q, s + q, jl, kl);
-      if (MODE == SW_DIV) {
-        if (live) a.divn[base + s + q] = (T)(v * a.inv_h);
-        v *= a.div_scale;
+    for (int q = 0; q < M; q++) {
+      r[q] = 0.0;
+      if (q < cnt) {
+        double v = sweep_load<T, MODE>(a, fld, base + s + q, s + q, jl, kl);
+        if (MODE == SW_DIV) {
+          if (live) a.divn[base + s + q] = (T)(v * a.inv_h);
+          v *= a.div_scale;
+        }
+        r[q] = v;
       }
-      r[q] = v;
     }
   }
   // forward recurrence over the chunk from zero
@@ -433,15 +795,20 @@ __global__ void __launch_bounds__(256) k_sweep_x(SweepArgs<T> a) {
       A *= al;
     }
   double B = z;
-  // inclusive scan of the affine maps (earlier lanes act first)
-  for (int off = 1; off < G; off <<= 1) {
-    const double Ap = __shfl_up(A, off, G), Bp = __shfl_up(B, off, G);
-    if (lane >= off) {
-      B = A * Bp + B;
-      A = A * Ap;
+  double win;
+  if (G == 64) {
+    Aff ex, tot;
+    wave_prefix64(Aff{A, B}, ex, tot);
+    win = ex.A * (tot.B / (1.0 - tot.A)) + ex.B;
+  } else {
+    // inclusive scan of the affine maps (earlier lanes act first)
+    for (int off = 1; off < G; off <<= 1) {
+      const double Ap = __shfl_up(A, off, G), Bp = __shfl_up(B, off, G);
+      if (lane >= off) {
+        B = A * Bp + B;
+        A = A * Ap;
+      }
     }
-  }
-  {
     const double At = __shfl(A, G - 1, G), Bt = __shfl(B, G - 1, G);
     const double wlast = Bt / (1.0 - At);
     double Ae = __shfl_up(A, 1, G), Be = __shfl_up(B, 1, G);
@@ -449,7 +816,9 @@ __global__ void __launch_bounds__(256) k_sweep_x(SweepArgs<T> a) {
       Ae = 1.0;
       Be = 0.0;
     }
-    const double win = Ae * wlast + Be;
+    win = Ae * wlast + Be;
+  }
+  {
     double pw = al;
 #pragma unroll
     for (int q = 0; q < M; q++)
@@ -469,15 +838,20 @@ __global__ void __launch_bounds__(256) k_sweep_x(SweepArgs<T> a) {
       A *= al;
     }
   B = t;
-  // suffix scan (later lanes act first)
-  for (int off = 1; off < G; off <<= 1) {
-    const double An = __shfl_down(A, off, G), Bn = __shfl_down(B, off, G);
-    if (lane + off < G) {
-      B = A * Bn + B;
-      A = A * An;
+  double xin;
+  if (G == 64) {
+    Aff ex, tot;
+    wave_suffix64(Aff{A, B}, ex, tot);
+    xin = ex.A * (tot.B / (1.0 - tot.A)) + ex.B;
+  } else {
+    // suffix scan (later lanes act first)
+    for (int off = 1; off < G; off <<= 1) {
+      const double An = __shfl_down(A, off, G), Bn = __shfl_down(B, off, G);
+      if (lane + off < G) {
+        B = A * Bn + B;
+        A = A * An;
+      }
     }
-  }
-  {
     const double A0 = __shfl(A, 0, G), B0 = __shfl(B, 0, G);
     const double x0 = B0 / (1.0 - A0);
     double An = __shfl_down(A, 1, G), Bn = __shfl_down(B, 1, G);
@@ -485,7 +859,9 @@ __global__ void __launch_bounds__(256) k_sweep_x(SweepArgs<T> a) {
       An = 1.0;
       Bn = 0.0;
     }
-    const double xin = An * x0 + Bn;
+    xin = An * x0 + Bn;
+  }
+  {
     double pw = al;
 #pragma unroll
     for (int q = M - 1; q >= 0; q--)
@@ -495,6 +871,29 @@ __global__ void __launch_bounds__(256) k_sweep_x(SweepArgs<T> a) {
       }
   }
   if (!live) return;
+  if (VEC) {
+    const int64_t o = base + s;
+    if (MODE == SW_PLAIN || MODE == SW_DIV) {
+      vstore<T, M>(a.f[fld] + o, r);
+    } else if (MODE == SW_FINAL) {
+      double u[M];
+      vload<T, M>(a.u[fld] + o, u);
+#pragma unroll
+      for (int q = 0; q < M; q++) u[q] += r[q];
+      vstore<T, M>(a.u[fld] + o, u);
+    } else {  // SW_PFINAL
+      vstore<T, M>(a.f[fld] + o, r);
+      double dn[M], dp[M], pp[M];
+      vload<T, M>(a.divn + o, dn);
+      vload<T, M>(a.divp + o, dp);
+      vload<double, M>(a.p + o, pp);
+#pragma unroll
+      for (int q = 0; q < M; q++) pp[q] = pp[q] + r[q] - a.half_chi_mu * (dn[q] + dp[q]);
+      vstore<double, M>(a.p + o, pp);
+      vstore<T, M>(a.divp + o, dn);
+    }
+    return;
+  }
 #pragma unroll
   for (int q = 0; q < M; q++)
     if (q < cnt) sweep_store<T, MODE>(a, fld, base + s + q, r[q]);
@@ -611,6 +1010,199 @@ __global__ void __launch_bounds__(LB) k_sweep_s(SweepArgs<T> a, int axis) {
 #pragma unroll
   for (int q = 0; q < M; q++)
     if (q < cnt) sweep_store<T, MODE>(a, fld, base + q * stride, r[q]);
+}
+
+// Strided lines through buffer resources.  blockDim = (64, G): a wave is one
+// 64-wide row of x (256 or 512 contiguous bytes per access), threadIdx.y the
+// chunk of M line elements.  Each array is addressed by a buffer resource
+// based at the block's first column: the lane offset is one VGPR and the
+// element offset pos * stride a wave-uniform scalar, so no per-element
+// 64-bit addresses are held.  Reads past the end of an array return 0 and
+// writes are dropped by the resource's range check.  Requires
+// (N - 1) * stride * sizeof(double) + 64 * sizeof(double) < 2^31.
+template <typename T>
+struct Col {
+  __amdgpu_buffer_rsrc_t r;
+  int vo;  // lane byte offset
+  int sb;  // byte stride between line elements
+  __device__ __forceinline__ Col(const void *base, int64_t bytes, int lane, int64_t stride) {
+    const int64_t lim = bytes < 0x7fffffff ? bytes : 0x7fffffff;
+    r = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)lim, 0x00020000);
+    vo = lane * (int)sizeof(T);
+    sb = (int)(stride * (int64_t)sizeof(T));
+  }
+  __device__ __forceinline__ T ld(int pos) const {
+    if constexpr (sizeof(T) == 4) {
+      return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, vo, pos * sb, 0));
+    } else {
+      const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, vo, pos * sb, 0);
+      return __hiloint2double((int)v[1], (int)v[0]);
+    }
+  }
+  __device__ __forceinline__ void st(int pos, T x) const {
+    if constexpr (sizeof(T) == 4) {
+      __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), r, vo, pos * sb, 0);
+    } else {
+      typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+      u2 v;
+      v[0] = (unsigned)__double2loint(x);
+      v[1] = (unsigned)__double2hiint(x);
+      __builtin_amdgcn_raw_buffer_store_b64(v, r, vo, pos * sb, 0);
+    }
+  }
+};
+
+template <typename T, int M, int MODE, int LB>
+__global__ void __launch_bounds__(LB) k_sweep_sb(SweepArgs<T> a, int axis) {
+  __shared__ double sA[LB], sB[LB];
+  const int tx = threadIdx.x, g = threadIdx.y, G = blockDim.y;
+  const int64_t n0 = a.g.n0, n1 = a.g.n1, ncell = a.g.ncell;
+  const int64_t x0 = (int64_t)blockIdx.x * 64;
+  const int64_t other = blockIdx.y;
+  const int fld = blockIdx.z;
+  const int N = axis == 1 ? (int)n1 : (int)a.g.n2;
+  const int64_t stride = axis == 1 ? n0 : n0 * n1;
+  const int64_t tb = axis == 1 ? x0 + other * n0 * n1 : x0 + other * n0;  // first column
+  const int64_t rem = ncell - tb;                                          // elements to the end
+  const bool live = x0 + tx < n0;
+  const int s = g * M;
+  const int cnt = s >= N ? 0 : (N - s < M ? N - s : M);
+  const double al = a.alpha, ic = a.inv_c;
+  const int slot = g * 64 + tx;
+
+  double r[M];
+  if (MODE == SW_DIV) {
+    // D.u at (x, line position, other): one-cell forward differences, the
+    // x neighbour through a row-based column with a wrapped lane offset, the
+    // sweep-axis neighbour at the wrapped position, the third axis through
+    // the next plane's column.
+    constexpr int SZ = sizeof(T);
+    const int64_t rowb = tb - x0;
+    const int xn = (int)((x0 + tx + 1) % n0);
+    const Col<T> ua(a.u[0] + tb, rem * SZ, tx, stride);
+    const Col<T> ub(a.u[0] + rowb, (ncell - rowb) * SZ, xn, stride);
+    const int nother = axis == 1 ? (int)a.g.n2 : (int)n1;
+    const int64_t onext = (other + 1) % nother;
+    const int64_t tbn = axis == 1 ? x0 + onext * n0 * n1 : x0 + onext * n0;
+    const int la = axis == 1 ? 1 : 2, lb = axis == 1 ? 2 : 1;  // line / other velocity
+    const Col<T> sa(a.u[la] + tb, rem * SZ, tx, stride);
+    const bool has_b = a.dim == 3;
+    const Col<T> oa(a.u[has_b ? lb : 0] + tb, rem * SZ, tx, stride);
+    const Col<T> ob(a.u[has_b ? lb : 0] + tbn, (ncell - tbn) * SZ, tx, stride);
+#pragma unroll
+    for (int q = 0; q < M; q++) {
+      r[q] = 0.0;
+      if (q < cnt) {
+        const int pos = s + q;
+        const int pn = pos + 1 == N ? 0 : pos + 1;
+        double d = (double)ub.ld(pos) - (double)ua.ld(pos) + (double)sa.ld(pn) - (double)sa.ld(pos);
+        if (has_b) d += (double)ob.ld(pos) - (double)oa.ld(pos);
+        r[q] = d;
+      }
+    }
+  } else {
+    const Col<T> cf(a.f[fld] + tb, rem * (int64_t)sizeof(T), tx, stride);
+#pragma unroll
+    for (int q = 0; q < M; q++) r[q] = q < cnt ? (double)cf.ld(s + q) : 0.0;
+  }
+  if (MODE == SW_DIV) {
+    const Col<T> cd(a.divn + tb, rem * (int64_t)sizeof(T), tx, stride);
+#pragma unroll
+    for (int q = 0; q < M; q++)
+      if (q < cnt) {
+        if (live) cd.st(s + q, (T)(r[q] * a.inv_h));
+        r[q] *= a.div_scale;
+      }
+  }
+  double z = 0.0, A = 1.0;
+#pragma unroll
+  for (int q = 0; q < M; q++)
+    if (q < cnt) {
+      z = al * z + r[q] * ic;
+      r[q] = z;
+      A *= al;
+    }
+  sA[slot] = A;
+  sB[slot] = z;
+  __syncthreads();
+  {
+    double Ap = 1.0, Bp = 0.0;
+    for (int h = 0; h < g; h++) {
+      Bp = sA[h * 64 + tx] * Bp + sB[h * 64 + tx];
+      Ap = sA[h * 64 + tx] * Ap;
+    }
+    double At = Ap, Bt = Bp;
+    for (int h = g; h < G; h++) {
+      Bt = sA[h * 64 + tx] * Bt + sB[h * 64 + tx];
+      At = sA[h * 64 + tx] * At;
+    }
+    const double win = Ap * (Bt / (1.0 - At)) + Bp;
+    double pw = al;
+#pragma unroll
+    for (int q = 0; q < M; q++)
+      if (q < cnt) {
+        r[q] += pw * win;
+        pw *= al;
+      }
+  }
+  __syncthreads();
+  double t = 0.0;
+  A = 1.0;
+#pragma unroll
+  for (int q = M - 1; q >= 0; q--)
+    if (q < cnt) {
+      t = al * t + r[q];
+      r[q] = t;
+      A *= al;
+    }
+  sA[slot] = A;
+  sB[slot] = t;
+  __syncthreads();
+  {
+    double As = 1.0, Bs = 0.0;
+    for (int h = G - 1; h > g; h--) {
+      Bs = sA[h * 64 + tx] * Bs + sB[h * 64 + tx];
+      As = sA[h * 64 + tx] * As;
+    }
+    double At = As, Bt = Bs;
+    for (int h = g; h >= 0; h--) {
+      Bt = sA[h * 64 + tx] * Bt + sB[h * 64 + tx];
+      At = sA[h * 64 + tx] * At;
+    }
+    const double xin = As * (Bt / (1.0 - At)) + Bs;
+    double pw = al;
+#pragma unroll
+    for (int q = M - 1; q >= 0; q--)
+      if (q < cnt) {
+        r[q] += pw * xin;
+        pw *= al;
+      }
+  }
+  if (!live) return;
+  const Col<T> cf(a.f[fld] + tb, rem * (int64_t)sizeof(T), tx, stride);
+  if (MODE == SW_PLAIN || MODE == SW_DIV) {
+#pragma unroll
+    for (int q = 0; q < M; q++)
+      if (q < cnt) cf.st(s + q, (T)r[q]);
+  } else if (MODE == SW_FINAL) {
+    const Col<T> cu(a.u[fld] + tb, rem * (int64_t)sizeof(T), tx, stride);
+#pragma unroll
+    for (int q = 0; q < M; q++)
+      if (q < cnt) cu.st(s + q, (T)((double)cu.ld(s + q) + r[q]));
+  } else {  // SW_PFINAL
+    const Col<T> cdn(a.divn + tb, rem * (int64_t)sizeof(T), tx, stride);
+    const Col<T> cdp(a.divp + tb, rem * (int64_t)sizeof(T), tx, stride);
+    const Col<double> cp(a.p + tb, rem * (int64_t)sizeof(double), tx, stride);
+#pragma unroll
+    for (int q = 0; q < M; q++)
+      if (q < cnt) {
+        cf.st(s + q, (T)r[q]);
+        const T dn = cdn.ld(s + q);
+        const double ds = (double)dn + (double)cdp.ld(s + q);
+        cp.st(s + q, cp.ld(s + q) + r[q] - a.half_chi_mu * ds);
+        cdp.st(s + q, dn);
+      }
+  }
 }
 
 }  // namespace ibgm

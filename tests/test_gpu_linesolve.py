@@ -24,7 +24,7 @@ def _cond(diag, off):
     return (abs(diag) + 2 * abs(off)) / (abs(diag) - 2 * abs(off))
 
 
-@pytest.mark.parametrize("shape", [(3, 5, 7), (6, 37, 13), (4, 64, 200), (2, 96, 256),
+@pytest.mark.parametrize("shape", [(3, 5, 7), (6, 37, 13), (4, 64, 200), (2, 96, 256), (80, 6, 66),
                                    (1, 70, 512), (5, 9, 1000)])
 @pytest.mark.parametrize("kind", ["mom", "psi"])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
