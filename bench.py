@@ -41,6 +41,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="approximate CPU budget of the oracle sample")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="also run a plain device copy of MIB MiB (3 times), the reference "
+                         "for scaling hardware byte counters")
     return ap.parse_args()
 
 
@@ -48,14 +51,16 @@ def kernel_bytes(name: str, b: int, ncell: int, dim: int) -> float:
     """Algorithmic HBM bytes of one launch: every grid array the kernel must
     read or write, once (b = bytes per grid value; p is always FP64)."""
     per_cell = {
-        # u, nl, f, psi read; delta, nl written; f cleared; p read
-        "explicit": (5 * dim + 1) * b + 8,
+        # u, nl, psi, p read; delta, nl written (f is read only in the few
+        # tiles the spreading flagged, and not counted)
+        "explicit": (4 * dim + 1) * b + 8,
         # momentum sweeps carry all dim components
         "mom_x_plain": 2 * b * dim, "mom_s_plain": 2 * b * dim,
         "mom_x_final": 3 * b * dim, "mom_s_final": 3 * b * dim,
-        # psi: first sweep reads u and writes div, psi; last reads psi, div
-        # pair, p and writes psi, p, div
-        "psi_x_div": (dim + 2) * b, "psi_s_div": (dim + 2) * b,
+        # D.u^{n+1}: reads u, writes div; psi: the first sweep reads div and
+        # writes psi; the last reads psi, the div pair, p and writes psi, p, div
+        "divergence": (dim + 1) * b,
+        "psi_x_first": 2 * b, "psi_s_first": 2 * b,
         "psi_x_plain": 2 * b, "psi_s_plain": 2 * b,
         "psi_x_pfinal": 5 * b + 16, "psi_s_pfinal": 5 * b + 16,
     }.get(name)
@@ -64,8 +69,8 @@ def kernel_bytes(name: str, b: int, ncell: int, dim: int) -> float:
 
 def step_bytes(b: int, ncell: int, dim: int) -> float:
     mom = (dim - 1) * 2 * b * dim + 3 * b * dim
-    psi = (dim + 2) * b + (dim - 2) * 2 * b + 5 * b + 16
-    return ((5 * dim + 1) * b + 8 + mom + psi) * ncell
+    psi = (dim + 1) * b + 2 * b + (dim - 2) * 2 * b + 5 * b + 16
+    return ((4 * dim + 1) * b + 8 + mom + psi) * ncell
 
 
 def run_gpu(w, precision, steps, warmup):
@@ -147,6 +152,14 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs an MI355X (no GPU visible)", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        src = torch.empty(args.copy_calibration * 2 ** 20 // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     from paper_1305_3976_amd import inputs
     w = inputs.config_shell_256(steps=args.steps, n=args.n, npts=args.points)
     ncell = w.n[0] * w.n[1] * w.n[2]

@@ -48,13 +48,13 @@ extern "C" const char *ib_last_error(void) { return g_err.c_str(); }
 enum KernelId {
   KP_INTERP_EVOLVE = 0, KP_FORCE, KP_SPREAD, KP_EXPLICIT, KP_DIVERGENCE,
   KP_MOM_X_PLAIN, KP_MOM_S_PLAIN, KP_MOM_X_FINAL, KP_MOM_S_FINAL,
-  KP_PSI_X_DIV, KP_PSI_S_DIV, KP_PSI_X_PLAIN, KP_PSI_S_PLAIN,
+  KP_PSI_X_FIRST, KP_PSI_S_FIRST, KP_PSI_X_PLAIN, KP_PSI_S_PLAIN,
   KP_PSI_X_PFINAL, KP_PSI_S_PFINAL, KP_LINE_X, KP_LINE_S, KP_INTERP, KP_SORT, KP_COUNT
 };
 static const char *kKernelNames[KP_COUNT] = {
     "interp_evolve", "force", "spread", "explicit", "divergence",
     "mom_x_plain", "mom_s_plain", "mom_x_final", "mom_s_final",
-    "psi_x_div", "psi_s_div", "psi_x_plain", "psi_s_plain",
+    "psi_x_first", "psi_s_first", "psi_x_plain", "psi_s_plain",
     "psi_x_pfinal", "psi_s_pfinal", "line_x", "line_s", "interp", "spread_sort"};
 
 struct PendingEvent {
@@ -81,7 +81,8 @@ struct ib_ctx {
   // spreading tiles
   TileGrid tg;
   int *t_count, *t_start, *t_flag, *t_bsum, *t_list, *t_nlist, *tile_of, *rank_of;
-  double *Xs, *Fs, *ws;
+  int *st_base;
+  void *st_wt, *st_val;
   // structure (library allocation)
   int32_t *ptr, *nbr;
   double *kap, *l0, *w;
@@ -168,14 +169,14 @@ static ib_status factor(double d, double e, double *alpha, double *inv_c) {
 
 // ----------------------------------------------------------- sweeps --
 
+// Elements per lane of an x line: the smallest supported chunk that fits the
+// line into 32 lanes, so a wave carries two lines (two loads in flight and
+// two independent scans).
 static int x_chunk(int64_t N) {
-  if (N <= 64) return 1;
-  if (N <= 128) return 2;
-  if (N <= 192) return 3;
-  if (N <= 256) return 4;
-  if (N <= 384) return 6;
-  if (N <= 512) return 8;
-  return 16;
+  static const int ms[] = {1, 2, 4, 6, 8, 12, 16, 32};
+  for (int m : ms)
+    if ((N + m - 1) / m <= 32) return m;
+  return 32;
 }
 static int next_pow2(int v) {
   int p = 1;
@@ -200,6 +201,7 @@ static bool x_vectorizable(const SweepArgs<T> &a, int nf, int M) {
     return false;
   for (int i = 0; i < nf; i++) {
     if (!aligned16(a.f[i])) return false;
+    if (MODE == SW_PLAIN && !aligned16(a.o[i])) return false;
     if (MODE == SW_FINAL && !aligned16(a.u[i])) return false;
   }
   if (MODE == SW_PFINAL && !(aligned16(a.divn) && aligned16(a.divp) && aligned16(a.p)))
@@ -226,15 +228,17 @@ static void dispatch_x(SweepArgs<T> a, int nf, hipStream_t st) {
   switch (M) {
     case 1: go_x_any<T, 1, MODE>(a, nf, st); break;
     case 2: go_x_any<T, 2, MODE>(a, nf, st); break;
-    case 3: go_x_any<T, 3, MODE>(a, nf, st); break;
     case 4: go_x_any<T, 4, MODE>(a, nf, st); break;
     case 6: go_x_any<T, 6, MODE>(a, nf, st); break;
     case 8: go_x_any<T, 8, MODE>(a, nf, st); break;
-    default: go_x_any<T, 16, MODE>(a, nf, st); break;
+    case 12: go_x_any<T, 12, MODE>(a, nf, st); break;
+    case 16: go_x_any<T, 16, MODE>(a, nf, st); break;
+    default: go_x_any<T, 32, MODE>(a, nf, st); break;
   }
 }
 
-// Strided lines: chunks of 32 elements (8 for lines of at most 64), TX
+// Strided lines (fallback for short lines or grids too large for 32-bit
+// buffer offsets): chunks of 32 elements (8 for lines of at most 64), TX
 // consecutive x per block row, ceil(N/M) rows; launch bound by block size.
 template <typename T, int M, int MODE, int LB>
 static void go_s(SweepArgs<T> a, int axis, int nf, int TX, hipStream_t st) {
@@ -245,48 +249,56 @@ static void go_s(SweepArgs<T> a, int axis, int nf, int TX, hipStream_t st) {
   hipLaunchKernelGGL((k_sweep_s<T, M, MODE, LB>), grid, dim3(TX, G), 0, st, a, axis);
 }
 
-// Chunk length of the buffer-addressed strided sweep (16 or 32 line elements
-// per thread); IBGM_S_CHUNK overrides the default for tuning runs.
-static int s_chunk_choice() {
-  static int v = -1;
-  if (v < 0) {
-    const char *e = getenv("IBGM_S_CHUNK");
-    v = (e && atoi(e) == 32) ? 32 : 16;
-  }
-  return v;
+// Chunk length (16 or 32 line elements per thread) and row width (32 or 64
+// columns) of the buffer-addressed strided sweep.  Defaults: chunk 16; rows
+// of 64 for FP32 recurrences and of 32 for FP64 ones (whose larger register
+// footprint otherwise leaves one block per compute unit).  IBGM_S_CHUNK and
+// IBGM_S_TX override them for tuning runs.
+static int env_choice(const char *name, int a, int b, int dflt) {
+  const char *e = getenv(name);
+  if (!e) return dflt;
+  const int v = atoi(e);
+  return v == a ? a : (v == b ? b : dflt);
 }
 
-template <typename T, int M, int MODE, int LB>
+template <typename T, typename R, int M, int MODE, int LB, int TX>
 static void go_sb(SweepArgs<T> a, int axis, int nf, hipStream_t st) {
   const int64_t N = axis == 1 ? a.g.n1 : a.g.n2;
   const int G = (int)((N + M - 1) / M);
   const int64_t other = axis == 1 ? a.g.n2 : a.g.n1;
-  dim3 grid((unsigned)((a.g.n0 + 63) / 64), (unsigned)other, nf);
-  hipLaunchKernelGGL((k_sweep_sb<T, M, MODE, LB>), grid, dim3(64, G), 0, st, a, axis);
+  dim3 grid((unsigned)((a.g.n0 + TX - 1) / TX), (unsigned)other, nf);
+  hipLaunchKernelGGL((k_sweep_sb<T, R, M, MODE, LB, TX>), grid, dim3(TX, G), 0, st, a, axis);
 }
 
-template <typename T, int MODE>
+template <typename T, typename R, int M, int MODE, int TX>
+static bool go_sb_fit(SweepArgs<T> a, int axis, int nf, hipStream_t st) {
+  const int64_t N = axis == 1 ? a.g.n1 : a.g.n2;
+  const int threads = TX * (int)((N + M - 1) / M);
+  if (threads <= 256) go_sb<T, R, M, MODE, 256, TX>(a, axis, nf, st);
+  else if (threads <= 512) go_sb<T, R, M, MODE, 512, TX>(a, axis, nf, st);
+  else if (threads <= 1024) go_sb<T, R, M, MODE, 1024, TX>(a, axis, nf, st);
+  else return false;
+  return true;
+}
+
+template <typename T, int MODE, typename R>
 static void dispatch_s(SweepArgs<T> a, int axis, int nf, hipStream_t st) {
   const int64_t N = axis == 1 ? a.g.n1 : a.g.n2;
   const int64_t stride = axis == 1 ? a.g.n0 : a.g.n0 * a.g.n1;
-  const bool buf_ok = MODE != SW_DIV && N >= 64 && N <= 512 && a.g.n0 >= 64 &&
+  const bool buf_ok = N >= 64 && N <= 1024 && a.g.n0 >= 64 &&
                       ((N - 1) * stride + 64) * (int64_t)sizeof(double) < 0x7fffffff;
   if (buf_ok) {
-    const int M = s_chunk_choice();
-    const int threads = 64 * (int)((N + M - 1) / M);
-    if constexpr (MODE != SW_DIV) {
-      if (M == 16) {
-        if (threads <= 512) go_sb<T, 16, MODE, 512>(a, axis, nf, st);
-        else if (threads <= 1024) go_sb<T, 16, MODE, 1024>(a, axis, nf, st);
-        else go_sb<T, 32, MODE, 1024>(a, axis, nf, st);
-        return;
-      }
-    }
-    {
-      if (threads <= 512) go_sb<T, 32, MODE, 512>(a, axis, nf, st);
-      else go_sb<T, 32, MODE, 1024>(a, axis, nf, st);
-    }
-    return;
+    const int M = env_choice("IBGM_S_CHUNK", 16, 32, 16);
+    const int TX = env_choice("IBGM_S_TX", 32, 64, sizeof(R) == 8 ? 32 : 64);
+    bool ok;
+    if (M == 16)
+      ok = TX == 32 ? go_sb_fit<T, R, 16, MODE, 32>(a, axis, nf, st)
+                    : go_sb_fit<T, R, 16, MODE, 64>(a, axis, nf, st);
+    else
+      ok = TX == 32 ? go_sb_fit<T, R, 32, MODE, 32>(a, axis, nf, st)
+                    : go_sb_fit<T, R, 32, MODE, 64>(a, axis, nf, st);
+    if (ok) return;
+    if (go_sb_fit<T, R, 32, MODE, 32>(a, axis, nf, st)) return;
   }
   const int TX = a.g.n0 >= 32 ? 32 : (a.g.n0 >= 16 ? 16 : 8);
   if (N <= 64) {
@@ -302,13 +314,13 @@ static void dispatch_s(SweepArgs<T> a, int axis, int nf, hipStream_t st) {
 }
 
 // Launch one sweep along `axis`; `id_x` / `id_s` name it for profiling (the
-// strided id is id_x + 1).
-template <typename T, int MODE>
+// strided id is id_x + 1).  R is the recurrence type of the strided kernel.
+template <typename T, int MODE, typename R = double>
 static void sweep(ib_ctx *c, int id_x, SweepArgs<T> a, int axis, int nf, hipStream_t st) {
   if (axis == 0)
     launch(c, id_x, [&] { dispatch_x<T, MODE>(a, nf, st); });
   else
-    launch(c, id_x + 1, [&] { dispatch_s<T, MODE>(a, axis, nf, st); });
+    launch(c, id_x + 1, [&] { dispatch_s<T, MODE, R>(a, axis, nf, st); });
 }
 
 // ------------------------------------------------------------ validation --
@@ -344,10 +356,11 @@ static TileGrid tile_grid(const ib_grid_params *p) {
   return tg;
 }
 
-// Workspace: delta[3], f[3], div_new (grid dtype); X^{n+1}, X^{n+1/2}, F and
-// the sorted copies of X^{n+1/2}, F (FP64 [dim][np]) and w (FP64 [np]); the
-// spreading tile tables (counts, starts, flags, touched list, block sums),
-// the point sort (tile, rank); the touched-list length; one status word.
+// Workspace: delta[3], f[3], div_new (grid dtype); X^{n+1}, X^{n+1/2}, F
+// (FP64 [dim][np]); the per-point stencils in sorted order (start cells, 4
+// weights per component and axis, spread values); the spreading tile tables
+// (counts, flags, touched list, starts, block sums), the point sort (tile,
+// rank); the touched-list length; one status word.
 static size_t workspace_bytes(const ib_grid_params *p, int64_t np) {
   const size_t nc = (size_t)p->n[0] * p->n[1] * p->n[2];
   const size_t t = p->precision == IB_PREC_MIXED ? 4 : 8;
@@ -355,9 +368,10 @@ static size_t workspace_bytes(const ib_grid_params *p, int64_t np) {
   const size_t lag = sizeof(double) * (size_t)p->dim * npp;
   const TileGrid tg = tile_grid(p);
   const size_t nb = (size_t)((tg.ntiles + SCAN_TILE - 1) / SCAN_TILE);
-  return 7 * align256(nc * t) + 5 * align256(lag) + align256(sizeof(double) * npp) +
-         3 * align256(sizeof(int) * tg.ntiles) + align256(sizeof(int) * (tg.ntiles + 1)) +
-         align256(sizeof(int) * nb) + 2 * align256(sizeof(int) * npp) + 256 + 256;
+  return 7 * align256(nc * t) + 3 * align256(lag) + align256(sizeof(int) * 9 * npp) +
+         align256(t * 36 * npp) + align256(t * 3 * npp) + 3 * align256(sizeof(int) * tg.ntiles) +
+         align256(sizeof(int) * (tg.ntiles + 1)) + align256(sizeof(int) * nb) +
+         2 * align256(sizeof(int) * npp) + 256 + 256;
 }
 
 extern "C" ib_status ib_workspace_size(const ib_grid_params *prm, int64_t n_points,
@@ -437,9 +451,11 @@ static void launch_spread(ib_ctx *c, const double *X, const double *F, const dou
     hipLaunchKernelGGL(k_scan_write, dim3(nb), dim3(256), 0, c->stream, c->t_count,
                        c->t_start, c->t_bsum, c->tg.ntiles);
   });
+  Stencils<T> stn{c->st_base, (T *)c->st_wt, (T *)c->st_val};
+  const double inv_hd = 1.0 / std::pow(c->prm.h, DIM);
   launch(c, KP_SORT, [&] {
-    hipLaunchKernelGGL((k_scatter<DIM>), dim3(pb), dim3(256), 0, c->stream, c->tile_of,
-                       c->rank_of, c->t_start, X, F, w, c->Xs, c->Fs, c->ws, np);
+    hipLaunchKernelGGL((k_scatter<T, DIM>), dim3(pb), dim3(256), 0, c->stream, c->tile_of,
+                       c->rank_of, c->t_start, X, F, w, stn, c->g, inv_h, inv_hd, np);
   });
   launch(c, KP_SORT, [&] {
     hipLaunchKernelGGL((k_touch<DIM>), dim3((unsigned)((c->tg.ntiles + 255) / 256)), dim3(256),
@@ -447,9 +463,7 @@ static void launch_spread(ib_ctx *c, const double *X, const double *F, const dou
                        c->t_nlist, c->g, c->tg);
   });
   SpreadArgs<T, DIM> a{};
-  a.Xs = c->Xs;
-  a.Fs = c->Fs;
-  a.ws = c->ws;
+  a.st = stn;
   for (int i = 0; i < 3; i++) a.f[i] = (T *)(i < DIM ? f[i] : nullptr);
   a.start = c->t_start;
   a.list = c->t_list;
@@ -457,8 +471,6 @@ static void launch_spread(ib_ctx *c, const double *X, const double *F, const dou
   a.np = np;
   a.g = c->g;
   a.tg = c->tg;
-  a.inv_h = inv_h;
-  a.inv_hd = 1.0 / std::pow(c->prm.h, DIM);
   const unsigned grid = (unsigned)std::min<int64_t>(c->tg.ntiles, 4096);
   launch(c, KP_SPREAD, [&] {
     hipLaunchKernelGGL((k_spread_tiles<T, DIM, ADD>), dim3(grid), dim3(256), 0, c->stream, a);
@@ -486,6 +498,15 @@ static void launch_explicit(ib_ctx *c, bool first) {
   a.inv_rho = 1.0 / c->prm.rho;
   a.first = first;
   a.advect = !(c->prm.flags & IB_FLAG_NO_ADVECTION);
+  if constexpr (DIM == 3) {
+    if (c->g.n0 % EX == 0 && c->g.n1 % EY == 0) {
+      const dim3 grid(c->g.n0 / EX, c->g.n1 / EY, (c->g.n2 + EZ - 1) / EZ);
+      launch(c, KP_EXPLICIT, [&] {
+        hipLaunchKernelGGL((k_explicit3<T>), grid, dim3(EX * EY), 0, c->stream, a);
+      });
+      return;
+    }
+  }
   launch(c, KP_EXPLICIT, [&] {
     hipLaunchKernelGGL((k_explicit<T, DIM>), dim3((unsigned)((c->g.ncell + 255) / 256)),
                        dim3(256), 0, c->stream, a);
@@ -519,36 +540,40 @@ static void enqueue_step(ib_ctx *c) {
   int order[3];
   const int shift = c->prm.rotate_split ? (int)(n % DIM) : 0;
   for (int s = 0; s < DIM; s++) order[s] = (s + shift) % DIM;
-  // Steps 3c-3d (+z): delta form (1 - nu D_aa) d_a = d_{a-1}, u += d_last
+  // Steps 3c-3d (+z): delta form (1 - nu D_aa) d_a = d_{a-1}, u += d_last;
+  // the momentum systems are well conditioned (|alpha| well below 1), so
+  // their strided recurrences run in the storage precision
   SweepArgs<T> m{};
   m.g = c->g;
   m.dim = DIM;
   m.alpha = c->mom_alpha;
   m.inv_c = c->mom_invc;
   for (int i = 0; i < 3; i++) {
-    m.f[i] = (T *)(i < DIM ? c->delta[i] : nullptr);
+    m.f[i] = m.o[i] = (T *)(i < DIM ? c->delta[i] : nullptr);
     m.u[i] = (T *)(i < DIM ? c->buf.u[i] : nullptr);
   }
   for (int s = 0; s < DIM; s++) {
-    if (s < DIM - 1) sweep<T, SW_PLAIN>(c, KP_MOM_X_PLAIN, m, order[s], DIM, c->stream);
-    else sweep<T, SW_FINAL>(c, KP_MOM_X_FINAL, m, order[s], DIM, c->stream);
+    if (s < DIM - 1) sweep<T, SW_PLAIN, T>(c, KP_MOM_X_PLAIN, m, order[s], DIM, c->stream);
+    else sweep<T, SW_FINAL, T>(c, KP_MOM_X_FINAL, m, order[s], DIM, c->stream);
   }
-  // Step 3e-3f: psi sweeps, the first forming -(rho/dt) D.u^{n+1}, the last
-  // updating p
+  // Steps 3e-3f: D.u^{n+1} into div_new, then the psi sweeps: the first
+  // solves for -(rho/dt) div_new (the scale rides on 1/c) into psi, the last
+  // also updates p and hands div_new to div_prev
+  launch_divergence<T, DIM>(c, c->divn);
   SweepArgs<T> q{};
   q.g = c->g;
   q.dim = DIM;
   q.alpha = c->psi_alpha;
+  q.inv_c = c->psi_invc * (-c->prm.rho / c->prm.dt);
+  q.f[0] = (T *)c->divn;
+  q.o[0] = (T *)c->buf.psi;
+  sweep<T, SW_PLAIN>(c, KP_PSI_X_FIRST, q, order[0], 1, c->stream);
   q.inv_c = c->psi_invc;
-  q.f[0] = (T *)c->buf.psi;
-  for (int i = 0; i < 3; i++) q.u[i] = (T *)(i < DIM ? c->buf.u[i] : nullptr);
+  q.f[0] = q.o[0] = (T *)c->buf.psi;
   q.divn = (T *)c->divn;
   q.divp = (T *)c->buf.div_prev;
   q.p = c->buf.p;
-  q.inv_h = 1.0 / c->prm.h;
-  q.div_scale = -(c->prm.rho / c->prm.dt) / c->prm.h;
   q.half_chi_mu = 0.5 * c->prm.chi * c->prm.mu;
-  sweep<T, SW_DIV>(c, KP_PSI_X_DIV, q, order[0], 1, c->stream);
   for (int s = 1; s < DIM - 1; s++) sweep<T, SW_PLAIN>(c, KP_PSI_X_PLAIN, q, order[s], 1, c->stream);
   sweep<T, SW_PFINAL>(c, KP_PSI_X_PFINAL, q, order[DIM - 1], 1, c->stream);
   c->step = n + 1;
@@ -639,9 +664,9 @@ extern "C" ib_status ib_init(ib_ctx **out, const ib_grid_params *prm, const ib_b
   c->tg = tile_grid(prm);
   const size_t tb = align256(sizeof(int) * c->tg.ntiles);
   const size_t pb = align256(sizeof(int) * np);
-  c->Xs = (double *)w; w += lb;
-  c->Fs = (double *)w; w += lb;
-  c->ws = (double *)w; w += align256(sizeof(double) * np);
+  c->st_base = (int *)w; w += align256(sizeof(int) * 9 * np);
+  c->st_wt = w; w += align256(c->tsz * 36 * np);
+  c->st_val = w; w += align256(c->tsz * 3 * np);
   c->t_count = (int *)w; w += tb;
   c->t_flag = (int *)w; w += tb;
   c->t_list = (int *)w; w += tb;
@@ -795,12 +820,12 @@ extern "C" ib_status ib_line_solve(void *data, int32_t dtype, const int32_t n[3]
     if (dtype == IB_F64) {
       SweepArgs<double> a{};
       a.g = g; a.alpha = al; a.inv_c = ic;
-      for (int i = 0; i < nf; i++) a.f[i] = (double *)data + (f0 + i) * field_stride;
+      for (int i = 0; i < nf; i++) a.f[i] = a.o[i] = (double *)data + (f0 + i) * field_stride;
       sweep<double, SW_PLAIN>(nullptr, KP_LINE_X, a, axis, nf, st);
     } else {
       SweepArgs<float> a{};
       a.g = g; a.alpha = al; a.inv_c = ic;
-      for (int i = 0; i < nf; i++) a.f[i] = (float *)data + (f0 + i) * field_stride;
+      for (int i = 0; i < nf; i++) a.f[i] = a.o[i] = (float *)data + (f0 + i) * field_stride;
       sweep<float, SW_PLAIN>(nullptr, KP_LINE_X, a, axis, nf, st);
     }
   }

@@ -84,11 +84,14 @@ __device__ __forceinline__ Aff readlane_aff(Aff f, int lane) {
   return {__hiloint2double(ahi, alo), __hiloint2double(bhi, blo)};
 }
 
-// Over the 64 lanes of a wave, lane l holding chunk l's map: the composite of
-// the chunks before l (chunk 0 acting first) and of all 64.  Row-local
-// Hillis-Steele steps use DPP row shifts; the four row totals are read back
-// with readlane and chained.  Requires all 64 lanes active.
-__device__ __forceinline__ void wave_prefix64(Aff f, Aff &excl, Aff &tot) {
+// Over segments of SEG = 64 or 32 lanes (a wave holds 64/SEG independent
+// lines), lane l holding chunk l's map: the composite of the chunks before l
+// in its segment (the segment's first chunk acting first) and of the whole
+// segment.  Row-local Hillis-Steele steps use DPP row shifts; the 16-lane
+// row totals are read back with readlane and chained.  Requires all 64
+// lanes active.
+template <int SEG>
+__device__ __forceinline__ void wave_prefix(Aff f, Aff &excl, Aff &tot) {
   Aff x = f;
   x = after(dpp_aff<0x111>(x), x);
   x = after(dpp_aff<0x112>(x), x);
@@ -96,17 +99,25 @@ __device__ __forceinline__ void wave_prefix64(Aff f, Aff &excl, Aff &tot) {
   x = after(dpp_aff<0x118>(x), x);
   const Aff r0 = readlane_aff(x, 15), r1 = readlane_aff(x, 31), r2 = readlane_aff(x, 47),
             r3 = readlane_aff(x, 63);
-  const Aff p1 = r0, p2 = after(r0, r1), p3 = after(p2, r2);
-  tot = after(p3, r3);
   const Aff e = dpp_aff<0x111>(x);  // exclusive within the row
   const int row = __lane_id() >> 4;
-  const Aff pr = row == 0 ? Aff{1.0, 0.0} : (row == 1 ? p1 : (row == 2 ? p2 : p3));
+  Aff pr;
+  if (SEG == 64) {
+    const Aff p2 = after(r0, r1), p3 = after(p2, r2);
+    tot = after(p3, r3);
+    pr = row == 0 ? Aff{1.0, 0.0} : (row == 1 ? r0 : (row == 2 ? p2 : p3));
+  } else {
+    const bool hi = row >= 2;
+    tot = hi ? after(r2, r3) : after(r0, r1);
+    pr = (row & 1) == 0 ? Aff{1.0, 0.0} : (hi ? r2 : r0);
+  }
   excl = after(pr, e);
 }
 
-// Mirror image for maps acting right to left (chunk 63 first): the composite
-// of the chunks after l, and of all 64.
-__device__ __forceinline__ void wave_suffix64(Aff f, Aff &excl, Aff &tot) {
+// Mirror image for maps acting right to left (the segment's last chunk
+// first): the composite of the chunks after l in its segment, and of all.
+template <int SEG>
+__device__ __forceinline__ void wave_suffix(Aff f, Aff &excl, Aff &tot) {
   Aff x = f;
   x = after(dpp_aff<0x101>(x), x);
   x = after(dpp_aff<0x102>(x), x);
@@ -114,11 +125,18 @@ __device__ __forceinline__ void wave_suffix64(Aff f, Aff &excl, Aff &tot) {
   x = after(dpp_aff<0x108>(x), x);
   const Aff t0 = readlane_aff(x, 0), t1 = readlane_aff(x, 16), t2 = readlane_aff(x, 32),
             t3 = readlane_aff(x, 48);
-  const Aff q2 = t3, q1 = after(t3, t2), q0 = after(q1, t1);
-  tot = after(q0, t0);
   const Aff e = dpp_aff<0x101>(x);  // exclusive within the row
   const int row = __lane_id() >> 4;
-  const Aff qr = row == 3 ? Aff{1.0, 0.0} : (row == 2 ? q2 : (row == 1 ? q1 : q0));
+  Aff qr;
+  if (SEG == 64) {
+    const Aff q1 = after(t3, t2), q0 = after(q1, t1);
+    tot = after(q0, t0);
+    qr = row == 3 ? Aff{1.0, 0.0} : (row == 2 ? t3 : (row == 1 ? q1 : q0));
+  } else {
+    const bool hi = row >= 2;
+    tot = hi ? after(t3, t2) : after(t1, t0);
+    qr = (row & 1) == 1 ? Aff{1.0, 0.0} : (hi ? t3 : t1);
+  }
   excl = after(qr, e);
 }
 
@@ -363,21 +381,39 @@ __global__ void __launch_bounds__(256) k_scan_write(int *count, int *start, cons
   if (b < ntiles && b + 4 >= ntiles) start[ntiles] = run;
 }
 
-// Place every point at its sorted slot and gather its position, force and
-// weight there, so that a tile reads its points contiguously.
-template <int DIM>
+// Place every point at its sorted slot and precompute its stencil there:
+// for each component c and axis, the wrapped start cell and the 4 weights,
+// and the spread value F_c w / h^d -- computed once per point, read by every
+// tile the point reaches.
+template <typename T>
+struct Stencils {
+  int *base;  // [(c*3 + ax) * np + slot]
+  T *wt;      // [((c*3 + ax) * 4 + t) * np + slot]
+  T *val;     // [c * np + slot]
+};
+
+template <typename T, int DIM>
 __global__ void __launch_bounds__(256) k_scatter(const int *tile_of, const int *rank_of,
                                                   const int *start, const double *X,
-                                                  const double *F, const double *w, double *Xs,
-                                                  double *Fs, double *ws, int64_t np) {
+                                                  const double *F, const double *w,
+                                                  Stencils<T> st, Grid g, double inv_h,
+                                                  double inv_hd, int64_t np) {
+  using C = T;
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= np) return;
   const int64_t d = start[tile_of[k]] + rank_of[k];
+  const int32_t nn[3] = {g.n0, g.n1, g.n2};
+  double xk[DIM];
+  for (int ax = 0; ax < DIM; ax++) xk[ax] = X[ax * np + k];
+  const double wk = w[k] * inv_hd;
   for (int c = 0; c < DIM; c++) {
-    Xs[c * np + d] = X[c * np + k];
-    Fs[c * np + d] = F[c * np + k];
+    for (int ax = 0; ax < DIM; ax++) {
+      C wt[4];
+      st.base[(c * 3 + ax) * np + d] = axis_stencil<C>(xk[ax], inv_h, ax == c ? 0.0 : 0.5, nn[ax], wt);
+      for (int t = 0; t < 4; t++) st.wt[((c * 3 + ax) * 4 + t) * np + d] = wt[t];
+    }
+    st.val[c * np + d] = (T)(F[c * np + k] * wk);
   }
-  ws[d] = w[k];
 }
 
 // Tiles whose cells lie within 4 cells above an anchor tile, per axis: the
@@ -426,13 +462,12 @@ __global__ void __launch_bounds__(256) k_touch(const int *start, int *flag, int 
 
 template <typename T, int DIM>
 struct SpreadArgs {
-  const double *Xs, *Fs, *ws;  // points in sorted order
+  Stencils<T> st;  // points in sorted order
   T *f[3];
   const int *start, *list, *nlist;
   int64_t np;
   Grid g;
   TileGrid tg;
-  double inv_h, inv_hd;
 };
 
 // Workgroups loop over the touched tiles (a bounded loop: at most ntiles
@@ -441,7 +476,6 @@ struct SpreadArgs {
 template <typename T, int DIM, bool ADD>
 __global__ void __launch_bounds__(256) k_spread_tiles(SpreadArgs<T, DIM> a) {
   using C = T;
-  constexpr int ROWS = DIM == 3 ? 16 : 4;
   constexpr int CELLS = DIM == 3 ? TS * TS * TS : TS * TS;
   __shared__ C acc[DIM][CELLS];
   __shared__ int c_start[27], c_pref[28], s_list[3][3], s_len[3], s_cnt[27];
@@ -491,36 +525,60 @@ __global__ void __launch_bounds__(256) k_spread_tiles(SpreadArgs<T, DIM> a) {
       c_pref[ncomb] = pref;
     }
     __syncthreads();
-    const int items = c_pref[ncomb] * ROWS;
-    for (int it = threadIdx.x; it < items; it += blockDim.x) {
-      const int pi = it / ROWS, row = it % ROWS;
+    // one thread per candidate point; only the stencil rows and columns that
+    // fall inside the tile are visited
+    const int npts = c_pref[ncomb];
+    const int64_t np = a.np;
+    for (int pi = threadIdx.x; pi < npts; pi += blockDim.x) {
       int slot = 0;
       while (c_pref[slot + 1] <= pi) slot++;
       const int64_t k = c_start[slot] + (pi - c_pref[slot]);
-      const int t1 = row & 3, t2 = row >> 2;
-      double xk[DIM];
-      for (int ax = 0; ax < DIM; ax++) xk[ax] = a.Xs[ax * a.np + k];
-      const double wk = a.ws[k] * a.inv_hd;
       for (int c = 0; c < DIM; c++) {
-        C w0[4], w1[4], w2[4];
-        int jj = axis_stencil<C>(xk[1], a.inv_h, c == 1 ? 0.0 : 0.5, nn[1], w1) + t1;
-        jj -= jj >= nn[1] ? nn[1] : 0;
-        if (jj < lo[1] || jj >= hi[1]) continue;
-        C rw = w1[t1];
-        int kk = 0;
-        if (DIM == 3) {
-          kk = axis_stencil<C>(xk[2], a.inv_h, c == 2 ? 0.0 : 0.5, nn[2], w2) + t2;
-          kk -= kk >= nn[2] ? nn[2] : 0;
-          if (kk < lo[2] || kk >= hi[2]) continue;
-          rw *= w2[t2];
+        int b[3], tlo[3], thi[3];
+        bool any = true;
+        for (int ax = 0; ax < 3; ax++) {
+          if (ax >= DIM) {
+            b[ax] = 0;
+            tlo[ax] = 0;
+            thi[ax] = 1;
+            continue;
+          }
+          b[ax] = a.st.base[(c * 3 + ax) * np + k];
+          // stencil offsets t in 0..3 with (b + t) mod n inside [lo, hi)
+          int t0 = 4, t1 = -1;
+          for (int t = 0; t < 4; t++) {
+            int cell = b[ax] + t;
+            cell -= cell >= nn[ax] ? nn[ax] : 0;
+            if (cell >= lo[ax] && cell < hi[ax]) {
+              t0 = t < t0 ? t : t0;
+              t1 = t;
+            }
+          }
+          tlo[ax] = t0;
+          thi[ax] = t1 + 1;
+          any &= t0 <= t1;
         }
-        const int b0 = axis_stencil<C>(xk[0], a.inv_h, c == 0 ? 0.0 : 0.5, nn[0], w0);
-        const C val = (C)(a.Fs[c * a.np + k] * wk) * rw;
-        const int lrow = ((kk - lo[2]) * TS + (jj - lo[1])) * TS;
-        for (int t0 = 0; t0 < 4; t0++) {
-          int ii = b0 + t0;
-          ii -= ii >= nn[0] ? nn[0] : 0;
-          if (ii >= lo[0] && ii < hi[0]) atomicAdd(&acc[c][lrow + ii - lo[0]], val * w0[t0]);
+        if (!any) continue;
+        const C val = a.st.val[c * np + k];
+        for (int t2 = tlo[2]; t2 < thi[2]; t2++) {
+          int kk = 0;
+          C rz = C(1);
+          if (DIM == 3) {
+            kk = b[2] + t2;
+            kk -= kk >= nn[2] ? nn[2] : 0;
+            rz = a.st.wt[((c * 3 + 2) * 4 + t2) * np + k];
+          }
+          for (int t1 = tlo[1]; t1 < thi[1]; t1++) {
+            int jj = b[1] + t1;
+            jj -= jj >= nn[1] ? nn[1] : 0;
+            const C rw = val * rz * a.st.wt[((c * 3 + 1) * 4 + t1) * np + k];
+            const int lrow = ((kk - lo[2]) * TS + (jj - lo[1])) * TS;
+            for (int t0 = tlo[0]; t0 < thi[0]; t0++) {
+              int ii = b[0] + t0;
+              ii -= ii >= nn[0] ? nn[0] : 0;
+              atomicAdd(&acc[c][lrow + ii - lo[0]], rw * a.st.wt[((c * 3 + 0) * 4 + t0) * np + k]);
+            }
+          }
         }
       }
     }
@@ -619,6 +677,108 @@ __global__ void __launch_bounds__(256) k_explicit(ExplicitArgs<T, DIM> a) {
   }
 }
 
+// 3-D explicit step on a 2.5-D blocking: a workgroup owns an EX x EY tile of
+// (x, y) columns and marches KZ planes along z.  Three rotating planes of
+// u, v, w (tile plus a one-cell halo) and the current plane of p* = p + psi
+// (tile plus its -x, -y halo) sit in LDS, so each value is fetched from HBM
+// about once instead of once per stencil use.  Same arithmetic as
+// k_explicit.
+constexpr int EX = 64, EY = 4, EZ = 16;
+constexpr int EW = EX + 2, EH = EY + 2;  // velocity plane with halo
+constexpr int PW = EX + 1, PH = EY + 1;  // p* plane with -x, -y halo
+
+template <typename T>
+__global__ void __launch_bounds__(EX * EY) k_explicit3(ExplicitArgs<T, 3> a) {
+  using C = T;
+  __shared__ C U[3][3][EH * EW];
+  __shared__ double PS[PH * PW];
+  const int n0 = a.g.n0, n1 = a.g.n1, n2 = a.g.n2;
+  const int tx = threadIdx.x % EX, ty = threadIdx.x / EX;
+  const int i0 = blockIdx.x * EX, j0 = blockIdx.y * EY, k0 = blockIdx.z * EZ;
+  const int i = i0 + tx, j = j0 + ty;
+  const int64_t plane = (int64_t)n0 * n1;
+  auto wrap = [](int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); };
+  // load plane kk of u, v, w (tile + halo) into rotating slot sl
+  auto load_vel = [&](int kk, int sl) {
+    const int kw = wrap(kk, n2);
+    for (int e = threadIdx.x; e < EH * EW; e += EX * EY) {
+      const int jl = e / EW, il = e % EW;
+      const int64_t g = (int64_t)kw * plane + (int64_t)wrap(j0 - 1 + jl, n1) * n0 + wrap(i0 - 1 + il, n0);
+      U[0][sl][e] = (C)a.u[0][g];
+      U[1][sl][e] = (C)a.u[1][g];
+      U[2][sl][e] = (C)a.u[2][g];
+    }
+  };
+  auto load_p = [&](int kk) {
+    const int kw = wrap(kk, n2);
+    for (int e = threadIdx.x; e < PH * PW; e += EX * EY) {
+      const int jl = e / PW, il = e % PW;
+      const int64_t g = (int64_t)kw * plane + (int64_t)wrap(j0 - 1 + jl, n1) * n0 + wrap(i0 - 1 + il, n0);
+      PS[e] = a.p[g] + (double)a.psi[g];
+    }
+  };
+  const int tiles_x = (n0 + TS - 1) / TS;
+  const int c = (ty + 1) * EW + (tx + 1);  // this column in a velocity plane
+  load_vel(k0 - 1, 0);
+  load_vel(k0, 1);
+  // p* below the first plane, at this column
+  double ps_below = a.p[(int64_t)wrap(k0 - 1, n2) * plane + (int64_t)j * n0 + i] +
+                    (double)a.psi[(int64_t)wrap(k0 - 1, n2) * plane + (int64_t)j * n0 + i];
+  for (int kz = 0; kz < EZ && k0 + kz < n2; kz++) {
+    const int k = k0 + kz;
+    const int sm = kz % 3, s0 = (kz + 1) % 3, sp = (kz + 2) % 3;
+    load_vel(k + 1, sp);
+    load_p(k);
+    __syncthreads();
+    const int64_t idx = (int64_t)k * plane + (int64_t)j * n0 + i;
+    const int pc = (ty + 1) * PW + (tx + 1);
+    const double ps0 = PS[pc];
+    const double psm[3] = {PS[pc - 1], PS[pc - PW], ps_below};
+    const int64_t tile = i / TS + (int64_t)tiles_x * (j / TS + (int64_t)a.tg.nt[1] * (k / TS));
+    const bool forced = a.flag[tile] != 0;
+    // neighbour offsets within a plane, and the plane slots below / above
+    const int dpl[3] = {1, EW, 0}, sl_m[3] = {s0, s0, sm}, sl_p[3] = {s0, s0, sp};
+#pragma unroll
+    for (int ci = 0; ci < 3; ci++) {
+      const C *Ui = U[ci][s0];
+      const C u0 = Ui[c];
+      C dv = 0, ad = 0, lap = 0;
+#pragma unroll
+      for (int cj = 0; cj < 3; cj++) {
+        // u_ci one cell up / down along axis cj
+        const C up = U[ci][sl_p[cj]][c + dpl[cj]];
+        const C um = U[ci][sl_m[cj]][c - dpl[cj]];
+        lap += up - C(2) * u0 + um;
+        if (!a.advect) continue;
+        if (cj == ci) {
+          const C ap = C(0.5) * (u0 + up), am = C(0.5) * (um + u0);
+          dv += ap * ap - am * am;
+          ad += C(0.5) * (ap * (up - u0) + am * (u0 - um));
+        } else {
+          // u_cj averaged along ci, on the edges at this cell and one up along cj
+          const C *Uj0 = U[cj][sl_m[ci]];  // plane holding "one down along ci"
+          const C *Uj = U[cj][s0];
+          const C *Ujp = U[cj][sl_p[cj]];  // plane holding "one up along cj"
+          const C *Ujpm = U[cj][(ci == 2) ? sm : ((cj == 2) ? sp : s0)];
+          const C Ua = C(0.5) * (Uj0[c - dpl[ci]] + Uj[c]);
+          const C Ub = C(0.5) * (Ujpm[c + dpl[cj] - dpl[ci]] + Ujp[c + dpl[cj]]);
+          dv += Ub * C(0.5) * (u0 + up) - Ua * C(0.5) * (um + u0);
+          ad += C(0.5) * (Ub * (up - u0) + Ua * (u0 - um));
+        }
+      }
+      const C N = C(0.5) * (dv + ad) * (C)a.inv_h;
+      const C gp = (C)((ps0 - psm[ci]) * a.inv_h);
+      const C Nh = a.first ? N : C(1.5) * N - C(0.5) * (C)a.nl[ci][idx];
+      const C fc = forced ? (C)a.f[ci][idx] : C(0);
+      const C d = (C)a.dt * (-Nh + ((C)a.mu * lap * (C)a.inv_h2 - gp + fc) * (C)a.inv_rho);
+      a.delta[ci][idx] = (T)d;
+      a.nl[ci][idx] = (T)N;
+    }
+    ps_below = ps0;
+    __syncthreads();
+  }
+}
+
 // D.u at every cell (used once, to seed div_prev = D.u^0).
 template <typename T, int DIM>
 __global__ void __launch_bounds__(256) k_divergence(const T *u0, const T *u1,
@@ -653,19 +813,17 @@ __global__ void __launch_bounds__(256) k_divergence(const T *u0, const T *u1,
 // Schur-complement partition of a periodic line (Sec. "Linear Solver") with
 // the P x P interface system replaced by the scan of the factored form.
 
-enum { SW_PLAIN = 0, SW_FINAL = 1, SW_DIV = 2, SW_PFINAL = 3 };
+enum { SW_PLAIN = 0, SW_FINAL = 1, SW_PFINAL = 3 };
 
 template <typename T>
 struct SweepArgs {
-  T *f[3];             // per field: rhs in, solution out (PLAIN); rhs (FINAL);
-                       // psi out (DIV); psi in/out (PFINAL)
-  T *u[3];             // FINAL: u += x (per field);  DIV: velocity components
-  T *divn;             // DIV: D.u^{n+1} out;  PFINAL: in
+  T *f[3];             // per field: right-hand side in
+  T *o[3];             // PLAIN: solution out (may alias f)
+  T *u[3];             // FINAL: u += x (per field)
+  T *divn;             // PFINAL: D.u^{n+1} in
   T *divp;             // PFINAL: D.u^n in, D.u^{n+1} out
   double *p;           // PFINAL: p += x - chi mu (divn + divp)/2
-  double alpha, inv_c; // factored-form coefficients
-  double inv_h;        // DIV: D.u = inv_h * (sum of one-cell differences)
-  double div_scale;    // DIV: rhs = -(rho/dt) D.u = div_scale * (sum of differences)
+  double alpha, inv_c; // factored-form coefficients (inv_c may carry a rhs scale)
   double half_chi_mu;  // PFINAL
   Grid g;
   int32_t G;           // threads per line (x kernel: power of two <= 64)
@@ -673,27 +831,10 @@ struct SweepArgs {
 };
 
 template <typename T, int MODE>
-__device__ __forceinline__ double sweep_load(const SweepArgs<T> &a, int fld,
-                                             int64_t idx, int64_t i, int64_t j,
-                                             int64_t k) {
-  if (MODE == SW_DIV) {
-    const int64_t n0 = a.g.n0, n1 = a.g.n1, n2 = a.g.n2;
-    double s = (double)a.u[0][idx + ((i + 1 == n0) ? -(n0 - 1) : 1)] - (double)a.u[0][idx];
-    s += (double)a.u[1][idx + ((j + 1 == n1) ? -(n1 - 1) * n0 : n0)] - (double)a.u[1][idx];
-    if (a.dim == 3)
-      s += (double)a.u[2][idx + ((k + 1 == n2) ? -(n2 - 1) * n0 * n1 : n0 * n1)] -
-           (double)a.u[2][idx];
-    return s;
-  } else {
-    return (double)a.f[fld][idx];
-  }
-}
-
-template <typename T, int MODE>
-__device__ __forceinline__ void sweep_store(const SweepArgs<T> &a, int fld,
-                                            int64_t idx, double x) {
-  if (MODE == SW_PLAIN || MODE == SW_DIV) {
-    a.f[fld][idx] = (T)x;
+__device__ __forceinline__ void sweep_store(const SweepArgs<T> &a, int fld, int64_t idx,
+                                            double x) {
+  if (MODE == SW_PLAIN) {
+    a.o[fld][idx] = (T)x;
   } else if (MODE == SW_FINAL) {
     a.u[fld][idx] = (T)((double)a.u[fld][idx] + x);
   } else {  // SW_PFINAL
@@ -765,25 +906,24 @@ __global__ void __launch_bounds__(256) k_sweep_x(SweepArgs<T> a) {
   const int64_t s = (int64_t)lane * M;
   const int cnt = (int)(s >= N ? 0 : (N - s < M ? N - s : M));
   const int64_t base = line * N;
-  const int64_t jl = line % a.g.n1, kl = line / a.g.n1;
   const double al = a.alpha, ic = a.inv_c;
 
   double r[M];
-  if (VEC && MODE != SW_DIV) {
+  // epilogue operands are fetched together with the right-hand side so the
+  // wave's loads are in flight at once
+  double pre0[VEC && MODE != SW_PLAIN ? M : 1], pre1[VEC && MODE == SW_PFINAL ? M : 1],
+      pre2[VEC && MODE == SW_PFINAL ? M : 1];
+  if (VEC) {
     vload<T, M>(a.f[fld] + base + s, r);
+    if constexpr (VEC && MODE == SW_FINAL) vload<T, M>(a.u[fld] + base + s, pre0);
+    if constexpr (VEC && MODE == SW_PFINAL) {
+      vload<T, M>(a.divn + base + s, pre0);
+      vload<T, M>(a.divp + base + s, pre1);
+      vload<double, M>(a.p + base + s, pre2);
+    }
   } else {
 #pragma unroll
-    for (int q = 0; q < M; q++) {
-      r[q] = 0.0;
-      if (q < cnt) {
-        double v = sweep_load<T, MODE>(a, fld, base + s + q, s + q, jl, kl);
-        if (MODE == SW_DIV) {
-          if (live) a.divn[base + s + q] = (T)(v * a.inv_h);
-          v *= a.div_scale;
-        }
-        r[q] = v;
-      }
-    }
+    for (int q = 0; q < M; q++) r[q] = q < cnt ? (double)a.f[fld][base + s + q] : 0.0;
   }
   // forward recurrence over the chunk from zero
   double z = 0.0, A = 1.0;
@@ -796,9 +936,10 @@ __global__ void __launch_bounds__(256) k_sweep_x(SweepArgs<T> a) {
     }
   double B = z;
   double win;
-  if (G == 64) {
+  if (G == 64 || G == 32) {
     Aff ex, tot;
-    wave_prefix64(Aff{A, B}, ex, tot);
+    if (G == 64) wave_prefix<64>(Aff{A, B}, ex, tot);
+    else wave_prefix<32>(Aff{A, B}, ex, tot);
     win = ex.A * (tot.B / (1.0 - tot.A)) + ex.B;
   } else {
     // inclusive scan of the affine maps (earlier lanes act first)
@@ -839,9 +980,10 @@ __global__ void __launch_bounds__(256) k_sweep_x(SweepArgs<T> a) {
     }
   B = t;
   double xin;
-  if (G == 64) {
+  if (G == 64 || G == 32) {
     Aff ex, tot;
-    wave_suffix64(Aff{A, B}, ex, tot);
+    if (G == 64) wave_suffix<64>(Aff{A, B}, ex, tot);
+    else wave_suffix<32>(Aff{A, B}, ex, tot);
     xin = ex.A * (tot.B / (1.0 - tot.A)) + ex.B;
   } else {
     // suffix scan (later lanes act first)
@@ -873,24 +1015,18 @@ __global__ void __launch_bounds__(256) k_sweep_x(SweepArgs<T> a) {
   if (!live) return;
   if (VEC) {
     const int64_t o = base + s;
-    if (MODE == SW_PLAIN || MODE == SW_DIV) {
-      vstore<T, M>(a.f[fld] + o, r);
-    } else if (MODE == SW_FINAL) {
-      double u[M];
-      vload<T, M>(a.u[fld] + o, u);
+    if (MODE == SW_PLAIN) {
+      vstore<T, M>(a.o[fld] + o, r);
+    } else if constexpr (MODE == SW_FINAL) {
 #pragma unroll
-      for (int q = 0; q < M; q++) u[q] += r[q];
-      vstore<T, M>(a.u[fld] + o, u);
-    } else {  // SW_PFINAL
+      for (int q = 0; q < M; q++) pre0[q] += r[q];
+      vstore<T, M>(a.u[fld] + o, pre0);
+    } else if constexpr (MODE == SW_PFINAL) {
       vstore<T, M>(a.f[fld] + o, r);
-      double dn[M], dp[M], pp[M];
-      vload<T, M>(a.divn + o, dn);
-      vload<T, M>(a.divp + o, dp);
-      vload<double, M>(a.p + o, pp);
 #pragma unroll
-      for (int q = 0; q < M; q++) pp[q] = pp[q] + r[q] - a.half_chi_mu * (dn[q] + dp[q]);
-      vstore<double, M>(a.p + o, pp);
-      vstore<T, M>(a.divp + o, dn);
+      for (int q = 0; q < M; q++) pre2[q] = pre2[q] + r[q] - a.half_chi_mu * (pre0[q] + pre1[q]);
+      vstore<double, M>(a.p + o, pre2);
+      vstore<T, M>(a.divp + o, pre0);
     }
     return;
   }
@@ -925,23 +1061,7 @@ __global__ void __launch_bounds__(LB) k_sweep_s(SweepArgs<T> a, int axis) {
 
   double r[M];
 #pragma unroll
-  for (int q = 0; q < M; q++) {
-    r[q] = 0.0;
-    if (q < cnt) {
-      const int64_t idx = base + q * stride;
-      double v;
-      if (MODE == SW_DIV) {
-        const int64_t pos = s + q;
-        v = sweep_load<T, MODE>(a, fld, idx, xs, axis == 1 ? pos : other,
-                                axis == 1 ? other : pos);
-        if (live) a.divn[idx] = (T)(v * a.inv_h);
-        v *= a.div_scale;
-      } else {
-        v = (double)a.f[fld][idx];
-      }
-      r[q] = v;
-    }
-  }
+  for (int q = 0; q < M; q++) r[q] = q < cnt ? (double)a.f[fld][base + q * stride] : 0.0;
   double z = 0.0, A = 1.0;
 #pragma unroll
   for (int q = 0; q < M; q++)
@@ -1012,9 +1132,10 @@ __global__ void __launch_bounds__(LB) k_sweep_s(SweepArgs<T> a, int axis) {
     if (q < cnt) sweep_store<T, MODE>(a, fld, base + q * stride, r[q]);
 }
 
-// Strided lines through buffer resources.  blockDim = (64, G): a wave is one
-// 64-wide row of x (256 or 512 contiguous bytes per access), threadIdx.y the
-// chunk of M line elements.  Each array is addressed by a buffer resource
+// Strided lines through buffer resources.  blockDim = (TX, G): TX = 64 makes
+// a wave one 64-wide row of x (256 or 512 contiguous bytes per access), TX =
+// 32 halves the block for register-heavy FP64 recurrences; threadIdx.y is
+// the chunk of M line elements.  Each array is addressed by a buffer resource
 // based at the block's first column: the lane offset is one VGPR and the
 // element offset pos * stride a wave-uniform scalar, so no per-element
 // 64-bit addresses are held.  Reads past the end of an array return 0 and
@@ -1052,12 +1173,14 @@ struct Col {
   }
 };
 
-template <typename T, int M, int MODE, int LB>
+// R: recurrence type (double, or float for the benign momentum systems under
+// the mixed policy).
+template <typename T, typename R, int M, int MODE, int LB, int TX>
 __global__ void __launch_bounds__(LB) k_sweep_sb(SweepArgs<T> a, int axis) {
-  __shared__ double sA[LB], sB[LB];
+  __shared__ R sA[LB], sB[LB];
   const int tx = threadIdx.x, g = threadIdx.y, G = blockDim.y;
   const int64_t n0 = a.g.n0, n1 = a.g.n1, ncell = a.g.ncell;
-  const int64_t x0 = (int64_t)blockIdx.x * 64;
+  const int64_t x0 = (int64_t)blockIdx.x * TX;
   const int64_t other = blockIdx.y;
   const int fld = blockIdx.z;
   const int N = axis == 1 ? (int)n1 : (int)a.g.n2;
@@ -1067,54 +1190,36 @@ __global__ void __launch_bounds__(LB) k_sweep_sb(SweepArgs<T> a, int axis) {
   const bool live = x0 + tx < n0;
   const int s = g * M;
   const int cnt = s >= N ? 0 : (N - s < M ? N - s : M);
-  const double al = a.alpha, ic = a.inv_c;
-  const int slot = g * 64 + tx;
+  const R al = (R)a.alpha, ic = (R)a.inv_c;
+  const int slot = g * TX + tx;
 
-  double r[M];
-  if (MODE == SW_DIV) {
-    // D.u at (x, line position, other): one-cell forward differences, the
-    // x neighbour through a row-based column with a wrapped lane offset, the
-    // sweep-axis neighbour at the wrapped position, the third axis through
-    // the next plane's column.
-    constexpr int SZ = sizeof(T);
-    const int64_t rowb = tb - x0;
-    const int xn = (int)((x0 + tx + 1) % n0);
-    const Col<T> ua(a.u[0] + tb, rem * SZ, tx, stride);
-    const Col<T> ub(a.u[0] + rowb, (ncell - rowb) * SZ, xn, stride);
-    const int nother = axis == 1 ? (int)a.g.n2 : (int)n1;
-    const int64_t onext = (other + 1) % nother;
-    const int64_t tbn = axis == 1 ? x0 + onext * n0 * n1 : x0 + onext * n0;
-    const int la = axis == 1 ? 1 : 2, lb = axis == 1 ? 2 : 1;  // line / other velocity
-    const Col<T> sa(a.u[la] + tb, rem * SZ, tx, stride);
-    const bool has_b = a.dim == 3;
-    const Col<T> oa(a.u[has_b ? lb : 0] + tb, rem * SZ, tx, stride);
-    const Col<T> ob(a.u[has_b ? lb : 0] + tbn, (ncell - tbn) * SZ, tx, stride);
-#pragma unroll
-    for (int q = 0; q < M; q++) {
-      r[q] = 0.0;
-      if (q < cnt) {
-        const int pos = s + q;
-        const int pn = pos + 1 == N ? 0 : pos + 1;
-        double d = (double)ub.ld(pos) - (double)ua.ld(pos) + (double)sa.ld(pn) - (double)sa.ld(pos);
-        if (has_b) d += (double)ob.ld(pos) - (double)oa.ld(pos);
-        r[q] = d;
-      }
-    }
-  } else {
+  R r[M];
+  // epilogue operands are fetched together with the right-hand side
+  constexpr int MU = MODE == SW_FINAL ? M : 1, MP = MODE == SW_PFINAL ? M : 1;
+  T pu[MU], pdn[MP], pdp[MP];
+  double pp[MP];
+  {
     const Col<T> cf(a.f[fld] + tb, rem * (int64_t)sizeof(T), tx, stride);
 #pragma unroll
-    for (int q = 0; q < M; q++) r[q] = q < cnt ? (double)cf.ld(s + q) : 0.0;
-  }
-  if (MODE == SW_DIV) {
-    const Col<T> cd(a.divn + tb, rem * (int64_t)sizeof(T), tx, stride);
+    for (int q = 0; q < M; q++) r[q] = q < cnt ? (R)cf.ld(s + q) : R(0);
+    if constexpr (MODE == SW_FINAL) {
+      const Col<T> cu(a.u[fld] + tb, rem * (int64_t)sizeof(T), tx, stride);
 #pragma unroll
-    for (int q = 0; q < M; q++)
-      if (q < cnt) {
-        if (live) cd.st(s + q, (T)(r[q] * a.inv_h));
-        r[q] *= a.div_scale;
+      for (int q = 0; q < M; q++) pu[q] = q < cnt ? cu.ld(s + q) : T(0);
+    }
+    if constexpr (MODE == SW_PFINAL) {
+      const Col<T> cdn(a.divn + tb, rem * (int64_t)sizeof(T), tx, stride);
+      const Col<T> cdp(a.divp + tb, rem * (int64_t)sizeof(T), tx, stride);
+      const Col<double> cp(a.p + tb, rem * (int64_t)sizeof(double), tx, stride);
+#pragma unroll
+      for (int q = 0; q < M; q++) {
+        pdn[q] = q < cnt ? cdn.ld(s + q) : T(0);
+        pdp[q] = q < cnt ? cdp.ld(s + q) : T(0);
+        pp[q] = q < cnt ? cp.ld(s + q) : 0.0;
       }
+    }
   }
-  double z = 0.0, A = 1.0;
+  R z = 0, A = 1;
 #pragma unroll
   for (int q = 0; q < M; q++)
     if (q < cnt) {
@@ -1126,18 +1231,18 @@ __global__ void __launch_bounds__(LB) k_sweep_sb(SweepArgs<T> a, int axis) {
   sB[slot] = z;
   __syncthreads();
   {
-    double Ap = 1.0, Bp = 0.0;
+    R Ap = 1, Bp = 0;
     for (int h = 0; h < g; h++) {
-      Bp = sA[h * 64 + tx] * Bp + sB[h * 64 + tx];
-      Ap = sA[h * 64 + tx] * Ap;
+      Bp = sA[h * TX + tx] * Bp + sB[h * TX + tx];
+      Ap = sA[h * TX + tx] * Ap;
     }
-    double At = Ap, Bt = Bp;
+    R At = Ap, Bt = Bp;
     for (int h = g; h < G; h++) {
-      Bt = sA[h * 64 + tx] * Bt + sB[h * 64 + tx];
-      At = sA[h * 64 + tx] * At;
+      Bt = sA[h * TX + tx] * Bt + sB[h * TX + tx];
+      At = sA[h * TX + tx] * At;
     }
-    const double win = Ap * (Bt / (1.0 - At)) + Bp;
-    double pw = al;
+    const R win = Ap * (Bt / (R(1) - At)) + Bp;
+    R pw = al;
 #pragma unroll
     for (int q = 0; q < M; q++)
       if (q < cnt) {
@@ -1146,8 +1251,8 @@ __global__ void __launch_bounds__(LB) k_sweep_sb(SweepArgs<T> a, int axis) {
       }
   }
   __syncthreads();
-  double t = 0.0;
-  A = 1.0;
+  R t = 0;
+  A = 1;
 #pragma unroll
   for (int q = M - 1; q >= 0; q--)
     if (q < cnt) {
@@ -1159,18 +1264,18 @@ __global__ void __launch_bounds__(LB) k_sweep_sb(SweepArgs<T> a, int axis) {
   sB[slot] = t;
   __syncthreads();
   {
-    double As = 1.0, Bs = 0.0;
+    R As = 1, Bs = 0;
     for (int h = G - 1; h > g; h--) {
-      Bs = sA[h * 64 + tx] * Bs + sB[h * 64 + tx];
-      As = sA[h * 64 + tx] * As;
+      Bs = sA[h * TX + tx] * Bs + sB[h * TX + tx];
+      As = sA[h * TX + tx] * As;
     }
-    double At = As, Bt = Bs;
+    R At = As, Bt = Bs;
     for (int h = g; h >= 0; h--) {
-      Bt = sA[h * 64 + tx] * Bt + sB[h * 64 + tx];
-      At = sA[h * 64 + tx] * At;
+      Bt = sA[h * TX + tx] * Bt + sB[h * TX + tx];
+      At = sA[h * TX + tx] * At;
     }
-    const double xin = As * (Bt / (1.0 - At)) + Bs;
-    double pw = al;
+    const R xin = As * (Bt / (R(1) - At)) + Bs;
+    R pw = al;
 #pragma unroll
     for (int q = M - 1; q >= 0; q--)
       if (q < cnt) {
@@ -1179,28 +1284,26 @@ __global__ void __launch_bounds__(LB) k_sweep_sb(SweepArgs<T> a, int axis) {
       }
   }
   if (!live) return;
-  const Col<T> cf(a.f[fld] + tb, rem * (int64_t)sizeof(T), tx, stride);
-  if (MODE == SW_PLAIN || MODE == SW_DIV) {
+  if (MODE == SW_PLAIN) {
+    const Col<T> co(a.o[fld] + tb, rem * (int64_t)sizeof(T), tx, stride);
 #pragma unroll
     for (int q = 0; q < M; q++)
-      if (q < cnt) cf.st(s + q, (T)r[q]);
-  } else if (MODE == SW_FINAL) {
+      if (q < cnt) co.st(s + q, (T)r[q]);
+  } else if constexpr (MODE == SW_FINAL) {
     const Col<T> cu(a.u[fld] + tb, rem * (int64_t)sizeof(T), tx, stride);
 #pragma unroll
     for (int q = 0; q < M; q++)
-      if (q < cnt) cu.st(s + q, (T)((double)cu.ld(s + q) + r[q]));
-  } else {  // SW_PFINAL
-    const Col<T> cdn(a.divn + tb, rem * (int64_t)sizeof(T), tx, stride);
+      if (q < cnt) cu.st(s + q, (T)((R)pu[q] + r[q]));
+  } else if constexpr (MODE == SW_PFINAL) {
+    const Col<T> cf(a.f[fld] + tb, rem * (int64_t)sizeof(T), tx, stride);
     const Col<T> cdp(a.divp + tb, rem * (int64_t)sizeof(T), tx, stride);
     const Col<double> cp(a.p + tb, rem * (int64_t)sizeof(double), tx, stride);
 #pragma unroll
     for (int q = 0; q < M; q++)
       if (q < cnt) {
         cf.st(s + q, (T)r[q]);
-        const T dn = cdn.ld(s + q);
-        const double ds = (double)dn + (double)cdp.ld(s + q);
-        cp.st(s + q, cp.ld(s + q) + r[q] - a.half_chi_mu * ds);
-        cdp.st(s + q, dn);
+        cp.st(s + q, pp[q] + (double)r[q] - a.half_chi_mu * ((double)pdn[q] + (double)pdp[q]));
+        cdp.st(s + q, pdn[q]);
       }
   }
 }

@@ -105,3 +105,35 @@ def test_nonfinite_position_is_reported():
         g.sync()
     assert ei.value.status == ibgm.IB_E_NONFINITE
     g.close()
+
+
+@pytest.mark.parametrize("precision,tol", [(0, FP64_TOL), (1, MIXED_TOL)])
+def test_shell3d_plane_marching_explicit(precision, tol):
+    """Grid whose x extent is a multiple of 64 and y of 4, so the explicit step
+    runs on the LDS plane-marching kernel; z = 40 leaves a partial z block."""
+    n = (64, 16, 40)
+    h = 1.0 / 64
+    S = inputs.ellipsoid_shell(500, axes=(0.3, 0.08, 0.2), center=(0.5, 0.125, 0.31))
+    # smooth periodic modes on the 1 x 0.25 x 0.625 box (seeded phases)
+    rng = np.random.default_rng(11)
+    x = np.arange(n[0]) * h
+    y = np.arange(n[1]) * h
+    z = np.arange(n[2]) * h
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    u0 = []
+    for c in range(3):
+        f = np.zeros((n[2], n[1], n[0]))
+        for kx, ky, kz in ((1, 4, 1.6), (2, 4, 3.2), (1, 8, 1.6)):
+            ph = rng.uniform(0, 2 * np.pi)
+            f += 0.03 * np.sin(2 * np.pi * (kx * X + ky * Y + kz * Z) + ph)
+        u0.append(f)
+    w = inputs.Workload("shell3d_tiled", 3, n, 1.0, 0.02, 1e-3, 12, S, u0)
+    o = oracle_sim(w).advance(w.steps)
+    g = gpu_sim(w, precision)
+    g.step(w.steps)
+    g.sync()
+    errs = field_errors(g.state(), o, 3)
+    print("shell3d tiled precision", precision, errs)
+    for k, e in errs.items():
+        assert e <= tol, (k, e)
+    g.close()
