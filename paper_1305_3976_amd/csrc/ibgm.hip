@@ -499,8 +499,8 @@ static void launch_explicit(ib_ctx *c, bool first) {
   a.first = first;
   a.advect = !(c->prm.flags & IB_FLAG_NO_ADVECTION);
   if constexpr (DIM == 3) {
-    if (c->g.n0 % EX == 0 && c->g.n1 % EY == 0) {
-      const dim3 grid(c->g.n0 / EX, c->g.n1 / EY, (c->g.n2 + EZ - 1) / EZ);
+    if (c->g.n0 % EX == 0 && c->g.n1 % EY == 0 && c->g.ncell < INT32_MAX) {
+      const dim3 grid((c->g.n0 / EX) * (c->g.n1 / EY) * ((c->g.n2 + EZ - 1) / EZ));
       launch(c, KP_EXPLICIT, [&] {
         hipLaunchKernelGGL((k_explicit3<T>), grid, dim3(EX * EY), 0, c->stream, a);
       });

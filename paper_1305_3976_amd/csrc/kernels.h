@@ -678,74 +678,120 @@ __global__ void __launch_bounds__(256) k_explicit(ExplicitArgs<T, DIM> a) {
 }
 
 // 3-D explicit step on a 2.5-D blocking: a workgroup owns an EX x EY tile of
-// (x, y) columns and marches KZ planes along z.  Three rotating planes of
-// u, v, w (tile plus a one-cell halo) and the current plane of p* = p + psi
-// (tile plus its -x, -y halo) sit in LDS, so each value is fetched from HBM
-// about once instead of once per stencil use.  Same arithmetic as
-// k_explicit.
+// (x, y) columns and marches EZ planes along z.  Three planes of u, v, w
+// (tile plus a one-cell halo) and the current plane of p* = p + psi (tile
+// plus its -x, -y halo) sit in LDS, so each value is fetched from HBM about
+// once instead of once per stencil use.  The loads are software-pipelined:
+// while plane k is computed from LDS, plane k+2 of the velocities, plane k+1
+// of p* and this cell's N^{n-1} and f are already in flight into registers.
+// Same arithmetic as k_explicit.
 constexpr int EX = 64, EY = 4, EZ = 16;
 constexpr int EW = EX + 2, EH = EY + 2;  // velocity plane with halo
 constexpr int PW = EX + 1, PH = EY + 1;  // p* plane with -x, -y halo
+constexpr int ENT = EX * EY;             // threads per workgroup
+constexpr int VPT = (EH * EW + ENT - 1) / ENT;  // velocity entries per thread
+constexpr int PPT = (PH * PW + ENT - 1) / ENT;  // p* entries per thread
 
 template <typename T>
-__global__ void __launch_bounds__(EX * EY) k_explicit3(ExplicitArgs<T, 3> a) {
+__global__ void __launch_bounds__(ENT) k_explicit3(ExplicitArgs<T, 3> a) {
   using C = T;
   __shared__ C U[3][3][EH * EW];
   __shared__ double PS[PH * PW];
   const int n0 = a.g.n0, n1 = a.g.n1, n2 = a.g.n2;
   const int tx = threadIdx.x % EX, ty = threadIdx.x / EX;
-  const int i0 = blockIdx.x * EX, j0 = blockIdx.y * EY, k0 = blockIdx.z * EZ;
-  const int i = i0 + tx, j = j0 + ty;
-  const int64_t plane = (int64_t)n0 * n1;
+  // Workgroups are dealt round-robin to the 8 XCDs (each with its own L2).
+  // Re-map the 1-D block index so each XCD walks a contiguous run of tiles
+  // (x fastest): the halo columns and rows a tile shares with its neighbours
+  // are then fetched into one L2.
+  const int nbx = n0 / EX, nby = n1 / EY;
+  const int nb = gridDim.x;
+  const int b = (nb % 8 == 0) ? (blockIdx.x % 8) * (nb / 8) + blockIdx.x / 8 : blockIdx.x;
+  const int i0 = (b % nbx) * EX, j0 = ((b / nbx) % nby) * EY, k0 = (b / (nbx * nby)) * EZ;
+  const int plane = n0 * n1;  // < 2^31 (checked on the host)
   auto wrap = [](int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); };
-  // load plane kk of u, v, w (tile + halo) into rotating slot sl
-  auto load_vel = [&](int kk, int sl) {
-    const int kw = wrap(kk, n2);
-    for (int e = threadIdx.x; e < EH * EW; e += EX * EY) {
-      const int jl = e / EW, il = e % EW;
-      const int64_t g = (int64_t)kw * plane + (int64_t)wrap(j0 - 1 + jl, n1) * n0 + wrap(i0 - 1 + il, n0);
-      U[0][sl][e] = (C)a.u[0][g];
-      U[1][sl][e] = (C)a.u[1][g];
-      U[2][sl][e] = (C)a.u[2][g];
+  // in-plane offsets of this thread's halo-tile entries and of its own cell,
+  // fixed for the whole march; planes only move a wave-uniform base
+  int voff[VPT], poff[PPT];
+#pragma unroll
+  for (int q = 0; q < VPT; q++) {
+    const int e = min((int)threadIdx.x + q * ENT, EH * EW - 1);
+    voff[q] = wrap(j0 - 1 + e / EW, n1) * n0 + wrap(i0 - 1 + e % EW, n0);
+  }
+#pragma unroll
+  for (int q = 0; q < PPT; q++) {
+    const int e = min((int)threadIdx.x + q * ENT, PH * PW - 1);
+    poff[q] = wrap(j0 - 1 + e / PW, n1) * n0 + wrap(i0 - 1 + e % PW, n0);
+  }
+  const int cell = (j0 + ty) * n0 + (i0 + tx);
+  const int tflag_row = (i0 + tx) / TS + a.tg.nt[0] * ((j0 + ty) / TS);
+  const int tplane = a.tg.nt[0] * a.tg.nt[1];
+  auto pbase = [&](int kk) { return (int64_t)wrap(kk, n2) * plane; };
+  // prologue: planes k0-1, k0, k0+1 of the velocities and plane k0 of p*
+  for (int sl = 0; sl < 3; sl++) {
+    const int64_t pb = pbase(k0 - 1 + sl);
+#pragma unroll
+    for (int q = 0; q < VPT; q++) {
+      const int e = threadIdx.x + q * ENT;
+      if (e < EH * EW) {
+        U[0][sl][e] = (C)a.u[0][pb + voff[q]];
+        U[1][sl][e] = (C)a.u[1][pb + voff[q]];
+        U[2][sl][e] = (C)a.u[2][pb + voff[q]];
+      }
     }
-  };
-  auto load_p = [&](int kk) {
-    const int kw = wrap(kk, n2);
-    for (int e = threadIdx.x; e < PH * PW; e += EX * EY) {
-      const int jl = e / PW, il = e % PW;
-      const int64_t g = (int64_t)kw * plane + (int64_t)wrap(j0 - 1 + jl, n1) * n0 + wrap(i0 - 1 + il, n0);
-      PS[e] = a.p[g] + (double)a.psi[g];
+  }
+  {
+    const int64_t pb = pbase(k0);
+#pragma unroll
+    for (int q = 0; q < PPT; q++) {
+      const int e = threadIdx.x + q * ENT;
+      if (e < PH * PW) PS[e] = a.p[pb + poff[q]] + (double)a.psi[pb + poff[q]];
     }
-  };
-  const int tiles_x = (n0 + TS - 1) / TS;
+  }
+  const int64_t pbm = pbase(k0 - 1);
+  double ps_below = a.p[pbm + cell] + (double)a.psi[pbm + cell];
   const int c = (ty + 1) * EW + (tx + 1);  // this column in a velocity plane
-  load_vel(k0 - 1, 0);
-  load_vel(k0, 1);
-  // p* below the first plane, at this column
-  double ps_below = a.p[(int64_t)wrap(k0 - 1, n2) * plane + (int64_t)j * n0 + i] +
-                    (double)a.psi[(int64_t)wrap(k0 - 1, n2) * plane + (int64_t)j * n0 + i];
+  const int pc = (ty + 1) * PW + (tx + 1);
+  __syncthreads();
   for (int kz = 0; kz < EZ && k0 + kz < n2; kz++) {
     const int k = k0 + kz;
     const int sm = kz % 3, s0 = (kz + 1) % 3, sp = (kz + 2) % 3;
-    load_vel(k + 1, sp);
-    load_p(k);
-    __syncthreads();
-    const int64_t idx = (int64_t)k * plane + (int64_t)j * n0 + i;
-    const int pc = (ty + 1) * PW + (tx + 1);
+    const bool more = kz + 1 < EZ && k + 1 < n2;  // uniform over the workgroup
+    // 1. fetch ahead: plane k+2 of u, v, w and plane k+1 of p*
+    C vr[3][VPT];
+    double pr[PPT];
+    if (more) {
+      const T *u0p = a.u[0] + pbase(k + 2), *u1p = a.u[1] + pbase(k + 2),
+              *u2p = a.u[2] + pbase(k + 2);
+#pragma unroll
+      for (int q = 0; q < VPT; q++) {
+        vr[0][q] = (C)u0p[voff[q]];
+        vr[1][q] = (C)u1p[voff[q]];
+        vr[2][q] = (C)u2p[voff[q]];
+      }
+      const double *pp = a.p + pbase(k + 1);
+      const T *sp_ = a.psi + pbase(k + 1);
+#pragma unroll
+      for (int q = 0; q < PPT; q++) pr[q] = pp[poff[q]] + (double)sp_[poff[q]];
+    }
+    // this cell's N^{n-1} and f
+    const int64_t kp = (int64_t)k * plane;
+    const bool forced = a.flag[tflag_row + tplane * (k / TS)] != 0;
+    C nlp[3], fc[3];
+#pragma unroll
+    for (int ci = 0; ci < 3; ci++) {
+      nlp[ci] = a.first ? C(0) : (C)(a.nl[ci] + kp)[cell];
+      fc[ci] = forced ? (C)(a.f[ci] + kp)[cell] : C(0);
+    }
+    // 2. compute plane k from LDS
     const double ps0 = PS[pc];
     const double psm[3] = {PS[pc - 1], PS[pc - PW], ps_below};
-    const int64_t tile = i / TS + (int64_t)tiles_x * (j / TS + (int64_t)a.tg.nt[1] * (k / TS));
-    const bool forced = a.flag[tile] != 0;
-    // neighbour offsets within a plane, and the plane slots below / above
     const int dpl[3] = {1, EW, 0}, sl_m[3] = {s0, s0, sm}, sl_p[3] = {s0, s0, sp};
 #pragma unroll
     for (int ci = 0; ci < 3; ci++) {
-      const C *Ui = U[ci][s0];
-      const C u0 = Ui[c];
+      const C u0 = U[ci][s0][c];
       C dv = 0, ad = 0, lap = 0;
 #pragma unroll
       for (int cj = 0; cj < 3; cj++) {
-        // u_ci one cell up / down along axis cj
         const C up = U[ci][sl_p[cj]][c + dpl[cj]];
         const C um = U[ci][sl_m[cj]][c - dpl[cj]];
         lap += up - C(2) * u0 + um;
@@ -755,10 +801,10 @@ __global__ void __launch_bounds__(EX * EY) k_explicit3(ExplicitArgs<T, 3> a) {
           dv += ap * ap - am * am;
           ad += C(0.5) * (ap * (up - u0) + am * (u0 - um));
         } else {
-          // u_cj averaged along ci, on the edges at this cell and one up along cj
-          const C *Uj0 = U[cj][sl_m[ci]];  // plane holding "one down along ci"
+          // u_cj averaged along ci on the edges at this cell and one up along cj
+          const C *Uj0 = U[cj][sl_m[ci]];
           const C *Uj = U[cj][s0];
-          const C *Ujp = U[cj][sl_p[cj]];  // plane holding "one up along cj"
+          const C *Ujp = U[cj][sl_p[cj]];
           const C *Ujpm = U[cj][(ci == 2) ? sm : ((cj == 2) ? sp : s0)];
           const C Ua = C(0.5) * (Uj0[c - dpl[ci]] + Uj[c]);
           const C Ub = C(0.5) * (Ujpm[c + dpl[cj] - dpl[ci]] + Ujp[c + dpl[cj]]);
@@ -768,13 +814,30 @@ __global__ void __launch_bounds__(EX * EY) k_explicit3(ExplicitArgs<T, 3> a) {
       }
       const C N = C(0.5) * (dv + ad) * (C)a.inv_h;
       const C gp = (C)((ps0 - psm[ci]) * a.inv_h);
-      const C Nh = a.first ? N : C(1.5) * N - C(0.5) * (C)a.nl[ci][idx];
-      const C fc = forced ? (C)a.f[ci][idx] : C(0);
-      const C d = (C)a.dt * (-Nh + ((C)a.mu * lap * (C)a.inv_h2 - gp + fc) * (C)a.inv_rho);
-      a.delta[ci][idx] = (T)d;
-      a.nl[ci][idx] = (T)N;
+      const C Nh = a.first ? N : C(1.5) * N - C(0.5) * nlp[ci];
+      const C d = (C)a.dt * (-Nh + ((C)a.mu * lap * (C)a.inv_h2 - gp + fc[ci]) * (C)a.inv_rho);
+      (a.delta[ci] + kp)[cell] = (T)d;
+      (a.nl[ci] + kp)[cell] = (T)N;
     }
     ps_below = ps0;
+    // 3. rotate: plane k+2 replaces plane k-1, plane k+1 of p* replaces k
+    __syncthreads();
+    if (more) {
+#pragma unroll
+      for (int q = 0; q < VPT; q++) {
+        const int e = threadIdx.x + q * ENT;
+        if (e < EH * EW) {
+          U[0][sm][e] = vr[0][q];
+          U[1][sm][e] = vr[1][q];
+          U[2][sm][e] = vr[2][q];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < PPT; q++) {
+        const int e = threadIdx.x + q * ENT;
+        if (e < PH * PW) PS[e] = pr[q];
+      }
+    }
     __syncthreads();
   }
 }
