@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="approximate CPU budget of the oracle sample")
+    ap.add_argument("--ensemble-steps", type=int, default=500,
+                    help="steps of the batched 2-D ensemble (0 = skip it)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB (3 times), the reference "
                          "for scaling hardware byte counters")
@@ -107,6 +109,77 @@ def run_gpu(w, precision, steps, warmup):
     del sim
     torch.cuda.empty_cache()
     return ms, ms_plain, wall, kern
+
+
+def run_ensemble(steps, spl_choices=(2, 10), seed=4):
+    """Batched ensemble: 64 independent 2-D problems (N drawn from
+    {128,...,512}, 4N-point ellipses, stiffness log-uniform in [0.1, 100], time
+    step per member), FP32 grid.  Step 0 runs eagerly (start-up rules); then
+    every variant (steps per graph launch x one chain / one branch per size
+    class) is timed over the same number of steps after tuning, and the
+    fastest is reported, beside eager launches of the same steps."""
+    import torch
+    from paper_1305_3976_amd import ensemble, ibgm, inputs
+    members, shared = inputs.config_ensemble(nsims=64, seed=seed, steps=steps)
+    ens = ensemble.Ensemble(members, rho=shared["rho"], mu=shared["mu"],
+                            precision=ibgm.IB_PREC_MIXED)
+    st = ens.stream
+    t0 = time.perf_counter()
+    picks = ens.tune(reps=3)
+    tune_s = time.perf_counter() - t0
+    ens.step(1)
+    ens.sync()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    timed = steps - 1 - (steps - 1) % (2 * max(spl_choices))
+    # eager launches of the same steps
+    e0.record(st)
+    ens.step(timed)
+    e1.record(st)
+    ens.sync()
+    eager_ms = e0.elapsed_time(e1)
+    variants = {}
+    for spl in spl_choices:
+        for br in (False, True):
+            ens.capture(spl, branches=br)
+            ens.launch(1)                      # warm the instantiated graph
+            ens.sync()
+            e0.record(st)
+            ens.launch(timed // spl)
+            e1.record(st)
+            ens.sync()
+            variants["spl%d_%s" % (spl, "branches" if br else "chain")] = e0.elapsed_time(e1)
+    best = min(variants, key=variants.get)
+    ms = variants[best]
+    ens.close()
+    del ens
+    torch.cuda.empty_cache()
+    cells = sum(m.n ** 2 for m in members)
+    sizes = {}
+    for m in members:
+        sizes[m.n] = sizes.get(m.n, 0) + 1
+    return {
+        "workload": "ensemble2d_64: 64 independent 2-D periodic problems, N from {128,192,256,384,512} "
+                    "(seed %d), 4N-point 0.3x0.2 ellipses, stiffness log-uniform [0.1,100], "
+                    "mu=0.01, per-member dt from the stiffness table, FP32 grid" % seed,
+        "members": len(members), "members_per_size": sizes, "cells": cells,
+        "timed_steps": timed,
+        "member_steps_per_s": round(len(members) * timed / (ms * 1e-3), 1),
+        "ensemble_steps_per_s": round(timed / (ms * 1e-3), 2),
+        "gcell_updates_per_s": round(cells * timed / (ms * 1e-3) / 1e9, 3),
+        "ms_per_ensemble_step": round(ms / timed, 4),
+        "step_GB_s": round(step_bytes(4, cells, 2) / (ms / timed * 1e-3) / 1e9, 1),
+        "best_variant": best,
+        "variants_ms_per_step": {k: round(v / timed, 4) for k, v in variants.items()},
+        "eager_ms_per_step": round(eager_ms / timed, 4),
+        "tune_s": round(tune_s, 3),
+        "tuned_tiles": [{"n": n, "picks": {"%d/%s" % (a, "f64" if r else "f32"): list(v)
+                                           for (a, r), v in pk.items()}}
+                        for (n, _), pk in zip(ens_classes_sizes(members), picks)],
+    }
+
+
+def ens_classes_sizes(members):
+    return [(n, None) for n in sorted({m.n for m in members})]
 
 
 def oracle_sample(w, budget_s):
@@ -225,6 +298,11 @@ def main():
                         "step_GB_s": round(step_bytes(8, ncell, w.dim) / (ms64_plain / args.steps * 1e-3) / 1e9, 1),
                         "kernels_avg_us": {k: round(t / c * 1e3, 2) for k, (t, c) in kern64.items()}}
         line["mixed_vs_fp64_speedup"] = round(steps_s / s64, 3)
+    if args.ensemble_steps:
+        line["ensemble"] = run_ensemble(args.ensemble_steps)
+        print("# ensemble: %.1f member-steps/s, %.3f Gcell/s (%s)" % (
+            line["ensemble"]["member_steps_per_s"], line["ensemble"]["gcell_updates_per_s"],
+            line["ensemble"]["best_variant"]), file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         ref, n, el, thr = oracle_sample(w, args.cpu_seconds)
         line["cpu_baseline"] = {"value": round(n / el, 5), "unit": "IB steps/s", "cores": thr,

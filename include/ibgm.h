@@ -13,7 +13,8 @@
  *   Pointers.   Every array argument is a DEVICE pointer (hipMalloc / torch
  *               CUDA tensor) unless the comment says "host".  The caller
  *               owns every buffer; the library never frees caller memory.
- *   Layout.     Grid arrays are dense [n2][n1][n0] (x fastest, n2 = 1 in 2D).
+ *   Layout.     Grid arrays are dense [n2][n1][n0] (x fastest; in 2D, n2 is
+ *               the number of independent layers, 1 for one problem).
  *               Velocity component c lives on the faces normal to axis c:
  *               integer index along c, half-integer along the others; cell
  *               centred arrays (p, psi, div) sit at half-integers.  Lagrangian
@@ -22,7 +23,8 @@
  *   Precision.  IB_PREC_FP64: every grid array is FP64.  IB_PREC_MIXED: the
  *               velocity-like grid arrays (u, nl_prev, psi, div_prev, the
  *               workspace and spread forces) are FP32, while p, X, U stay
- *               FP64; line-solve recurrences always run in FP64 registers.
+ *               FP64.  Pressure-increment recurrences always run in FP64
+ *               registers; momentum recurrences in the storage precision.
  *   Streams.    Work is enqueued on the hipStream_t given to ib_init (or to
  *               ib_line_solve) and returns before it completes.  Device faults
  *               surface at the next call that synchronises (ib_sync).
@@ -61,7 +63,10 @@ typedef enum { IB_PREC_FP64 = 0, IB_PREC_MIXED = 1 } ib_precision;
 
 typedef struct {
   int32_t dim;          /* 2 or 3 */
-  int32_t n[3];         /* cells per axis, each >= 4 and <= 1024; n[2] = 1 in 2D */
+  int32_t n[3];         /* cells per axis, each >= 4 and <= 1024.  In 2D, n[2]
+                           counts independent layers: n[2] equal-size 2-D
+                           problems stacked along the slowest axis, never
+                           coupled (a batch; 1 for a single problem) */
   double h;             /* mesh width > 0 (the paper's h = H/N) */
   double rho;           /* density > 0 */
   double mu;            /* dynamic viscosity >= 0 */
@@ -76,6 +81,9 @@ typedef struct {
   int64_t step0;        /* index n of the state handed in; 0 = fresh start, which
                            applies the paper's n = 0 rules (forward Euler for X,
                            N^{1/2} = N(u^0)) and computes div_prev = D.u^0 */
+  const double *layer_dt; /* HOST, 2-D batches: time step of each of the n[2]
+                           layers (each > 0), or NULL for dt everywhere;
+                           copied at ib_init */
 } ib_grid_params;
 
 /* Device state, caller-owned, borrowed by the context until ib_destroy.
@@ -103,6 +111,9 @@ typedef struct {
   const int32_t *a, *b;      /* host, point indices in [0, n_points) */
   const double *kappa, *l0;  /* host, kappa finite, l0 >= 0 */
   const double *w;           /* host [n_points], spreading weight (Step 2b) */
+  const int32_t *layer;      /* host [n_points], 2-D batches: the layer (in
+                                [0, n[2])) each point lives in, or NULL for 0;
+                                links must not join points of different layers */
 } ib_structure;
 
 /* Bytes of device workspace a context with these parameters needs. */
@@ -129,15 +140,18 @@ ib_status ib_step(ib_ctx *ctx, int32_t nsteps);
 ib_status ib_sync(ib_ctx *ctx, int64_t *step_index);
 
 /* Step 2b on given buffers: f_out[c] (+)= sum_k F[c][k] w[k] delta_h(x - X_k)
- * for the context's grid.  X, F, w: FP64 device [dim][npts], [npts];
- * f_out[c]: grid dtype.  accumulate = 0 clears f_out first.  Grid cells are
- * summed with device atomics, so the order of additions varies run to run. */
+ * for the context's grid.  X, F, w: FP64 device [dim][npts], [npts], npts at
+ * most the context's n_points (in a 2-D batch, point k lives in the layer
+ * the structure gave it); f_out[c]: grid dtype.  accumulate = 0 clears f_out
+ * first.  Contributions are summed in LDS with atomics, so the order of
+ * additions (and the last bits of the sums) varies run to run. */
 ib_status ib_spread(ib_ctx *ctx, const double *X, const double *F,
                     const double *w, int64_t npts, void *const f_out[3],
                     int32_t accumulate);
 
 /* Step 1a on given buffers: U[c][k] = sum_ij u_in[c]_ij delta_h(x - X_k) h^d.
- * X, U: FP64 device [dim][npts]; u_in[c]: grid dtype. */
+ * X, U: FP64 device [dim][npts]; u_in[c]: grid dtype.  In a 2-D batch npts
+ * must not exceed n_points and point k reads the layer the structure gave it. */
 ib_status ib_interp(ib_ctx *ctx, const double *X, int64_t npts,
                     void *const u_in[3], double *U);
 
@@ -158,6 +172,34 @@ ib_status ib_line_solve(void *data, int32_t dtype, const int32_t n[3],
 
 /* Release the context's own allocations (not the caller's buffers). */
 ib_status ib_destroy(ib_ctx *ctx);
+
+/* Autotuner: time the tile shapes of the line-solve kernels (elements per
+ * lane of x lines; row width and chunk length of strided lines) on this
+ * context's grid, for each axis and recurrence precision, `reps` launches
+ * each, on the context's own scratch fields (synchronises; call between
+ * steps, not during capture), and use the fastest from then on.
+ * ib_tune_read reports the choice (0 = library default). */
+ib_status ib_tune(ib_ctx *ctx, int32_t reps);
+ib_status ib_tune_read(const ib_ctx *ctx, int32_t axis, int32_t fp64_recurrence,
+                       int32_t *x_chunk, int32_t *s_rows, int32_t *s_chunk);
+
+/* One hipGraph holding `steps_per_launch` IB-GM steps of each of `nctx`
+ * contexts (e.g. the size classes of an ensemble of independent problems),
+ * captured from the contexts' common stream `hip_stream` (a created stream:
+ * the null stream cannot be captured).  Every context must be past its first
+ * step (take it with ib_step), not profiling, and steps_per_launch must be a
+ * multiple of each rotation period (dim).  flags: 0 = one chain of launches;
+ * IB_GRAPH_BRANCHES = one independent branch per context, which the runtime
+ * may run concurrently.  ib_graph_launch replays the graph `nlaunches` times
+ * (asynchronous, on hip_stream) and advances every context's step index; the
+ * contexts' buffers must stay where they were at capture and the contexts must
+ * not be destroyed before the graph.  No memset nodes are captured. */
+#define IB_GRAPH_BRANCHES 1
+typedef struct ib_graph ib_graph;
+ib_status ib_graph_create(ib_graph **out, ib_ctx *const *ctxs, int32_t nctx,
+                          int32_t steps_per_launch, int32_t flags, void *hip_stream);
+ib_status ib_graph_launch(ib_graph *graph, int32_t nlaunches);
+ib_status ib_graph_destroy(ib_graph *graph);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *ib_last_error(void);

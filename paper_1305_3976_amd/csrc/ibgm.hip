@@ -64,6 +64,12 @@ struct PendingEvent {
 
 // ------------------------------------------------------------ context --
 
+// Tile shapes of the sweep kernels picked by ib_tune (0 = default).
+struct SweepTune {
+  int x_m;        // elements per lane of x lines
+  int s_tx, s_m;  // strided: row width and chunk length
+};
+
 struct ib_ctx {
   ib_grid_params prm;
   ib_buffers buf;
@@ -89,6 +95,14 @@ struct ib_ctx {
   int64_t nlinks;
   // factored coefficients
   double mom_alpha, mom_invc, psi_alpha, psi_invc;
+  // 2-D batches (library allocation; null for single problems): layer of
+  // each point, and per layer dt, momentum factors and the first psi sweep's
+  // scaled 1/c
+  int *p_layer;
+  double *l_dt, *l_mom_alpha, *l_mom_invc, *l_psi_invc;
+  // tile shapes chosen by ib_tune, per axis and recurrence type (0 = float)
+  bool tuned;
+  SweepTune tune[3][2];
   // profiling
   bool prof;
   std::vector<PendingEvent> pending;
@@ -221,9 +235,9 @@ static void go_x_any(SweepArgs<T> a, int nf, hipStream_t st) {
 }
 
 template <typename T, int MODE>
-static void dispatch_x(SweepArgs<T> a, int nf, hipStream_t st) {
+static void dispatch_x(SweepArgs<T> a, int nf, hipStream_t st, const SweepTune *tu = nullptr) {
   const int64_t N = a.g.n0;
-  const int M = x_chunk(N);
+  const int M = (tu && tu->x_m) ? tu->x_m : x_chunk(N);
   a.G = next_pow2((int)((N + M - 1) / M));
   switch (M) {
     case 1: go_x_any<T, 1, MODE>(a, nf, st); break;
@@ -282,14 +296,16 @@ static bool go_sb_fit(SweepArgs<T> a, int axis, int nf, hipStream_t st) {
 }
 
 template <typename T, int MODE, typename R>
-static void dispatch_s(SweepArgs<T> a, int axis, int nf, hipStream_t st) {
+static void dispatch_s(SweepArgs<T> a, int axis, int nf, hipStream_t st,
+                       const SweepTune *tu = nullptr) {
   const int64_t N = axis == 1 ? a.g.n1 : a.g.n2;
   const int64_t stride = axis == 1 ? a.g.n0 : a.g.n0 * a.g.n1;
   const bool buf_ok = N >= 64 && N <= 1024 && a.g.n0 >= 64 &&
                       ((N - 1) * stride + 64) * (int64_t)sizeof(double) < 0x7fffffff;
   if (buf_ok) {
-    const int M = env_choice("IBGM_S_CHUNK", 16, 32, 16);
-    const int TX = env_choice("IBGM_S_TX", 32, 64, sizeof(R) == 8 ? 32 : 64);
+    const int M = (tu && tu->s_m) ? tu->s_m : env_choice("IBGM_S_CHUNK", 16, 32, 16);
+    const int TX = (tu && tu->s_tx) ? tu->s_tx
+                                    : env_choice("IBGM_S_TX", 32, 64, sizeof(R) == 8 ? 32 : 64);
     bool ok;
     if (M == 16)
       ok = TX == 32 ? go_sb_fit<T, R, 16, MODE, 32>(a, axis, nf, st)
@@ -313,14 +329,19 @@ static void dispatch_s(SweepArgs<T> a, int axis, int nf, hipStream_t st) {
   else go_s<T, 32, MODE, 1024>(a, axis, nf, TX, st);
 }
 
+static const SweepTune *tune_of(const ib_ctx *c, int axis, bool r64) {
+  return (c && c->tuned) ? &c->tune[axis][r64 ? 1 : 0] : nullptr;
+}
+
 // Launch one sweep along `axis`; `id_x` / `id_s` name it for profiling (the
 // strided id is id_x + 1).  R is the recurrence type of the strided kernel.
 template <typename T, int MODE, typename R = double>
 static void sweep(ib_ctx *c, int id_x, SweepArgs<T> a, int axis, int nf, hipStream_t st) {
+  const SweepTune *tu = tune_of(c, axis, sizeof(R) == 8);
   if (axis == 0)
-    launch(c, id_x, [&] { dispatch_x<T, MODE>(a, nf, st); });
+    launch(c, id_x, [&] { dispatch_x<T, MODE>(a, nf, st, tu); });
   else
-    launch(c, id_x + 1, [&] { dispatch_s<T, MODE, R>(a, axis, nf, st); });
+    launch(c, id_x + 1, [&] { dispatch_s<T, MODE, R>(a, axis, nf, st, tu); });
 }
 
 // ------------------------------------------------------------ validation --
@@ -333,7 +354,12 @@ static ib_status check_params(const ib_grid_params *p) {
   for (int a = 0; a < p->dim; a++)
     if (p->n[a] < 4 || p->n[a] > 1024)
       return fail(IB_E_INVALID, "n[%d] = %d outside [4, 1024]", a, p->n[a]);
-  if (p->dim == 2 && p->n[2] != 1) return fail(IB_E_INVALID, "2-D grids need n[2] == 1");
+  if (p->dim == 2 && (p->n[2] < 1 || p->n[2] > 65535))
+    return fail(IB_E_INVALID, "2-D layer count n[2] = %d outside [1, 65535]", p->n[2]);
+  if (p->dim == 2 && p->layer_dt)
+    for (int l = 0; l < p->n[2]; l++)
+      if (!finite_pos(p->layer_dt[l]))
+        return fail(IB_E_INVALID, "layer_dt[%d] must be finite and > 0", l);
   if (!finite_pos(p->h)) return fail(IB_E_INVALID, "h must be finite and > 0");
   if (!finite_pos(p->rho)) return fail(IB_E_INVALID, "rho must be finite and > 0");
   if (!finite_pos(p->dt)) return fail(IB_E_INVALID, "dt must be finite and > 0");
@@ -351,7 +377,7 @@ static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 static TileGrid tile_grid(const ib_grid_params *p) {
   TileGrid tg{};
-  for (int a = 0; a < 3; a++) tg.nt[a] = a < p->dim ? (p->n[a] + TS - 1) / TS : 1;
+  for (int a = 0; a < 3; a++) tg.nt[a] = a < p->dim ? (p->n[a] + TS - 1) / TS : p->n[a];
   tg.ntiles = (int64_t)tg.nt[0] * tg.nt[1] * tg.nt[2];
   return tg;
 }
@@ -396,6 +422,8 @@ static void launch_interp(ib_ctx *c, int id, const double *X, int64_t np,
   a.Xn1 = c->Xn1;
   a.Xh = c->Xh;
   a.flag = c->flag;
+  a.layer = c->p_layer;
+  a.dt_layer = c->l_dt;
   a.np = np;
   a.g = c->g;
   a.inv_h = 1.0 / c->prm.h;
@@ -436,8 +464,8 @@ static void launch_spread(ib_ctx *c, const double *X, const double *F, const dou
   const unsigned pb = (unsigned)((np + 255) / 256);
   const unsigned nb = (unsigned)((c->tg.ntiles + SCAN_TILE - 1) / SCAN_TILE);
   launch(c, KP_SORT, [&] {
-    hipLaunchKernelGGL((k_bin<DIM>), dim3(pb), dim3(256), 0, c->stream, X, np, c->g, c->tg,
-                       inv_h, c->t_count, c->tile_of, c->rank_of);
+    hipLaunchKernelGGL((k_bin<DIM>), dim3(pb), dim3(256), 0, c->stream, X, c->p_layer, np,
+                       c->g, c->tg, inv_h, c->t_count, c->tile_of, c->rank_of);
   });
   launch(c, KP_SORT, [&] {
     hipLaunchKernelGGL(k_scan_sums, dim3(nb), dim3(256), 0, c->stream, c->t_count, c->t_bsum,
@@ -489,6 +517,7 @@ static void launch_explicit(ib_ctx *c, bool first) {
   a.p = c->buf.p;
   a.psi = (const T *)c->buf.psi;
   a.flag = c->t_flag;
+  a.dt_layer = c->l_dt;
   a.g = c->g;
   a.tg = c->tg;
   a.inv_h = 1.0 / c->prm.h;
@@ -548,6 +577,8 @@ static void enqueue_step(ib_ctx *c) {
   m.dim = DIM;
   m.alpha = c->mom_alpha;
   m.inv_c = c->mom_invc;
+  m.alpha_layer = c->l_mom_alpha;
+  m.invc_layer = c->l_mom_invc;
   for (int i = 0; i < 3; i++) {
     m.f[i] = m.o[i] = (T *)(i < DIM ? c->delta[i] : nullptr);
     m.u[i] = (T *)(i < DIM ? c->buf.u[i] : nullptr);
@@ -565,10 +596,12 @@ static void enqueue_step(ib_ctx *c) {
   q.dim = DIM;
   q.alpha = c->psi_alpha;
   q.inv_c = c->psi_invc * (-c->prm.rho / c->prm.dt);
+  q.invc_layer = c->l_psi_invc;  // per-layer -(rho/dt)/c in 2-D batches
   q.f[0] = (T *)c->divn;
   q.o[0] = (T *)c->buf.psi;
   sweep<T, SW_PLAIN>(c, KP_PSI_X_FIRST, q, order[0], 1, c->stream);
   q.inv_c = c->psi_invc;
+  q.invc_layer = nullptr;
   q.f[0] = q.o[0] = (T *)c->buf.psi;
   q.divn = (T *)c->divn;
   q.divp = (T *)c->buf.div_prev;
@@ -578,6 +611,8 @@ static void enqueue_step(ib_ctx *c) {
   sweep<T, SW_PFINAL>(c, KP_PSI_X_PFINAL, q, order[DIM - 1], 1, c->stream);
   c->step = n + 1;
 }
+
+static void enqueue_any(ib_ctx *c);
 
 // ---------------------------------------------------------------- API --
 
@@ -605,6 +640,19 @@ extern "C" ib_status ib_init(ib_ctx **out, const ib_grid_params *prm, const ib_b
   if (!st->w) return fail(IB_E_INVALID, "null spreading weights");
   for (int64_t i = 0; i < np; i++)
     if (!std::isfinite(st->w[i])) return fail(IB_E_INVALID, "non-finite weight at point %lld", (long long)i);
+  if (st->layer) {
+    if (d != 2) return fail(IB_E_INVALID, "point layers are for 2-D batches only");
+    for (int64_t i = 0; i < np; i++)
+      if (st->layer[i] < 0 || st->layer[i] >= prm->n[2])
+        return fail(IB_E_INVALID, "point %lld has layer %d outside [0, %d)", (long long)i,
+                    st->layer[i], prm->n[2]);
+    for (int64_t e = 0; e < st->n_links; e++)
+      if (st->a[e] >= 0 && st->a[e] < np && st->b[e] >= 0 && st->b[e] < np &&
+          st->layer[st->a[e]] != st->layer[st->b[e]])
+        return fail(IB_E_INVALID, "link %lld joins points of different layers", (long long)e);
+  } else if (d == 2 && prm->n[2] > 1) {
+    return fail(IB_E_INVALID, "a 2-D batch of %d layers needs the point layers", prm->n[2]);
+  }
   // CSR by point, both directions of every link
   std::vector<int32_t> deg(np + 1, 0);
   for (int64_t e = 0; e < st->n_links; e++) {
@@ -635,6 +683,20 @@ extern "C" ib_status ib_init(ib_ctx **out, const ib_grid_params *prm, const ib_b
   const double nu = prm->mu * prm->dt / (2.0 * prm->rho);
   if ((s = factor(1.0 + 2.0 * nu / h2, -nu / h2, &ma, &mi)) != IB_OK) return s;
   if ((s = factor(1.0 + 2.0 / h2, -1.0 / h2, &pa, &pi)) != IB_OK) return s;
+  const bool layered = d == 2 && (prm->layer_dt || st->layer);
+  std::vector<double> l_dt, l_ma, l_mi, l_pi;
+  if (layered) {
+    for (int l = 0; l < prm->n[2]; l++) {
+      const double dtl = prm->layer_dt ? prm->layer_dt[l] : prm->dt;
+      const double nul = prm->mu * dtl / (2.0 * prm->rho);
+      double a1, i1;
+      if ((s = factor(1.0 + 2.0 * nul / h2, -nul / h2, &a1, &i1)) != IB_OK) return s;
+      l_dt.push_back(dtl);
+      l_ma.push_back(a1);
+      l_mi.push_back(i1);
+      l_pi.push_back(pi * (-prm->rho / dtl));
+    }
+  }
 
   ib_ctx *c = new ib_ctx();
   c->prm = *prm;
@@ -644,7 +706,7 @@ extern "C" ib_status ib_init(ib_ctx **out, const ib_grid_params *prm, const ib_b
   c->dim = d;
   c->g.n0 = prm->n[0];
   c->g.n1 = prm->n[1];
-  c->g.n2 = d == 3 ? prm->n[2] : 1;
+  c->g.n2 = prm->n[2];
   c->g.ncell = (int64_t)c->g.n0 * c->g.n1 * c->g.n2;
   c->np = np;
   c->f32 = prm->precision == IB_PREC_MIXED;
@@ -684,6 +746,24 @@ extern "C" ib_status ib_init(ib_ctx **out, const ib_grid_params *prm, const ib_b
       hipMalloc(&c->l0, sizeof(double) * l0.size()) != hipSuccess ||
       hipMalloc(&c->w, sizeof(double) * np) != hipSuccess)
     return bail(fail(IB_E_DEVICE, "hipMalloc of the link table failed"));
+  if (layered) {
+    const size_t nl = (size_t)prm->n[2];
+    std::vector<int> lay(np, 0);
+    if (st->layer)
+      for (int64_t i = 0; i < np; i++) lay[i] = st->layer[i];
+    if (hipMalloc(&c->p_layer, sizeof(int) * np) != hipSuccess ||
+        hipMalloc(&c->l_dt, sizeof(double) * nl) != hipSuccess ||
+        hipMalloc(&c->l_mom_alpha, sizeof(double) * nl) != hipSuccess ||
+        hipMalloc(&c->l_mom_invc, sizeof(double) * nl) != hipSuccess ||
+        hipMalloc(&c->l_psi_invc, sizeof(double) * nl) != hipSuccess)
+      return bail(fail(IB_E_DEVICE, "hipMalloc of the layer tables failed"));
+    if (hipMemcpy(c->p_layer, lay.data(), sizeof(int) * np, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->l_dt, l_dt.data(), sizeof(double) * nl, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->l_mom_alpha, l_ma.data(), sizeof(double) * nl, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->l_mom_invc, l_mi.data(), sizeof(double) * nl, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->l_psi_invc, l_pi.data(), sizeof(double) * nl, hipMemcpyHostToDevice) != hipSuccess)
+      return bail(fail(IB_E_DEVICE, "upload of the layer tables failed"));
+  }
   if (hipMemcpyAsync(c->ptr, deg.data(), sizeof(int32_t) * (np + 1), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
       hipMemcpyAsync(c->nbr, nbr.data(), sizeof(int32_t) * nbr.size(), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
       hipMemcpyAsync(c->kap, kap.data(), sizeof(double) * kap.size(), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
@@ -716,15 +796,7 @@ extern "C" ib_status ib_init(ib_ctx **out, const ib_grid_params *prm, const ib_b
 extern "C" ib_status ib_step(ib_ctx *c, int32_t nsteps) {
   if (!c) return fail(IB_E_STATE, "null context");
   if (nsteps < 0) return fail(IB_E_INVALID, "nsteps < 0");
-  for (int32_t i = 0; i < nsteps; i++) {
-    if (c->f32) {
-      if (c->dim == 2) enqueue_step<float, 2>(c);
-      else enqueue_step<float, 3>(c);
-    } else {
-      if (c->dim == 2) enqueue_step<double, 2>(c);
-      else enqueue_step<double, 3>(c);
-    }
-  }
+  for (int32_t i = 0; i < nsteps; i++) enqueue_any(c);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(IB_E_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
   return IB_OK;
@@ -771,6 +843,9 @@ extern "C" ib_status ib_interp(ib_ctx *c, const double *X, int64_t npts, void *c
   if (!c) return fail(IB_E_STATE, "null context");
   if (npts < 0 || (npts > 0 && (!X || !U)) || !u_in)
     return fail(IB_E_INVALID, "bad interp arguments");
+  if (c->p_layer && npts > c->np)
+    return fail(IB_E_INVALID, "npts %lld exceeds the batch's %lld points", (long long)npts,
+                (long long)c->np);
   for (int i = 0; i < c->dim; i++)
     if (!u_in[i]) return fail(IB_E_INVALID, "null input component %d", i);
   if (npts == 0) return IB_OK;
@@ -846,6 +921,9 @@ extern "C" ib_status ib_destroy(ib_ctx *c) {
   if (c->kap) (void)hipFree(c->kap);
   if (c->l0) (void)hipFree(c->l0);
   if (c->w) (void)hipFree(c->w);
+  for (void *q : {(void *)c->p_layer, (void *)c->l_dt, (void *)c->l_mom_alpha,
+                  (void *)c->l_mom_invc, (void *)c->l_psi_invc})
+    if (q) (void)hipFree(q);
   delete c;
   return IB_OK;
 }
@@ -875,5 +953,257 @@ extern "C" ib_status ib_profile_read(ib_ctx *c, int32_t id, double *total_ms,
   drain_events(c);
   if (total_ms) *total_ms = c->prof_ms[id];
   if (launches) *launches = c->prof_n[id];
+  return IB_OK;
+}
+
+// ----------------------------------------------------------- autotuner --
+
+static void enqueue_any(ib_ctx *c) {
+  if (c->f32) {
+    if (c->dim == 2) enqueue_step<float, 2>(c);
+    else enqueue_step<float, 3>(c);
+  } else {
+    if (c->dim == 2) enqueue_step<double, 2>(c);
+    else enqueue_step<double, 3>(c);
+  }
+}
+
+static int x_chunk64(int64_t N) {
+  static const int ms[] = {1, 2, 4, 6, 8, 12, 16, 32};
+  for (int m : ms)
+    if ((N + m - 1) / m <= 64) return m;
+  return 32;
+}
+
+// Time one plain sweep configuration `reps` times on the context's scratch
+// fields (the momentum increments, free outside a step).
+template <typename T, typename R>
+static float time_sweep(ib_ctx *c, int axis, int nf, const SweepTune &tu, int reps,
+                        hipEvent_t e0, hipEvent_t e1) {
+  SweepArgs<T> a{};
+  a.g = c->g;
+  a.dim = c->dim;
+  a.alpha = c->psi_alpha;
+  a.inv_c = c->psi_invc;
+  for (int i = 0; i < nf; i++) a.f[i] = a.o[i] = (T *)c->delta[i];
+  auto run = [&] {
+    if (axis == 0) dispatch_x<T, SW_PLAIN>(a, nf, c->stream, &tu);
+    else dispatch_s<T, SW_PLAIN, R>(a, axis, nf, c->stream, &tu);
+  };
+  run();
+  (void)hipEventRecord(e0, c->stream);
+  for (int r = 0; r < reps; r++) run();
+  (void)hipEventRecord(e1, c->stream);
+  (void)hipEventSynchronize(e1);
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, e0, e1);
+  return ms;
+}
+
+template <typename T>
+static void tune_ctx(ib_ctx *c, int reps, hipEvent_t e0, hipEvent_t e1) {
+  const int nn[3] = {c->g.n0, c->g.n1, c->g.n2};
+  for (int axis = 0; axis < c->dim; axis++) {
+    const int64_t N = nn[axis];
+    for (int r64 = 0; r64 < 2; r64++) {
+      // the mixed policy runs momentum (all components) with FP32 recurrences
+      // and psi (one field) with FP64 ones; FP64 runs everything in FP64
+      const bool rd = r64 || !c->f32;
+      const int nf = (c->f32 && r64) ? 1 : c->dim;
+      std::vector<SweepTune> cand;
+      if (axis == 0) {
+        cand.push_back({x_chunk(N), 0, 0});
+        if (x_chunk64(N) != x_chunk(N)) cand.push_back({x_chunk64(N), 0, 0});
+      } else {
+        for (int m : {16, 32})
+          for (int tx : {32, 64})
+            if (tx * ((N + m - 1) / m) <= 1024) cand.push_back({0, tx, m});
+      }
+      float best = 1e30f;
+      SweepTune pick = cand.empty() ? SweepTune{0, 0, 0} : cand[0];
+      for (const SweepTune &t : cand) {
+        const float ms = rd ? time_sweep<T, double>(c, axis, nf, t, reps, e0, e1)
+                            : time_sweep<T, float>(c, axis, nf, t, reps, e0, e1);
+        if (ms < best) {
+          best = ms;
+          pick = t;
+        }
+      }
+      c->tune[axis][r64] = pick;
+    }
+  }
+}
+
+extern "C" ib_status ib_tune(ib_ctx *c, int32_t reps) {
+  if (!c) return fail(IB_E_STATE, "null context");
+  if (c->prof) return fail(IB_E_STATE, "disable profiling before tuning");
+  if (reps < 1 || reps > 1000) return fail(IB_E_INVALID, "reps must lie in [1, 1000]");
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  const size_t fb = align256((size_t)c->g.ncell * c->tsz);
+  for (int i = 0; i < c->dim; i++) HIP_TRY(hipMemsetAsync(c->delta[i], 0, fb, c->stream));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(IB_E_DEVICE, "hipEventCreate failed");
+  }
+  c->tuned = false;
+  if (c->f32) tune_ctx<float>(c, reps, e0, e1);
+  else tune_ctx<double>(c, reps, e0, e1);
+  c->tuned = true;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(IB_E_DEVICE, "tuning launch failed: %s", hipGetErrorString(e));
+  return IB_OK;
+}
+
+extern "C" ib_status ib_tune_read(const ib_ctx *c, int32_t axis, int32_t fp64_recurrence,
+                                  int32_t *x_chunk_out, int32_t *s_rows_out,
+                                  int32_t *s_chunk_out) {
+  if (!c) return fail(IB_E_STATE, "null context");
+  if (axis < 0 || axis >= c->dim) return fail(IB_E_INVALID, "axis out of range");
+  const SweepTune t = c->tuned ? c->tune[axis][fp64_recurrence ? 1 : 0] : SweepTune{0, 0, 0};
+  if (x_chunk_out) *x_chunk_out = t.x_m;
+  if (s_rows_out) *s_rows_out = t.s_tx;
+  if (s_chunk_out) *s_chunk_out = t.s_m;
+  return IB_OK;
+}
+
+// ---------------------------------------------------------- graph launch --
+
+struct ib_graph {
+  std::vector<ib_ctx *> ctx;
+  int spl;
+  hipStream_t stream;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
+// Capture `spl` steps of every context.  Without IB_GRAPH_BRANCHES the graph
+// is one chain (step s of every context, then step s + 1).  With it, each
+// context is recorded on a stream of its own forked from `st` and joined back,
+// so the graph holds one independent branch per context, which the runtime may
+// run concurrently (the problems share no data).
+static ib_status capture_steps(ib_ctx *const *ctxs, int32_t nctx, int32_t spl, hipStream_t st,
+                               int32_t flags, hipGraph_t *graph) {
+  const bool branches = (flags & IB_GRAPH_BRANCHES) && nctx > 1;
+  std::vector<hipStream_t> br;
+  std::vector<hipEvent_t> ev;
+  auto cleanup = [&]() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    for (hipStream_t b : br) (void)hipStreamDestroy(b);
+  };
+  if (branches) {
+    br.resize(nctx, nullptr);
+    ev.resize(nctx + 1, nullptr);
+    for (int i = 0; i < nctx; i++)
+      if (hipStreamCreateWithFlags(&br[i], hipStreamNonBlocking) != hipSuccess) {
+        cleanup();
+        return fail(IB_E_DEVICE, "hipStreamCreateWithFlags failed");
+      }
+    for (int i = 0; i <= nctx; i++)
+      if (hipEventCreateWithFlags(&ev[i], hipEventDisableTiming) != hipSuccess) {
+        cleanup();
+        return fail(IB_E_DEVICE, "hipEventCreateWithFlags failed");
+      }
+  }
+  std::vector<int64_t> saved(nctx);
+  std::vector<hipStream_t> own(nctx);
+  for (int i = 0; i < nctx; i++) saved[i] = ctxs[i]->step, own[i] = ctxs[i]->stream;
+  hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) {
+    cleanup();
+    return fail(IB_E_DEVICE, "hipStreamBeginCapture failed: %s", hipGetErrorString(e));
+  }
+  hipError_t ef = hipSuccess;
+  if (branches) {
+    ef = hipEventRecord(ev[nctx], st);
+    for (int i = 0; i < nctx && ef == hipSuccess; i++) {
+      ef = hipStreamWaitEvent(br[i], ev[nctx], 0);
+      ctxs[i]->stream = br[i];
+      for (int k = 0; k < spl && ef == hipSuccess; k++) enqueue_any(ctxs[i]);
+      if (ef == hipSuccess) ef = hipEventRecord(ev[i], br[i]);
+      if (ef == hipSuccess) ef = hipStreamWaitEvent(st, ev[i], 0);
+    }
+  } else {
+    for (int k = 0; k < spl; k++)
+      for (int i = 0; i < nctx; i++) enqueue_any(ctxs[i]);
+  }
+  hipError_t el = hipGetLastError();
+  e = hipStreamEndCapture(st, graph);
+  for (int i = 0; i < nctx; i++) ctxs[i]->step = saved[i], ctxs[i]->stream = own[i];
+  cleanup();
+  if (ef != hipSuccess)
+    return fail(IB_E_DEVICE, "fork/join during capture failed: %s", hipGetErrorString(ef));
+  if (el != hipSuccess)
+    return fail(IB_E_DEVICE, "kernel launch during capture failed: %s", hipGetErrorString(el));
+  if (e != hipSuccess || !*graph)
+    return fail(IB_E_DEVICE, "stream capture failed: %s", hipGetErrorString(e));
+  return IB_OK;
+}
+
+extern "C" ib_status ib_graph_create(ib_graph **out, ib_ctx *const *ctxs, int32_t nctx,
+                                     int32_t steps_per_launch, int32_t flags, void *hip_stream) {
+  if (!out) return fail(IB_E_INVALID, "null graph output");
+  *out = nullptr;
+  if (!ctxs || nctx < 1) return fail(IB_E_INVALID, "no contexts");
+  if (steps_per_launch < 1) return fail(IB_E_INVALID, "steps_per_launch < 1");
+  if (flags & ~IB_GRAPH_BRANCHES) return fail(IB_E_INVALID, "unknown graph flags %d", flags);
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (!st) return fail(IB_E_INVALID, "graph capture needs a created stream, not the null stream");
+  for (int i = 0; i < nctx; i++) {
+    ib_ctx *c = ctxs[i];
+    if (!c) return fail(IB_E_INVALID, "null context %d", i);
+    for (int j = 0; j < i; j++)
+      if (ctxs[j] == c) return fail(IB_E_INVALID, "context %d listed twice", i);
+    if (c->stream != st) return fail(IB_E_INVALID, "context %d uses another stream", i);
+    if (c->prof) return fail(IB_E_STATE, "context %d is profiling", i);
+    if (c->step < 1)
+      return fail(IB_E_STATE, "context %d is at step 0: take the first step with ib_step", i);
+    const int period = c->prm.rotate_split ? c->dim : 1;
+    if (steps_per_launch % period != 0)
+      return fail(IB_E_INVALID, "steps_per_launch must be a multiple of %d (context %d)",
+                  period, i);
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  hipGraph_t graph = nullptr;
+  ib_status s = capture_steps(ctxs, nctx, steps_per_launch, st, flags, &graph);
+  if (s != IB_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return s;
+  }
+  hipGraphExec_t exec = nullptr;
+  hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return fail(IB_E_DEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+  }
+  ib_graph *g = new ib_graph();
+  g->ctx.assign(ctxs, ctxs + nctx);
+  g->spl = steps_per_launch;
+  g->stream = st;
+  g->graph = graph;
+  g->exec = exec;
+  *out = g;
+  return IB_OK;
+}
+
+extern "C" ib_status ib_graph_launch(ib_graph *g, int32_t nlaunches) {
+  if (!g) return fail(IB_E_STATE, "null graph");
+  if (nlaunches < 0) return fail(IB_E_INVALID, "nlaunches < 0");
+  for (int32_t i = 0; i < nlaunches; i++) {
+    HIP_TRY(hipGraphLaunch(g->exec, g->stream));
+    for (ib_ctx *c : g->ctx) c->step += g->spl;
+  }
+  return IB_OK;
+}
+
+extern "C" ib_status ib_graph_destroy(ib_graph *g) {
+  if (!g) return IB_OK;
+  (void)hipStreamSynchronize(g->stream);
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  delete g;
   return IB_OK;
 }

@@ -157,6 +157,8 @@ struct InterpArgs {
   double *U;          // [DIM][np]  interpolated velocity (or U^{n-1} in place)
   double *Xn1, *Xh;   // [DIM][np]  (evolve only)
   int *flag;          // set to 1 on a non-finite X^{n+1}
+  const int *layer;   // 2-D batches: layer of each point (null: layer 0)
+  const double *dt_layer;  // 2-D batches: time step of each layer (null: dt)
   int64_t np;
   Grid g;
   double inv_h, dt;
@@ -169,6 +171,7 @@ __global__ void __launch_bounds__(256) k_interp(InterpArgs<T, DIM> a) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int c = blockIdx.y;
   if (k >= a.np) return;
+  const int64_t lay = (DIM == 2 && a.layer) ? a.layer[k] : 0;
   const int32_t nn[3] = {a.g.n0, a.g.n1, a.g.n2};
   C w[3][4];
   int b[3];
@@ -200,7 +203,7 @@ __global__ void __launch_bounds__(256) k_interp(InterpArgs<T, DIM> a) {
     for (int t1 = 0; t1 < 4; t1++) {
       int64_t jj = b[1] + t1;
       jj -= jj >= nn[1] ? nn[1] : 0;
-      const T *row = uc + jj * nn[0];
+      const T *row = uc + (lay * nn[1] + jj) * nn[0];
       C acc0 = 0;
       for (int t0 = 0; t0 < 4; t0++) {
         int64_t ii = b[0] + t0;
@@ -217,7 +220,8 @@ __global__ void __launch_bounds__(256) k_interp(InterpArgs<T, DIM> a) {
     return;
   }
   const double x = a.X[o];
-  const double xn1 = a.first ? x + a.dt * U : x + a.dt * (1.5 * U - 0.5 * a.U[o]);
+  const double dt = a.dt_layer ? a.dt_layer[lay] : a.dt;
+  const double xn1 = a.first ? x + dt * U : x + dt * (1.5 * U - 0.5 * a.U[o]);
   a.U[o] = U;
   a.Xn1[o] = xn1;
   a.Xh[o] = 0.5 * (xn1 + x);
@@ -294,9 +298,10 @@ __device__ __forceinline__ int anchor_cell(double x, double inv_h, int n) {
   return wrap_cell((int)floor(xi) - 1, n);
 }
 
+// (2-D batches: the third tile index is the point's layer.)
 template <int DIM>
-__global__ void __launch_bounds__(256) k_bin(const double *X, int64_t np, Grid g,
-                                              TileGrid tg, double inv_h, int *count,
+__global__ void __launch_bounds__(256) k_bin(const double *X, const int *layer, int64_t np,
+                                              Grid g, TileGrid tg, double inv_h, int *count,
                                               int *tile_of, int *rank_of) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= np) return;
@@ -306,6 +311,7 @@ __global__ void __launch_bounds__(256) k_bin(const double *X, int64_t np, Grid g
     t += (anchor_cell(X[ax * np + k], inv_h, nn[ax]) / TS) * mul;
     mul *= tg.nt[ax];
   }
+  if (DIM == 2 && layer) t += (int64_t)layer[k] * mul;
   tile_of[k] = (int)t;
   rank_of[k] = atomicAdd(&count[t], 1);
 }
@@ -439,11 +445,11 @@ __global__ void __launch_bounds__(256) k_touch(const int *start, int *flag, int 
   if (t >= tg.ntiles) return;
   const int32_t nn[3] = {g.n0, g.n1, g.n2};
   const int tc[3] = {(int)(t % tg.nt[0]), (int)((t / tg.nt[0]) % tg.nt[1]),
-                     DIM == 3 ? (int)(t / ((int64_t)tg.nt[0] * tg.nt[1])) : 0};
+                     (int)(t / ((int64_t)tg.nt[0] * tg.nt[1]))};
   int lst[3][3], len[3];
   for (int ax = 0; ax < 3; ax++) {
     if (ax >= DIM) {
-      lst[ax][0] = 0;
+      lst[ax][0] = tc[ax];  // 2-D: the tile's own layer
       len[ax] = 1;
     } else {
       len[ax] = source_tiles(tc[ax] * TS, min(nn[ax], tc[ax] * TS + TS), nn[ax], lst[ax]);
@@ -485,16 +491,16 @@ __global__ void __launch_bounds__(256) k_spread_tiles(SpreadArgs<T, DIM> a) {
   for (int e = blockIdx.x; e < ntodo; e += gridDim.x) {
     const int64_t t = a.list[e];
     const int tc[3] = {(int)(t % a.tg.nt[0]), (int)((t / a.tg.nt[0]) % a.tg.nt[1]),
-                       DIM == 3 ? (int)(t / ((int64_t)a.tg.nt[0] * a.tg.nt[1])) : 0};
+                       (int)(t / ((int64_t)a.tg.nt[0] * a.tg.nt[1]))};
     int lo[3], hi[3];
     for (int ax = 0; ax < 3; ax++) {
-      lo[ax] = ax < DIM ? tc[ax] * TS : 0;
-      hi[ax] = ax < DIM ? min(nn[ax], lo[ax] + TS) : 1;
+      lo[ax] = ax < DIM ? tc[ax] * TS : tc[ax];  // 2-D: the tile's layer
+      hi[ax] = ax < DIM ? min(nn[ax], lo[ax] + TS) : lo[ax] + 1;
     }
     if (threadIdx.x < 3) {
       const int ax = threadIdx.x;
       if (ax >= DIM) {
-        s_list[ax][0] = 0;
+        s_list[ax][0] = tc[ax];
         s_len[ax] = 1;
       } else {
         int l3[3];
@@ -538,7 +544,7 @@ __global__ void __launch_bounds__(256) k_spread_tiles(SpreadArgs<T, DIM> a) {
         bool any = true;
         for (int ax = 0; ax < 3; ax++) {
           if (ax >= DIM) {
-            b[ax] = 0;
+            b[ax] = lo[ax];  // 2-D: the tile's layer
             tlo[ax] = 0;
             thi[ax] = 1;
             continue;
@@ -561,7 +567,7 @@ __global__ void __launch_bounds__(256) k_spread_tiles(SpreadArgs<T, DIM> a) {
         if (!any) continue;
         const C val = a.st.val[c * np + k];
         for (int t2 = tlo[2]; t2 < thi[2]; t2++) {
-          int kk = 0;
+          int kk = b[2];
           C rz = C(1);
           if (DIM == 3) {
             kk = b[2] + t2;
@@ -616,6 +622,7 @@ struct ExplicitArgs {
   const double *p;
   const T *psi;
   const int *flag;  // per spreading tile: 1 if f holds force there
+  const double *dt_layer;  // 2-D batches: time step of each layer (null: dt)
   Grid g;
   TileGrid tg;
   double inv_h, inv_h2, dt, mu, inv_rho;
@@ -642,8 +649,10 @@ __global__ void __launch_bounds__(256) k_explicit(ExplicitArgs<T, DIM> a) {
     dp[2] = dm[2] = 0;
   }
   const double ps0 = a.p[idx] + (double)a.psi[idx];
-  const int64_t tile = i / TS + (int64_t)a.tg.nt[0] * (j / TS + (int64_t)a.tg.nt[1] * (k / TS));
+  const int64_t tile =
+      i / TS + (int64_t)a.tg.nt[0] * (j / TS + (int64_t)a.tg.nt[1] * (DIM == 3 ? k / TS : k));
   const bool forced = a.flag[tile] != 0;
+  const C dt = (C)((DIM == 2 && a.dt_layer) ? a.dt_layer[k] : a.dt);
 #pragma unroll
   for (int ci = 0; ci < DIM; ci++) {
     const T *__restrict__ ui = a.u[ci];
@@ -671,7 +680,7 @@ __global__ void __launch_bounds__(256) k_explicit(ExplicitArgs<T, DIM> a) {
     const C gp = (C)((ps0 - psm) * a.inv_h);
     const C Nh = a.first ? N : C(1.5) * N - C(0.5) * (C)a.nl[ci][idx];
     const C fc = forced ? (C)a.f[ci][idx] : C(0);
-    const C d = (C)a.dt * (-Nh + ((C)a.mu * lap * (C)a.inv_h2 - gp + fc) * (C)a.inv_rho);
+    const C d = dt * (-Nh + ((C)a.mu * lap * (C)a.inv_h2 - gp + fc) * (C)a.inv_rho);
     a.delta[ci][idx] = (T)d;
     a.nl[ci][idx] = (T)N;
   }
@@ -887,6 +896,7 @@ struct SweepArgs {
   T *divp;             // PFINAL: D.u^n in, D.u^{n+1} out
   double *p;           // PFINAL: p += x - chi mu (divn + divp)/2
   double alpha, inv_c; // factored-form coefficients (inv_c may carry a rhs scale)
+  const double *alpha_layer, *invc_layer;  // 2-D batches: per-layer coefficients
   double half_chi_mu;  // PFINAL
   Grid g;
   int32_t G;           // threads per line (x kernel: power of two <= 64)
@@ -969,7 +979,9 @@ __global__ void __launch_bounds__(256) k_sweep_x(SweepArgs<T> a) {
   const int64_t s = (int64_t)lane * M;
   const int cnt = (int)(s >= N ? 0 : (N - s < M ? N - s : M));
   const int64_t base = line * N;
-  const double al = a.alpha, ic = a.inv_c;
+  const int64_t lay = line / a.g.n1;
+  const double al = a.alpha_layer ? a.alpha_layer[lay] : a.alpha;
+  const double ic = a.invc_layer ? a.invc_layer[lay] : a.inv_c;
 
   double r[M];
   // epilogue operands are fetched together with the right-hand side so the
@@ -1119,7 +1131,9 @@ __global__ void __launch_bounds__(LB) k_sweep_s(SweepArgs<T> a, int axis) {
   const int64_t s = (int64_t)g * M;
   const int64_t base = (axis == 1 ? xs + other * n0 * n1 : xs + other * n0) + s * stride;
   const int cnt = (int)(s >= N ? 0 : (N - s < M ? N - s : M));
-  const double al = a.alpha, ic = a.inv_c;
+  // 2-D batches sweep y only, so the remaining index is the layer
+  const double al = a.alpha_layer ? a.alpha_layer[other] : a.alpha;
+  const double ic = a.invc_layer ? a.invc_layer[other] : a.inv_c;
   const int slot = g * TX + tx;
 
   double r[M];
@@ -1253,7 +1267,9 @@ __global__ void __launch_bounds__(LB) k_sweep_sb(SweepArgs<T> a, int axis) {
   const bool live = x0 + tx < n0;
   const int s = g * M;
   const int cnt = s >= N ? 0 : (N - s < M ? N - s : M);
-  const R al = (R)a.alpha, ic = (R)a.inv_c;
+  // 2-D batches sweep y only, so the remaining index is the layer
+  const R al = (R)(a.alpha_layer ? a.alpha_layer[other] : a.alpha);
+  const R ic = (R)(a.invc_layer ? a.invc_layer[other] : a.inv_c);
   const int slot = g * TX + tx;
 
   R r[M];

@@ -21,6 +21,7 @@ IB_OK, IB_E_INVALID, IB_E_UNSUPPORTED, IB_E_DEVICE, IB_E_NONFINITE, IB_E_STATE =
 IB_F64, IB_F32 = 0, 1
 IB_PREC_FP64, IB_PREC_MIXED = 0, 1
 IB_FLAG_NO_ADVECTION = 1
+IB_GRAPH_BRANCHES = 1
 
 _vp = ctypes.c_void_p
 _dp = ctypes.POINTER(ctypes.c_double)
@@ -31,7 +32,7 @@ class GridParams(ctypes.Structure):
                 ("rho", ctypes.c_double), ("mu", ctypes.c_double), ("dt", ctypes.c_double),
                 ("chi", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("rotate_split", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("step0", ctypes.c_int64)]
+                ("step0", ctypes.c_int64), ("layer_dt", _dp)]
 
 
 class Buffers(ctypes.Structure):
@@ -43,7 +44,7 @@ class Buffers(ctypes.Structure):
 class Structure(ctypes.Structure):
     _fields_ = [("n_links", ctypes.c_int64), ("a", ctypes.POINTER(ctypes.c_int32)),
                 ("b", ctypes.POINTER(ctypes.c_int32)), ("kappa", _dp), ("l0", _dp),
-                ("w", _dp)]
+                ("w", _dp), ("layer", ctypes.POINTER(ctypes.c_int32))]
 
 
 class IBError(RuntimeError):
@@ -77,8 +78,17 @@ def _load():
     L.ib_profile_name.argtypes = [ctypes.c_int32]
     L.ib_profile_read.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(ctypes.c_int64)]
+    L.ib_tune.argtypes = [_vp, ctypes.c_int32]
+    _ip = ctypes.POINTER(ctypes.c_int32)
+    L.ib_tune_read.argtypes = [_vp, ctypes.c_int32, ctypes.c_int32, _ip, _ip, _ip]
+    L.ib_graph_create.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int32,
+                                  ctypes.c_int32, ctypes.c_int32, _vp]
+    L.ib_graph_launch.argtypes = [_vp, ctypes.c_int32]
+    L.ib_graph_destroy.argtypes = [_vp]
     for f in ("ib_workspace_size", "ib_init", "ib_step", "ib_sync", "ib_spread", "ib_interp",
-              "ib_force", "ib_line_solve", "ib_destroy", "ib_profile_enable", "ib_profile_read"):
+              "ib_force", "ib_line_solve", "ib_destroy", "ib_profile_enable", "ib_profile_read",
+              "ib_tune", "ib_tune_read", "ib_graph_create", "ib_graph_launch",
+              "ib_graph_destroy"):
         getattr(L, f).restype = ctypes.c_int
     return L
 
@@ -87,7 +97,8 @@ lib = _load()
 
 EXPORTED = ("ib_workspace_size", "ib_init", "ib_step", "ib_sync", "ib_spread", "ib_interp",
             "ib_force", "ib_line_solve", "ib_destroy", "ib_last_error", "ib_profile_enable",
-            "ib_profile_count", "ib_profile_name", "ib_profile_read")
+            "ib_profile_count", "ib_profile_name", "ib_profile_read", "ib_tune", "ib_tune_read",
+            "ib_graph_create", "ib_graph_launch", "ib_graph_destroy")
 
 
 def check(status: int):
@@ -137,12 +148,13 @@ class Config:
     precision: int = IB_PREC_FP64
     rotate_split: bool = True
     no_advection: bool = False
+    layer_dt: tuple = None  # 2-D batches: time step of each layer
 
     def params(self, step0: int = 0) -> GridParams:
         P = GridParams()
         P.dim = self.dim
         nn = list(self.n) + [1] * (3 - len(self.n))
-        if self.dim == 2:
+        if self.dim == 2 and len(self.n) < 3:
             nn[2] = 1
         for a in range(3):
             P.n[a] = nn[a]
@@ -151,6 +163,9 @@ class Config:
         P.rotate_split = 1 if self.rotate_split else 0
         P.flags = IB_FLAG_NO_ADVECTION if self.no_advection else 0
         P.step0 = step0
+        if self.layer_dt is not None:
+            self._ldt = np.ascontiguousarray(self.layer_dt, dtype=np.float64)
+            P.layer_dt = self._ldt.ctypes.data_as(_dp)
         return P
 
     @property
@@ -160,7 +175,7 @@ class Config:
     @property
     def shape(self):
         nn = list(self.n) + [1] * (3 - len(self.n))
-        return (nn[2] if self.dim == 3 else 1, nn[1], nn[0])
+        return (nn[2], nn[1], nn[0])
 
 
 class Simulation:
@@ -211,6 +226,9 @@ class Simulation:
         self._host = [np.ascontiguousarray(a, dtype=np.int32), np.ascontiguousarray(b, dtype=np.int32),
                       np.ascontiguousarray(k, dtype=np.float64), np.ascontiguousarray(l0, dtype=np.float64),
                       np.ascontiguousarray(structure.w, dtype=np.float64)]
+        layer = getattr(structure, "layer", None)
+        if layer is not None:
+            self._host.append(np.ascontiguousarray(layer, dtype=np.int32))
         S = Structure()
         S.n_links = len(self._host[0])
         S.a = self._host[0].ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
@@ -218,6 +236,8 @@ class Simulation:
         S.kappa = self._host[2].ctypes.data_as(_dp)
         S.l0 = self._host[3].ctypes.data_as(_dp)
         S.w = self._host[4].ctypes.data_as(_dp)
+        if len(self._host) > 5:
+            S.layer = self._host[5].ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
         self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
         ctx = _vp()
         check(lib.ib_init(ctypes.byref(ctx), ctypes.byref(P), ctypes.byref(B), ctypes.byref(S),
@@ -257,6 +277,17 @@ class Simulation:
         check(lib.ib_force(self.ctx, _ptr(X), _ptr(F)))
         return F
 
+    # -- tuning --------------------------------------------------------------
+    def tune(self, reps: int = 3):
+        check(lib.ib_tune(self.ctx, reps))
+        out = {}
+        for axis in range(self.cfg.dim):
+            for r64 in (0, 1):
+                v = [ctypes.c_int32() for _ in range(3)]
+                check(lib.ib_tune_read(self.ctx, axis, r64, *[ctypes.byref(x) for x in v]))
+                out[(axis, r64)] = tuple(x.value for x in v)
+        return out
+
     # -- profiling ---------------------------------------------------------
     def profile(self, enable: bool = True):
         check(lib.ib_profile_enable(self.ctx, 1 if enable else 0))
@@ -283,6 +314,36 @@ class Simulation:
         if getattr(self, "ctx", None):
             lib.ib_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Graph:
+    """One hipGraph replaying `steps_per_launch` steps of several simulations
+    that share a (non-null) stream (ib_graph_create / ib_graph_launch).
+    branches=True records each simulation as an independent graph branch."""
+
+    def __init__(self, sims, steps_per_launch: int, branches: bool = False, stream=None):
+        self.sims = list(sims)
+        arr = (_vp * len(self.sims))(*[s.ctx.value for s in self.sims])
+        st = stream if stream is not None else self.sims[0].stream
+        g = _vp()
+        check(lib.ib_graph_create(ctypes.byref(g), arr, len(self.sims), steps_per_launch,
+                                  IB_GRAPH_BRANCHES if branches else 0, _vp(st.cuda_stream)))
+        self.g = g
+        self.steps_per_launch = steps_per_launch
+
+    def launch(self, nlaunches: int = 1):
+        check(lib.ib_graph_launch(self.g, nlaunches))
+
+    def close(self):
+        if getattr(self, "g", None):
+            lib.ib_graph_destroy(self.g)
+            self.g = None
 
     def __del__(self):
         try:

@@ -281,3 +281,50 @@ def config_shell_256(steps: int = 200, n: int = 256, npts: int = 65536) -> Workl
     link weights, see ellipsoid_shell), fluid at rest."""
     return Workload("shell3d_%d" % n, 3, (n, n, n), 1.0, 0.01, 5e-4, steps,
                     ellipsoid_shell(npts, weights="cotan"), zero_velocity(3, (n, n, n)))
+
+
+# ------------------------------------------------------- batched ensemble --
+
+def stiffness_time_step(sigma: float) -> float:
+    """Time step for a thin ellipse of stiffness sigma, from the step sizes the
+    paper uses for its thin-ellipse runs at N = 512 (Sec. "Thin Ellipse":
+    0.08/512, 0.04/512 and 0.01/512 for sigma = 0.1, 1 and 10), taken
+    piecewise linear in (log10 sigma, log2 dt), with the last factor (1/4 per
+    decade) continued above sigma = 10 and the first (1/2 per decade) below
+    sigma = 0.1."""
+    ls = math.log10(sigma)
+    if ls <= 0.0:
+        l2 = math.log2(0.04 / 512) - ls * 1.0          # x2 per decade downwards
+    else:
+        l2 = math.log2(0.04 / 512) - ls * 2.0          # x1/4 per decade upwards
+    return 2.0 ** l2
+
+
+@dataclass
+class EnsembleMember:
+    """One independent 2-D problem of a batched ensemble."""
+    index: int
+    n: int
+    sigma: float
+    dt: float
+    structure: Structure
+
+
+def config_ensemble(nsims: int = 64, seed: int = 4, steps: int = 500,
+                    sizes=(128, 192, 256, 384, 512), sigma_range=(0.1, 100.0),
+                    points_per_cell: int = 4, rho: float = 1.0, mu: float = 0.01):
+    """Batched ensemble of independent 2-D periodic problems: grid size drawn
+    uniformly from `sizes`, a centred 0.3 x 0.2 ellipse with 4N points and
+    stiffness log-uniform in sigma_range, fluid at rest, time step from
+    stiffness_time_step.  Returns (members, dict of shared parameters)."""
+    rng = np.random.default_rng(seed)
+    ns = rng.choice(np.asarray(sizes), size=nsims)
+    lo, hi = math.log(sigma_range[0]), math.log(sigma_range[1])
+    sig = np.exp(rng.uniform(lo, hi, size=nsims))
+    members = []
+    for i in range(nsims):
+        n = int(ns[i])
+        sg = float(sig[i])
+        members.append(EnsembleMember(i, n, sg, stiffness_time_step(sg),
+                                      ellipse(points_per_cell * n, 0.3, 0.2, sg)))
+    return members, {"rho": rho, "mu": mu, "steps": steps, "chi": 0.6}

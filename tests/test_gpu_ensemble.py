@@ -1,0 +1,215 @@
+"""Batched ensembles of independent 2-D problems (uneven grid sizes and
+stiffnesses, each with its own time step) through the C ABI: every member
+matches its own oracle run, graph replays match eager stepping, the autotuner
+picks valid tile shapes that keep parity, and bad layer tables are rejected."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1305_3976_amd import ensemble, ibgm, inputs
+from helpers import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+MIXED_TOL = 1e-5
+MIXED_PSI_TOL = 1e-4
+SMALL_SIZES = (48, 64, 96)
+
+
+def small_members(nsims=7, seed=11, sizes=SMALL_SIZES):
+    members, shared = inputs.config_ensemble(nsims=nsims, seed=seed, sizes=sizes)
+    return members, shared
+
+
+def oracle_member(m, shared, steps):
+    n = m.n
+    P = oracle.make_params(2, (n, n, 1), 1.0 / n, rho=shared["rho"], mu=shared["mu"], dt=m.dt,
+                           chi=shared["chi"])
+    u0 = [np.zeros((1, n, n)) for _ in range(2)]
+    S = m.structure
+    return oracle.Sim(P, u0, S.X, S.links, S.w).advance(steps)
+
+
+def state_errors(u, p, psi, X, ref_u, ref_p, ref_psi, ref_X):
+    e = {"u%d" % c: rel_l2(u[c], ref_u[c]) for c in range(2)}
+    e["p"] = rel_l2(p, ref_p)
+    # psi is the per-step increment of p: with the small time steps of stiff
+    # members it is orders of magnitude below p, and its rounding error scales
+    # with p (the pressure it updates), so it is measured against that scale
+    scale = max(np.linalg.norm(ref_psi), np.linalg.norm(ref_p), 1e-30)
+    e["psi"] = float(np.linalg.norm(np.asarray(psi) - ref_psi) / scale)
+    e["X"] = rel_l2(X, ref_X)
+    return e
+
+
+def member_errors(ens, m, o):
+    st = ens.member_state(m)
+    return state_errors(st["u"], st["p"], st["psi"], st["X"],
+                        [o.u[c][0] for c in range(2)], o.p[0], o.psi[0], o.X)
+
+
+def mixed_p_tolerance(m, o, steps):
+    """Bar for p under the mixed policy.  Storing u^{n+1} in FP32 perturbs it by
+    about eps32 |u| per step; the psi sweeps answer the divergence of that
+    grid-scale noise with a pressure of about (rho/dt) eps32 |u| h, which p
+    accumulates as a random walk.  The relative p error is therefore about
+    eps32 sqrt(steps) rho max|u| h / (dt rms(p)); with the stiffness-matched
+    time steps of the ensemble that is 1e-5 to 3e-5 for every member, so the
+    1e-5 bar holds for u, psi and X while p is held to 10 x this estimate."""
+    n = m.n
+    est = 2.0 ** -24 * np.sqrt(steps) * max(np.abs(o.u[c]).max() for c in range(2)) / n \
+        / (m.dt * np.sqrt(np.mean(o.p ** 2)))
+    return max(MIXED_TOL, 10.0 * est)
+
+
+@pytest.fixture(scope="module")
+def small_oracle():
+    members, shared = small_members()
+    steps = 100
+    return members, shared, steps, [oracle_member(m, shared, steps) for m in members]
+
+
+@pytest.mark.parametrize("precision,tol", [(0, FP64_TOL), (1, MIXED_TOL)])
+@pytest.mark.parametrize("branches", [False, True])
+def test_members_match_oracle(small_oracle, precision, tol, branches):
+    members, shared, steps, refs = small_oracle
+    assert len({m.n for m in members}) == len(SMALL_SIZES)   # every class present
+    ens = ensemble.Ensemble(members, rho=shared["rho"], mu=shared["mu"], precision=precision)
+    ens.run(steps, steps_per_launch=4, branches=branches)   # 1 eager + 24 x 4 graph + 3 eager
+    assert ens.sync() == [steps] * len(ens.sims)
+    for m, o in zip(members, refs):
+        errs = member_errors(ens, m, o)
+        print("member", m.index, "n", m.n, "sigma %.3g" % m.sigma, errs)
+        for k, e in errs.items():
+            lim = tol
+            if precision == 1 and k == "psi":
+                lim = MIXED_PSI_TOL
+            if precision == 1 and k == "p":
+                lim = mixed_p_tolerance(m, o, steps)
+            assert e <= lim, (m.index, k, e, lim)
+    ens.close()
+
+
+def all_states(ens):
+    return [s.state() for s in ens.sims]
+
+
+@pytest.mark.parametrize("branches", [False, True])
+def test_graph_replays_match_eager(branches):
+    members, shared = small_members(nsims=5, seed=12)
+    mk = lambda: ensemble.Ensemble(members, rho=shared["rho"], mu=shared["mu"], precision=0)
+    eager, graphed = mk(), mk()
+    eager.step(1)
+    graphed.step(1)
+    graphed.capture(4, branches=branches)
+    for r in range(4):
+        eager.step(4)
+        graphed.launch(1)
+        torch.cuda.synchronize()
+        for sa, sb in zip(all_states(eager), all_states(graphed)):
+            errs = state_errors(sb["u"], sb["p"], sb["psi"], sb["X"],
+                                sa["u"], sa["p"], sa["psi"], sa["X"])
+            # equal up to the order of the atomic additions of spreading
+            assert max(errs.values()) <= 1e-13, (r, errs)
+        # the program's own eager work between replays
+        eager.step(2)
+        graphed.step(2)
+    assert eager.sync() == graphed.sync() == [1 + 4 * 6] * len(eager.sims)
+    eager.close()
+    graphed.close()
+
+
+def test_graph_rejects_bad_use():
+    members, shared = small_members(nsims=3, seed=13)
+    ens = ensemble.Ensemble(members, rho=shared["rho"], mu=shared["mu"], precision=0)
+    with pytest.raises(ibgm.IBError):          # step 0 cannot be captured
+        ens.capture(2)
+    ens.step(1)
+    with pytest.raises(ibgm.IBError):          # not a multiple of the rotation period
+        ens.capture(3)
+    other = ibgm.Simulation(ibgm.Config(2, (64, 64), 1.0 / 64, dt=1e-4),
+                            [np.zeros((1, 64, 64))] * 2, inputs.ellipse(64, 0.3, 0.2, 1.0))
+    other.step(1)
+    with pytest.raises(ibgm.IBError):          # another stream
+        ibgm.Graph(ens.sims + [other], 2, stream=ens.stream)
+    other.close()
+    ens.close()
+
+
+def test_tune_picks_valid_shapes_and_keeps_parity():
+    members, shared = small_members(nsims=4, seed=14, sizes=(64, 96))
+    steps = 12
+    refs = [oracle_member(m, shared, steps) for m in members]
+    ens = ensemble.Ensemble(members, rho=shared["rho"], mu=shared["mu"], precision=0)
+    picks = ens.tune(reps=2)
+    for (n, group), pk in zip(ens.classes, picks):
+        for (axis, r64), (xm, tx, sm) in pk.items():
+            if axis == 0:
+                assert xm in (1, 2, 4, 6, 8, 12, 16, 32) and (n + xm - 1) // xm <= 64
+            else:
+                assert tx in (32, 64) and sm in (16, 32) and tx * ((n + sm - 1) // sm) <= 1024
+    ens.run(steps, steps_per_launch=2)
+    for m, o in zip(members, refs):
+        errs = member_errors(ens, m, o)
+        assert max(errs.values()) <= FP64_TOL, (m.index, errs)
+    ens.close()
+
+
+def test_tune_3d_keeps_results():
+    w = inputs.config_shell_256(steps=6, n=64, npts=2048)
+    w.n = (64, 48, 40)
+    w.u0 = inputs.zero_velocity(3, w.n)
+    runs = []
+    for tune in (False, True):
+        cfg = ibgm.Config(3, w.n, w.h, rho=w.rho, mu=w.mu, dt=w.dt, precision=0)
+        s = ibgm.Simulation(cfg, w.u0, w.structure)
+        if tune:
+            pk = s.tune(reps=2)
+            assert set(pk) == {(a, r) for a in range(3) for r in (0, 1)}
+        s.step(w.steps)
+        s.sync()
+        runs.append(s.state())
+        s.close()
+    for key in ("p", "X"):
+        assert rel_l2(runs[1][key], runs[0][key]) <= 1e-13, key
+
+
+def test_layer_tables_rejected():
+    n = 64
+    a = inputs.ellipse(64, 0.3, 0.2, 1.0)
+    b = inputs.ellipse(64, 0.2, 0.1, 1.0)
+
+    class Batch:
+        pass
+
+    def batch(layer, links=None):
+        B = Batch()
+        B.X = np.concatenate([a.X, b.X], axis=1)
+        la, lb, lk, ll = a.links
+        ma, mb, mk, ml = b.links
+        B.links = links or (np.concatenate([la, ma + 64]).astype(np.int32),
+                            np.concatenate([lb, mb + 64]).astype(np.int32),
+                            np.concatenate([lk, mk]), np.concatenate([ll, ml]))
+        B.w = np.concatenate([a.w, b.w])
+        B.layer = layer
+        return B
+
+    ok_layer = np.repeat(np.arange(2, dtype=np.int32), 64)
+    cfg = ibgm.Config(2, (n, n, 2), 1.0 / n, dt=1e-4, layer_dt=(1e-4, 2e-4))
+    u0 = [np.zeros(cfg.shape)] * 2
+    ibgm.Simulation(cfg, u0, batch(ok_layer)).close()
+    bad = ok_layer.copy()
+    bad[5] = 2                                             # layer out of range
+    with pytest.raises(ibgm.IBError):
+        ibgm.Simulation(cfg, u0, batch(bad))
+    cross = ok_layer.copy()
+    cross[0] = 1                                           # a link joins two layers
+    with pytest.raises(ibgm.IBError):
+        ibgm.Simulation(cfg, u0, batch(cross))
+    with pytest.raises(ibgm.IBError):                      # non-positive layer step
+        ibgm.Simulation(ibgm.Config(2, (n, n, 2), 1.0 / n, dt=1e-4, layer_dt=(1e-4, 0.0)),
+                        u0, batch(ok_layer))
+    with pytest.raises(ibgm.IBError):                      # a batch without a layer table
+        ibgm.Simulation(cfg, u0, batch(None))
