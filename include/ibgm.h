@@ -135,6 +135,14 @@ ib_status ib_init(ib_ctx **out, const ib_grid_params *prm,
  * sweeps (eq:PenaltyStepPart1/2) and the pressure update.  Asynchronous. */
 ib_status ib_step(ib_ctx *ctx, int32_t nsteps);
 
+/* Continue from state the caller has written into the context's buffers
+ * (u, nl_prev, psi, div_prev, p, X, U_prev; same addresses) as step index
+ * step0 >= 0.  step0 = 0 applies the start-up rules of ib_init: it enqueues
+ * div_prev = D.u^0, and the next step takes forward Euler for X and
+ * N^{1/2} = N(u^0).  Asynchronous; the structure is kept.  A graph
+ * captured from this context before the restart must be created again. */
+ib_status ib_restart(ib_ctx *ctx, int64_t step0);
+
 /* Wait for the stream; report the step index and IB_E_NONFINITE if any
  * position became non-finite since init. */
 ib_status ib_sync(ib_ctx *ctx, int64_t *step_index);

@@ -2,8 +2,10 @@
 
     python -m paper_1305_3976_amd.build
 
-The library is one translation unit (csrc/ibgm.hip including csrc/kernels.h)
-compiled for gfx950 only, with packed-FP32 instructions disabled.
+Two translation units, compiled in parallel for gfx950 only with packed-FP32
+instructions disabled, then linked into one shared library:
+  csrc/ibgm.hip     the IB-GM step (device code in csrc/kernels.h)
+  csrc/closure.hip  the learned-closure kernels (matrix-core convolutions)
 """
 from __future__ import annotations
 
@@ -14,9 +16,13 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "ibgm.hip")
+SOURCES = [os.path.join(HERE, "csrc", "ibgm.hip"), os.path.join(HERE, "csrc", "closure.hip")]
 LIB = os.path.join(HERE, "libibgm.so")
 INCLUDE = os.path.join(ROOT, "include")
+OBJDIR = os.path.join(HERE, "_build")
+FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-Wno-unused-command-line-argument"]
 
 
 def hipcc() -> str:
@@ -27,17 +33,33 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False) -> str:
+    os.makedirs(OBJDIR, exist_ok=True)
+    cc = hipcc()
+    objs, procs = [], []
+    for src in SOURCES:
+        obj = os.path.join(OBJDIR, os.path.basename(src) + ".%d.o" % os.getpid())
+        cmd = [cc, *FLAGS, "-I", INCLUDE, "-I", os.path.join(HERE, "csrc"), "-c", "-o", obj, src]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT,
+                                            text=True)))
+        objs.append(obj)
+    failed = False
+    for src, p in procs:
+        out, _ = p.communicate()
+        if p.returncode != 0:
+            sys.stderr.write(out)
+            failed = True
+    if failed:
+        raise RuntimeError("hipcc failed compiling libibgm.so sources")
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-Wno-unused-command-line-argument",
-           "-I", INCLUDE, "-I", os.path.join(HERE, "csrc"), "-o", tmp, SRC]
-    if verbose:
-        print(" ".join(cmd), flush=True)
+    cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     res = subprocess.run(cmd, capture_output=True, text=True)
+    for o in objs:
+        os.remove(o)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libibgm.so")
+        raise RuntimeError("hipcc failed linking libibgm.so")
     os.replace(tmp, LIB)
     return LIB
 

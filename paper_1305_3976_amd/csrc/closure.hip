@@ -1,0 +1,647 @@
+// closure.hip -- the learned-closure kernels of libibgm.so (C ABI in
+// include/ibgm_closure.h): 3x3x3 convolutions on the gfx950 matrix cores
+// (v_mfma_f32_32x32x16_bf16: BF16 operands, FP32 accumulation), their two
+// gradients, the loss, Adam, and the MAC restriction / gather / apply steps
+// that connect the network to the IB-GM fields.
+//
+// Convolution as an implicit GEMM.  For one output row of 32 voxels along x
+// and one tap, the product [32 voxels x 16 input channels] x [16 x 32 output
+// channels] is one matrix-core instruction; 27 taps x (ci/16) of them build
+// the 32 x 32 output block.  A workgroup (4 waves) keeps every packed weight
+// fragment of the layer in LDS for its whole life and walks output tiles of
+// 32 x 4 x 2 voxels: it stages the tile's input halo (34 x 6 x 4 voxels, all
+// channels) in LDS, and each wave accumulates two rows.  Matrix-core lane
+// layout (32x32x16): lane l supplies A[row l%32][k 8(l/32)..+7] and
+// B[k 8(l/32)..+7][col l%32]; accumulator j of lane l is
+// D[8(j/4) + 4(l/32) + j%4][l%32].
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+
+#include "errors.h"
+#include "ibgm_closure.h"
+
+namespace {
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int TX = 32, TY = 4, TZ = 2;               // output tile (voxels)
+constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2;  // its input halo
+constexpr int NT = 256;                               // threads per workgroup
+constexpr int CO = 32;                                // output channels
+constexpr int WG_CONV = 256;                          // persistent workgroups (1 per CU)
+
+__device__ __forceinline__ int wrapi(int i, int n) {
+  i %= n;
+  return i < 0 ? i + n : i;
+}
+
+struct ConvArgs {
+  const bf16 *x;      // [B][D2][D1][D0][CI]
+  const bf16 *wp;     // packed fragments [27][CI/16][64][8]
+  const float *bias;  // [32] or null
+  const bf16 *mask;   // [B][E2][E1][E0][32] or null: output *= (mask > 0)
+  void *y;            // [B][E2][E1][E0][ystride]
+  int B, D0, D1, D2, E0, E1, E2;
+  int off, wrap;
+  int relu, out_f32, co_store, ystride;
+  int nt0, nt1, nt2, ntiles;
+};
+
+// Stage the input halo of the tile at (b, ox0, oy0, oz0) in LDS: voxel v of
+// the halo (x fastest) at byte v * VS, CI channels, zeros outside the input
+// unless the indices wrap.
+template <int CI, int VS>
+__device__ __forceinline__ void load_halo(unsigned char *sh, const bf16 *x, int b, int ox0,
+                                          int oy0, int oz0, int D0, int D1, int D2, int off,
+                                          int wrap) {
+  constexpr int CH = CI / 8;  // 16-byte chunks per voxel
+  for (int c = threadIdx.x; c < HX * HY * HZ * CH; c += NT) {
+    const int v = c / CH, part = c - v * CH;
+    const int hx = v % HX, hy = (v / HX) % HY, hz = v / (HX * HY);
+    int gx = ox0 + hx + off, gy = oy0 + hy + off, gz = oz0 + hz + off;
+    uint4 val = make_uint4(0, 0, 0, 0);
+    bool in = true;
+    if (wrap) {
+      gx = wrapi(gx, D0), gy = wrapi(gy, D1), gz = wrapi(gz, D2);
+    } else {
+      in = gx >= 0 && gx < D0 && gy >= 0 && gy < D1 && gz >= 0 && gz < D2;
+    }
+    if (in) {
+      const size_t vox = (((size_t)b * D2 + gz) * D1 + gy) * D0 + gx;
+      val = *reinterpret_cast<const uint4 *>(x + vox * CI + part * 8);
+    }
+    *reinterpret_cast<uint4 *>(sh + v * VS + part * 16) = val;
+  }
+}
+
+template <int CI>
+__global__ __launch_bounds__(NT) void k_conv(ConvArgs a) {
+  constexpr int KS = CI / 16;
+  constexpr int VS = CI * 2 + 16;  // padded voxel stride in LDS (bytes)
+  __shared__ __align__(16) unsigned char sw[27 * KS * 64 * 16];
+  __shared__ __align__(16) unsigned char sh[HX * HY * HZ * VS];
+  for (int c = threadIdx.x; c < 27 * KS * 64; c += NT)
+    reinterpret_cast<uint4 *>(sw)[c] = reinterpret_cast<const uint4 *>(a.wp)[c];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 31, grp = lane >> 5;
+  const float bias = (a.bias && col < a.co_store) ? a.bias[col] : 0.f;
+  for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+    int r = tile;
+    const int t0 = r % a.nt0;
+    r /= a.nt0;
+    const int t1 = r % a.nt1;
+    r /= a.nt1;
+    const int t2 = r % a.nt2;
+    const int b = r / a.nt2;
+    const int ox0 = t0 * TX, oy0 = t1 * TY, oz0 = t2 * TZ;
+    __syncthreads();  // previous tile's reads of sh (and the weight copy) done
+    load_halo<CI, VS>(sh, a.x, b, ox0, oy0, oz0, a.D0, a.D1, a.D2, a.off, a.wrap);
+    __syncthreads();
+    f32x16 acc[2];
+    for (int mi = 0; mi < 2; mi++)
+      for (int j = 0; j < 16; j++) acc[mi][j] = 0.f;
+    // rows m = 2 wave + mi: (y, z) = (m % TY, m / TY)
+    const int m0 = 2 * wave;
+    const int my0 = m0 % TY, mz0 = m0 / TY;
+    const int my1 = (m0 + 1) % TY, mz1 = (m0 + 1) / TY;
+#pragma unroll 1
+    for (int t = 0; t < 27; t++) {
+      const int tz = t / 9, ty = (t / 3) % 3, tx = t % 3;
+      const int hx = col + tx;
+      const unsigned char *r0 = sh + (((mz0 + tz) * HY + my0 + ty) * HX + hx) * VS + grp * 16;
+      const unsigned char *r1 = sh + (((mz1 + tz) * HY + my1 + ty) * HX + hx) * VS + grp * 16;
+#pragma unroll
+      for (int ks = 0; ks < KS; ks++) {
+        const bf16x8 bw = *reinterpret_cast<const bf16x8 *>(sw + ((t * KS + ks) * 64 + lane) * 16);
+        const bf16x8 a0 = *reinterpret_cast<const bf16x8 *>(r0 + ks * 32);
+        const bf16x8 a1 = *reinterpret_cast<const bf16x8 *>(r1 + ks * 32);
+        acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, bw, acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, bw, acc[1], 0, 0, 0);
+      }
+    }
+    // epilogue: lane holds output channel `col` of 16 voxels per row
+    for (int mi = 0; mi < 2; mi++) {
+      const int oy = oy0 + (mi ? my1 : my0), oz = oz0 + (mi ? mz1 : mz0);
+      if (oy >= a.E1 || oz >= a.E2 || col >= a.co_store) continue;
+      const size_t rowv = (((size_t)b * a.E2 + oz) * a.E1 + oy) * a.E0;
+#pragma unroll
+      for (int j = 0; j < 16; j++) {
+        const int ox = ox0 + 8 * (j >> 2) + 4 * grp + (j & 3);
+        if (ox >= a.E0) continue;
+        const size_t vox = rowv + ox;
+        float v = acc[mi][j] + bias;
+        if (a.relu) v = fmaxf(v, 0.f);
+        if (a.mask && !((float)a.mask[vox * CO + col] > 0.f)) v = 0.f;
+        if (a.out_f32)
+          reinterpret_cast<float *>(a.y)[vox * a.ystride + col] = v;
+        else
+          reinterpret_cast<bf16 *>(a.y)[vox * a.ystride + col] = (bf16)v;
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------ weight gradient --
+
+struct WgradArgs {
+  const bf16 *x;   // layer input [B][D..][CI]
+  const bf16 *g;   // output gradient [B][E..][32]
+  float *part;     // [gridDim][27*32*32 + 32]
+  int B, D0, D1, D2, E0, E1, E2;
+  int off, wrap;
+  int nt0, nt1, nt2, ntiles;
+};
+
+// dW[t][ci][co] += sum over the tile's voxels p of x[p + t + off][ci] g[p][co]
+// as [ci x 16 voxels] x [16 voxels x co] products; wave w owns the taps
+// t = w, w + 4, ... (7 or 6 accumulators), wave 0 also sums g for the bias.
+template <int CI>
+__global__ __launch_bounds__(NT) void k_wgrad(WgradArgs a) {
+  constexpr int VS = CI * 2 + 16;
+  constexpr int GS = CO * 2 + 16;  // padded voxel stride of the gradient tile
+  __shared__ __align__(16) unsigned char sh[HX * HY * HZ * VS];
+  __shared__ __align__(16) unsigned char sg[TX * TY * TZ * GS];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row = lane & 31, grp = lane >> 5;
+  f32x16 acc[7];
+  for (int i = 0; i < 7; i++)
+    for (int j = 0; j < 16; j++) acc[i][j] = 0.f;
+  float bsum = 0.f;
+  const int ntap = wave < 3 ? 7 : 6;
+  for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+    int r = tile;
+    const int t0 = r % a.nt0;
+    r /= a.nt0;
+    const int t1 = r % a.nt1;
+    r /= a.nt1;
+    const int t2 = r % a.nt2;
+    const int b = r / a.nt2;
+    const int ox0 = t0 * TX, oy0 = t1 * TY, oz0 = t2 * TZ;
+    __syncthreads();
+    load_halo<CI, VS>(sh, a.x, b, ox0, oy0, oz0, a.D0, a.D1, a.D2, a.off, a.wrap);
+    // gradient tile, zeros for voxels outside the output
+    for (int c = threadIdx.x; c < TX * TY * TZ * 4; c += NT) {
+      const int v = c >> 2, part = c & 3;
+      const int vx = v % TX, vy = (v / TX) % TY, vz = v / (TX * TY);
+      const int ox = ox0 + vx, oy = oy0 + vy, oz = oz0 + vz;
+      uint4 val = make_uint4(0, 0, 0, 0);
+      if (ox < a.E0 && oy < a.E1 && oz < a.E2) {
+        const size_t vox = (((size_t)b * a.E2 + oz) * a.E1 + oy) * a.E0 + ox;
+        val = *reinterpret_cast<const uint4 *>(a.g + vox * CO + part * 8);
+      }
+      *reinterpret_cast<uint4 *>(sg + v * GS + part * 16) = val;
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int s = 0; s < TX * TY * TZ / 16; s++) {
+      // k-step s: 16 voxels of output row m = s / 2, x = (s % 2) 16 + 8 grp + e
+      const int m = s >> 1, my = m % TY, mz = m / TY;
+      const int xb = (s & 1) * 16 + 8 * grp;
+      bf16x8 bg;
+      const unsigned char *gp = sg + ((m * TX) + xb) * GS + row * 2;
+#pragma unroll
+      for (int e = 0; e < 8; e++) bg[e] = *reinterpret_cast<const bf16 *>(gp + e * GS);
+      if (wave == 0)
+#pragma unroll
+        for (int e = 0; e < 8; e++) bsum += (float)bg[e];
+#pragma unroll
+      for (int i = 0; i < 7; i++) {
+        if (i >= ntap) break;
+        const int t = wave + 4 * i;
+        const int tz = t / 9, ty = (t / 3) % 3, tx = t % 3;
+        bf16x8 ax;
+        if (row < CI) {
+          const unsigned char *hp =
+              sh + (((mz + tz) * HY + my + ty) * HX + xb + tx) * VS + row * 2;
+#pragma unroll
+          for (int e = 0; e < 8; e++) ax[e] = *reinterpret_cast<const bf16 *>(hp + e * VS);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 8; e++) ax[e] = (bf16)0.f;
+        }
+        acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ax, bg, acc[i], 0, 0, 0);
+      }
+    }
+  }
+  // partial sums of this workgroup: D[ci][co] of tap t
+  float *out = a.part + (size_t)blockIdx.x * (27 * 32 * 32 + 32);
+  for (int i = 0; i < ntap; i++) {
+    const int t = wave + 4 * i;
+#pragma unroll
+    for (int j = 0; j < 16; j++) {
+      const int ci = 8 * (j >> 2) + 4 * grp + (j & 3);
+      out[(t * 32 + ci) * 32 + row] = acc[i][j];
+    }
+  }
+  if (wave == 0) {
+    bsum += __shfl_xor(bsum, 32);
+    if (grp == 0) out[27 * 32 * 32 + row] = bsum;
+  }
+}
+
+// dW[t][ci][co] (real sizes) = sum over workgroups of the partials; db too.
+__global__ void k_wgrad_reduce(const float *part, int nblk, int ci, int co, float *dW,
+                               float *db) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nw = 27 * ci * co;
+  if (i < nw) {
+    const int c_o = i % co, c_i = (i / co) % ci, t = i / (co * ci);
+    const size_t src = ((size_t)t * 32 + c_i) * 32 + c_o;
+    float s = 0.f;
+    for (int k = 0; k < nblk; k++) s += part[(size_t)k * (27 * 32 * 32 + 32) + src];
+    dW[i] = s;
+  } else if (i < nw + co) {
+    const int c_o = i - nw;
+    float s = 0.f;
+    for (int k = 0; k < nblk; k++) s += part[(size_t)k * (27 * 32 * 32 + 32) + 27 * 32 * 32 + c_o];
+    if (db) db[c_o] = s;
+  }
+}
+
+// ------------------------------------------------------ small kernels --
+
+// packed[t][ks][l][e] = W[t][ci = 16 ks + 8 (l/32) + e][co = l % 32] (0 outside);
+// transposed: W'[t][c'][c''] = W[26 - t][c''][c'] with c' the input channel.
+__global__ void k_pack(const float *W, int ci, int co, int ci_pad, int transpose, bf16 *out) {
+  const int KS = ci_pad / 16;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 27 * KS * 64 * 8) return;
+  const int e = i & 7, l = (i >> 3) & 63, ks = (i >> 9) % KS, t = (i >> 9) / KS;
+  const int kin = 16 * ks + 8 * (l >> 5) + e, kout = l & 31;
+  float v = 0.f;
+  if (!transpose) {
+    if (kin < ci && kout < co) v = W[((size_t)t * ci + kin) * co + kout];
+  } else {
+    // adjoint: its input channel kin is the forward output channel, its output
+    // channel kout the forward input channel
+    if (kin < co && kout < ci) v = W[((size_t)(26 - t) * ci + kout) * co + kin];
+  }
+  out[i] = (bf16)v;
+}
+
+__global__ void k_mse(const float *pred, const float *target, int64_t nvox, int nch,
+                      bf16 *grad, float *part) {
+  __shared__ float red[256];
+  const float sc = 2.f / (float)((double)nvox * nch);
+  float s = 0.f;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nvox;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    bf16x8 gv[4];
+#pragma unroll
+    for (int c = 0; c < 32; c++) {
+      float g = 0.f;
+      if (c < nch) {
+        const float d = pred[v * nch + c] - target[v * nch + c];
+        s += d * d;
+        g = sc * d;
+      }
+      gv[c >> 3][c & 7] = (bf16)g;
+    }
+    for (int q = 0; q < 4; q++) reinterpret_cast<bf16x8 *>(grad + v * 32)[q] = gv[q];
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_mse_finish(const float *part, int nblk, double denom, float *loss) {
+  __shared__ float red[256];
+  float s = 0.f;
+  for (int i = threadIdx.x; i < nblk; i += blockDim.x) s += part[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *loss = (float)(red[0] / denom);
+}
+
+__global__ void k_adam(float *th, const float *g, float *m, float *v, int64_t n, float lr,
+                       float b1, float b2, float eps, float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  th[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+template <typename T>
+__global__ void k_restrict(const T *f, int n0, int n1, int n2, int kind, T *c) {
+  const int m0 = n0 / 2, m1 = n1 / 2, m2 = n2 / 2;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)m0 * m1 * m2) return;
+  const int I = (int)(i % m0), J = (int)((i / m0) % m1), K = (int)(i / ((int64_t)m0 * m1));
+  // spans along each axis: 2 fine indices, except 1 (index 2I) along a face's normal
+  const int s0 = (kind == 0) ? 1 : 2, s1 = (kind == 1) ? 1 : 2, s2 = (kind == 2) ? 1 : 2;
+  double acc = 0.0;
+  for (int c = 0; c < s2; c++)
+    for (int b = 0; b < s1; b++)
+      for (int a = 0; a < s0; a++)
+        acc += (double)f[((int64_t)(2 * K + c) * n1 + (2 * J + b)) * n0 + (2 * I + a)];
+  c[i] = (T)(acc / (s0 * s1 * s2));
+}
+
+struct GatherArgs {
+  const float *src[IB_GATHER_MAX_SOURCES];
+  float scale[IB_GATHER_MAX_SOURCES];
+  int chan[IB_GATHER_MAX_SOURCES];
+  int nsrc, n0, n1, n2;
+  const int *origins;
+  int B, d0, d1, d2, out_f32, out_ch;
+  void *out;
+};
+
+// out[b][voxel][c] = sum over sources s with chan[s] = c of scale[s] src[s][g]
+// at the periodic grid point g of the brick voxel (0 for channels no source
+// names).
+__global__ void k_gather(GatherArgs a) {
+  const int64_t per = (int64_t)a.d0 * a.d1 * a.d2;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= per * a.B) return;
+  const int b = (int)(i / per);
+  const int64_t r = i - b * per;
+  const int x = (int)(r % a.d0), y = (int)((r / a.d0) % a.d1), z = (int)(r / ((int64_t)a.d0 * a.d1));
+  const int gx = wrapi(a.origins[3 * b + 0] + x, a.n0);
+  const int gy = wrapi(a.origins[3 * b + 1] + y, a.n1);
+  const int gz = wrapi(a.origins[3 * b + 2] + z, a.n2);
+  const int64_t g = ((int64_t)gz * a.n1 + gy) * a.n0 + gx;
+  float v[16];
+#pragma unroll
+  for (int c = 0; c < 16; c++) v[c] = 0.f;
+  for (int s = 0; s < a.nsrc; s++) {
+    const float val = a.src[s][g] * a.scale[s];
+#pragma unroll
+    for (int c = 0; c < 16; c++)
+      if (c == a.chan[s]) v[c] += val;
+  }
+  if (a.out_f32) {
+    float *o = reinterpret_cast<float *>(a.out) + i * a.out_ch;
+#pragma unroll
+    for (int c = 0; c < 16; c++)
+      if (c < a.out_ch) o[c] = v[c];
+  } else {
+    bf16x8 w[2];
+#pragma unroll
+    for (int c = 0; c < 16; c++) w[c >> 3][c & 7] = (bf16)v[c];
+    reinterpret_cast<bf16x8 *>(reinterpret_cast<bf16 *>(a.out) + i * 16)[0] = w[0];
+    reinterpret_cast<bf16x8 *>(reinterpret_cast<bf16 *>(a.out) + i * 16)[1] = w[1];
+  }
+}
+
+__global__ void k_apply(float *u0, float *u1, float *u2, int64_t nvox, const float *y, float s) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nvox) return;
+  u0[i] += s * y[3 * i + 0];
+  u1[i] += s * y[3 * i + 1];
+  u2[i] += s * y[3 * i + 2];
+}
+
+// ------------------------------------------------------------- host ----
+
+using ibgm_err::fail;
+
+#define HIP_CHECK_LAUNCH(what)                                                          \
+  do {                                                                                  \
+    hipError_t e_ = hipGetLastError();                                                  \
+    if (e_ != hipSuccess) return fail(IB_E_DEVICE, "%s launch failed: %s", what,        \
+                                      hipGetErrorString(e_));                           \
+  } while (0)
+
+ib_status mode_off(int32_t mode, int *off, int *wrap, int *grow) {
+  switch (mode) {
+    case IB_CONV_PERIODIC: *off = -1, *wrap = 1, *grow = 0; return IB_OK;
+    case IB_CONV_VALID: *off = 0, *wrap = 0, *grow = -2; return IB_OK;
+    case IB_CONV_FULL: *off = -2, *wrap = 0, *grow = 2; return IB_OK;
+    default: return fail(IB_E_INVALID, "unknown convolution mode %d", mode);
+  }
+}
+
+ib_status check_dims(const int32_t *d, int32_t batch, int grow, int64_t *nvox_in,
+                     int64_t *nvox_out) {
+  if (!d) return fail(IB_E_INVALID, "null dims");
+  if (batch < 1) return fail(IB_E_INVALID, "batch < 1");
+  int64_t vi = batch, vo = batch;
+  for (int a = 0; a < 3; a++) {
+    if (d[a] < 1 || d[a] > 4096) return fail(IB_E_INVALID, "dims[%d] = %d out of [1, 4096]", a, d[a]);
+    if (d[a] + grow < 1) return fail(IB_E_INVALID, "dims[%d] = %d too small for a valid convolution", a, d[a]);
+    vi *= d[a], vo *= d[a] + grow;
+  }
+  if (vi * 32 >= ((int64_t)1 << 40) || vo * 32 >= ((int64_t)1 << 40))
+    return fail(IB_E_INVALID, "brick batch too large");
+  *nvox_in = vi, *nvox_out = vo;
+  return IB_OK;
+}
+
+ib_status launch_conv(const bf16 *x, int32_t batch, const int32_t *in_dims, int32_t ci_pad,
+                      const void *packed, const float *bias, int32_t mode, int relu,
+                      int out_f32, const bf16 *mask, void *y, int32_t co_store,
+                      int32_t y_stride, hipStream_t st) {
+  int off, wrap, grow;
+  ib_status s = mode_off(mode, &off, &wrap, &grow);
+  if (s != IB_OK) return s;
+  int64_t vi, vo;
+  if ((s = check_dims(in_dims, batch, grow, &vi, &vo)) != IB_OK) return s;
+  if (ci_pad != 16 && ci_pad != 32) return fail(IB_E_INVALID, "ci_pad must be 16 or 32");
+  if (!x || !packed || !y) return fail(IB_E_INVALID, "null convolution buffer");
+  if (co_store < 1 || co_store > CO || y_stride < co_store)
+    return fail(IB_E_INVALID, "need 1 <= co_store <= 32 and y_stride >= co_store");
+  if ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(packed)) & 15)
+    return fail(IB_E_INVALID, "x and packed weights must be 16-byte aligned");
+  ConvArgs a{};
+  a.x = x, a.wp = reinterpret_cast<const bf16 *>(packed), a.bias = bias, a.mask = mask, a.y = y;
+  a.B = batch, a.D0 = in_dims[0], a.D1 = in_dims[1], a.D2 = in_dims[2];
+  a.E0 = a.D0 + grow, a.E1 = a.D1 + grow, a.E2 = a.D2 + grow;
+  a.off = off, a.wrap = wrap, a.relu = relu, a.out_f32 = out_f32;
+  a.co_store = co_store, a.ystride = y_stride;
+  a.nt0 = (a.E0 + TX - 1) / TX, a.nt1 = (a.E1 + TY - 1) / TY, a.nt2 = (a.E2 + TZ - 1) / TZ;
+  const int64_t nt = (int64_t)a.nt0 * a.nt1 * a.nt2 * batch;
+  if (nt >= INT32_MAX) return fail(IB_E_INVALID, "too many tiles");
+  a.ntiles = (int)nt;
+  const int grid = (int)(nt < WG_CONV ? nt : WG_CONV);
+  if (ci_pad == 16) k_conv<16><<<grid, NT, 0, st>>>(a);
+  else k_conv<32><<<grid, NT, 0, st>>>(a);
+  HIP_CHECK_LAUNCH("conv3d");
+  return IB_OK;
+}
+
+}  // namespace
+
+extern "C" ib_status ib_conv3d_pack(const float *W, int32_t ci, int32_t co, int32_t ci_pad,
+                                    int32_t transpose, void *packed, void *hip_stream) {
+  if (!W || !packed) return fail(IB_E_INVALID, "null weights");
+  if (ci_pad != 16 && ci_pad != 32) return fail(IB_E_INVALID, "ci_pad must be 16 or 32");
+  if (ci < 1 || co < 1 || co > 32 || ci > 32)
+    return fail(IB_E_INVALID, "channels out of range (ci %d, co %d)", ci, co);
+  if (!transpose && ci > ci_pad) return fail(IB_E_INVALID, "ci > ci_pad");
+  if (transpose && ci_pad != 32) return fail(IB_E_INVALID, "the adjoint packing needs ci_pad 32");
+  const int n = 27 * (ci_pad / 16) * 64 * 8;
+  k_pack<<<(n + 255) / 256, 256, 0, (hipStream_t)hip_stream>>>(W, ci, co, ci_pad, transpose,
+                                                                reinterpret_cast<bf16 *>(packed));
+  HIP_CHECK_LAUNCH("pack");
+  return IB_OK;
+}
+
+extern "C" ib_status ib_conv3d_fwd(const uint16_t *x, int32_t batch, const int32_t in_dims[3],
+                                   int32_t ci_pad, const void *packed, const float *bias,
+                                   int32_t mode, int32_t flags, void *y, int32_t co_store,
+                                   int32_t y_stride, void *hip_stream) {
+  if (flags & ~(IB_CONV_RELU | IB_CONV_OUT_F32)) return fail(IB_E_INVALID, "unknown flags");
+  return launch_conv(reinterpret_cast<const bf16 *>(x), batch, in_dims, ci_pad, packed, bias,
+                     mode, (flags & IB_CONV_RELU) != 0, (flags & IB_CONV_OUT_F32) != 0, nullptr,
+                     y, co_store, y_stride, (hipStream_t)hip_stream);
+}
+
+extern "C" ib_status ib_conv3d_bwd_data(const uint16_t *gy, int32_t batch,
+                                        const int32_t out_dims[3], const void *packed,
+                                        int32_t mode, const uint16_t *act_below, uint16_t *gx,
+                                        void *hip_stream) {
+  int32_t amode;
+  if (mode == IB_CONV_PERIODIC) amode = IB_CONV_PERIODIC;
+  else if (mode == IB_CONV_VALID) amode = IB_CONV_FULL;
+  else return fail(IB_E_INVALID, "bwd_data: the layer must have run PERIODIC or VALID");
+  return launch_conv(reinterpret_cast<const bf16 *>(gy), batch, out_dims, 32, packed, nullptr,
+                     amode, 0, 0, reinterpret_cast<const bf16 *>(act_below), gx, 32, 32,
+                     (hipStream_t)hip_stream);
+}
+
+extern "C" ib_status ib_conv3d_bwd_weight(const uint16_t *x, const uint16_t *gy, int32_t batch,
+                                          const int32_t in_dims[3], int32_t ci_pad,
+                                          int32_t mode, int32_t ci, int32_t co, float *dW,
+                                          float *db, void *workspace, void *hip_stream) {
+  int off, wrap, grow;
+  ib_status s = mode_off(mode, &off, &wrap, &grow);
+  if (s != IB_OK) return s;
+  if (mode == IB_CONV_FULL) return fail(IB_E_INVALID, "bwd_weight: FULL layers are not built");
+  int64_t vi, vo;
+  if ((s = check_dims(in_dims, batch, grow, &vi, &vo)) != IB_OK) return s;
+  if (ci_pad != 16 && ci_pad != 32) return fail(IB_E_INVALID, "ci_pad must be 16 or 32");
+  if (ci < 1 || ci > ci_pad || co < 1 || co > 32) return fail(IB_E_INVALID, "channels out of range");
+  if (!x || !gy || !dW || !workspace) return fail(IB_E_INVALID, "null buffer");
+  if ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(gy) |
+       reinterpret_cast<uintptr_t>(workspace)) & 15)
+    return fail(IB_E_INVALID, "x, gy and workspace must be 16-byte aligned");
+  hipStream_t st = (hipStream_t)hip_stream;
+  WgradArgs a{};
+  a.x = reinterpret_cast<const bf16 *>(x), a.g = reinterpret_cast<const bf16 *>(gy);
+  a.part = reinterpret_cast<float *>(workspace);
+  a.B = batch, a.D0 = in_dims[0], a.D1 = in_dims[1], a.D2 = in_dims[2];
+  a.E0 = a.D0 + grow, a.E1 = a.D1 + grow, a.E2 = a.D2 + grow;
+  a.off = off, a.wrap = wrap;
+  a.nt0 = (a.E0 + TX - 1) / TX, a.nt1 = (a.E1 + TY - 1) / TY, a.nt2 = (a.E2 + TZ - 1) / TZ;
+  const int64_t nt = (int64_t)a.nt0 * a.nt1 * a.nt2 * batch;
+  if (nt >= INT32_MAX) return fail(IB_E_INVALID, "too many tiles");
+  a.ntiles = (int)nt;
+  const int grid = (int)(nt < IB_CONV_WGRAD_BLOCKS ? nt : IB_CONV_WGRAD_BLOCKS);
+  if (ci_pad == 16) k_wgrad<16><<<grid, NT, 0, st>>>(a);
+  else k_wgrad<32><<<grid, NT, 0, st>>>(a);
+  HIP_CHECK_LAUNCH("wgrad");
+  const int nout = 27 * ci * co + co;
+  k_wgrad_reduce<<<(nout + 255) / 256, 256, 0, st>>>(a.part, grid, ci, co, dW, db);
+  HIP_CHECK_LAUNCH("wgrad reduce");
+  return IB_OK;
+}
+
+extern "C" ib_status ib_mse_grad(const float *pred, const float *target, int64_t n_vox,
+                                 int32_t nch, float *loss, uint16_t *grad, void *workspace,
+                                 void *hip_stream) {
+  if (!pred || !target || !loss || !grad || !workspace) return fail(IB_E_INVALID, "null buffer");
+  if (n_vox < 1 || nch < 1 || nch > 32) return fail(IB_E_INVALID, "bad n_vox / nch");
+  if (reinterpret_cast<uintptr_t>(grad) & 15) return fail(IB_E_INVALID, "grad must be 16-byte aligned");
+  hipStream_t st = (hipStream_t)hip_stream;
+  const int64_t want = (n_vox + 255) / 256;
+  const int nblk = (int)(want < 1024 ? want : 1024);
+  float *part = reinterpret_cast<float *>(workspace);
+  k_mse<<<nblk, 256, 0, st>>>(pred, target, n_vox, nch, reinterpret_cast<bf16 *>(grad), part);
+  HIP_CHECK_LAUNCH("mse");
+  k_mse_finish<<<1, 256, 0, st>>>(part, nblk, (double)n_vox * nch, loss);
+  HIP_CHECK_LAUNCH("mse finish");
+  return IB_OK;
+}
+
+extern "C" ib_status ib_adam_step(float *theta, const float *g, float *m, float *v, int64_t n,
+                                  float lr, float beta1, float beta2, float eps, int32_t t,
+                                  void *hip_stream) {
+  if (!theta || !g || !m || !v) return fail(IB_E_INVALID, "null buffer");
+  if (n < 1 || t < 1) return fail(IB_E_INVALID, "need n >= 1 and t >= 1");
+  if (!(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps > 0.f && lr >= 0.f))
+    return fail(IB_E_INVALID, "bad Adam hyper-parameters");
+  const float c1 = 1.f - (float)std::pow((double)beta1, (double)t);
+  const float c2 = 1.f - (float)std::pow((double)beta2, (double)t);
+  k_adam<<<(unsigned)((n + 255) / 256), 256, 0, (hipStream_t)hip_stream>>>(theta, g, m, v, n, lr,
+                                                                           beta1, beta2, eps, c1, c2);
+  HIP_CHECK_LAUNCH("adam");
+  return IB_OK;
+}
+
+extern "C" ib_status ib_restrict(const void *fine, int32_t dtype, const int32_t nf[3],
+                                 int32_t kind, void *coarse, void *hip_stream) {
+  if (!fine || !coarse || !nf) return fail(IB_E_INVALID, "null buffer");
+  if (kind < 0 || kind > 3) return fail(IB_E_INVALID, "kind must be 0..3");
+  for (int a = 0; a < 3; a++)
+    if (nf[a] < 2 || nf[a] % 2 || nf[a] > 4096) return fail(IB_E_INVALID, "nf[%d] must be even in [2, 4096]", a);
+  const int64_t nc = (int64_t)(nf[0] / 2) * (nf[1] / 2) * (nf[2] / 2);
+  hipStream_t st = (hipStream_t)hip_stream;
+  const unsigned g = (unsigned)((nc + 255) / 256);
+  if (dtype == IB_F64)
+    k_restrict<double><<<g, 256, 0, st>>>((const double *)fine, nf[0], nf[1], nf[2], kind, (double *)coarse);
+  else if (dtype == IB_F32)
+    k_restrict<float><<<g, 256, 0, st>>>((const float *)fine, nf[0], nf[1], nf[2], kind, (float *)coarse);
+  else
+    return fail(IB_E_INVALID, "unknown dtype %d", dtype);
+  HIP_CHECK_LAUNCH("restrict");
+  return IB_OK;
+}
+
+extern "C" ib_status ib_closure_gather(const float *const *src, const float *scales,
+                                       const int32_t *chan, int32_t nsrc, const int32_t n[3],
+                                       const int32_t *origins, int32_t batch,
+                                       const int32_t dims[3], int32_t out_f32, int32_t out_ch,
+                                       void *out, void *hip_stream) {
+  if (!src || !scales || !chan || !n || !origins || !dims || !out)
+    return fail(IB_E_INVALID, "null argument");
+  if (nsrc < 1 || nsrc > IB_GATHER_MAX_SOURCES)
+    return fail(IB_E_INVALID, "nsrc must be 1..%d", IB_GATHER_MAX_SOURCES);
+  if (batch < 1) return fail(IB_E_INVALID, "batch < 1");
+  if (out_f32 ? (out_ch < 1 || out_ch > 16) : out_ch != 16)
+    return fail(IB_E_INVALID, "out_ch must be 16 (BF16) or 1..16 (FP32)");
+  GatherArgs a{};
+  for (int s = 0; s < nsrc; s++) {
+    if (!src[s]) return fail(IB_E_INVALID, "null source %d", s);
+    if (chan[s] < 0 || chan[s] >= out_ch) return fail(IB_E_INVALID, "chan[%d] out of range", s);
+    a.src[s] = src[s], a.scale[s] = scales[s], a.chan[s] = chan[s];
+  }
+  for (int i = 0; i < 3; i++)
+    if (n[i] < 1 || dims[i] < 1 || n[i] > 4096 || dims[i] > 4096) return fail(IB_E_INVALID, "bad n / dims");
+  if (!out_f32 && (reinterpret_cast<uintptr_t>(out) & 15)) return fail(IB_E_INVALID, "out must be 16-byte aligned");
+  a.nsrc = nsrc, a.n0 = n[0], a.n1 = n[1], a.n2 = n[2], a.origins = origins;
+  a.B = batch, a.d0 = dims[0], a.d1 = dims[1], a.d2 = dims[2], a.out_f32 = out_f32 ? 1 : 0;
+  a.out_ch = out_ch, a.out = out;
+  const int64_t tot = (int64_t)dims[0] * dims[1] * dims[2] * batch;
+  k_gather<<<(unsigned)((tot + 255) / 256), 256, 0, (hipStream_t)hip_stream>>>(a);
+  HIP_CHECK_LAUNCH("gather");
+  return IB_OK;
+}
+
+extern "C" ib_status ib_closure_apply(float *const u[3], const int32_t n[3], const float *y,
+                                      float scale, void *hip_stream) {
+  if (!u || !n || !y || !u[0] || !u[1] || !u[2]) return fail(IB_E_INVALID, "null argument");
+  for (int i = 0; i < 3; i++)
+    if (n[i] < 1 || n[i] > 4096) return fail(IB_E_INVALID, "bad n");
+  const int64_t nv = (int64_t)n[0] * n[1] * n[2];
+  k_apply<<<(unsigned)((nv + 255) / 256), 256, 0, (hipStream_t)hip_stream>>>(u[0], u[1], u[2], nv, y, scale);
+  HIP_CHECK_LAUNCH("apply");
+  return IB_OK;
+}

@@ -15,6 +15,7 @@
 #include <string>
 #include <vector>
 
+#include "errors.h"
 #include "ibgm.h"
 #include "kernels.h"
 
@@ -24,7 +25,7 @@ using namespace ibgm;
 
 static thread_local std::string g_err;
 
-static ib_status fail(ib_status st, const char *fmt, ...) {
+ib_status ibgm_err::fail(ib_status st, const char *fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -33,6 +34,7 @@ static ib_status fail(ib_status st, const char *fmt, ...) {
   g_err = buf;
   return st;
 }
+using ibgm_err::fail;
 
 #define HIP_TRY(expr)                                                     \
   do {                                                                    \
@@ -790,6 +792,25 @@ extern "C" ib_status ib_init(ib_ctx **out, const ib_grid_params *prm, const ib_b
     return bail(fail(IB_E_DEVICE, "initialisation on the stream failed"));
   if (hipGetLastError() != hipSuccess) return bail(fail(IB_E_DEVICE, "kernel launch failed"));
   *out = c;
+  return IB_OK;
+}
+
+extern "C" ib_status ib_restart(ib_ctx *c, int64_t step0) {
+  if (!c) return fail(IB_E_STATE, "null context");
+  if (step0 < 0) return fail(IB_E_INVALID, "step0 must be >= 0");
+  if (c->prof) return fail(IB_E_STATE, "disable profiling before a restart");
+  c->step = step0;
+  if (step0 == 0) {
+    if (c->f32) {
+      if (c->dim == 2) launch_divergence<float, 2>(c, c->buf.div_prev);
+      else launch_divergence<float, 3>(c, c->buf.div_prev);
+    } else {
+      if (c->dim == 2) launch_divergence<double, 2>(c, c->buf.div_prev);
+      else launch_divergence<double, 3>(c, c->buf.div_prev);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(IB_E_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
+  }
   return IB_OK;
 }
 

@@ -1,4 +1,5 @@
-"""ctypes binding of libibgm.so (the C ABI in include/ibgm.h).
+"""ctypes binding of libibgm.so (the C ABI in include/ibgm.h and
+include/ibgm_closure.h).
 
 Argument marshalling only: every step of the path runs in the library's HIP
 kernels.  PyTorch supplies device memory and the stream.  Importing this
@@ -64,6 +65,7 @@ def _load():
     L.ib_init.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(GridParams),
                           ctypes.POINTER(Buffers), ctypes.POINTER(Structure), _vp]
     L.ib_step.argtypes = [_vp, ctypes.c_int32]
+    L.ib_restart.argtypes = [_vp, ctypes.c_int64]
     L.ib_sync.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64)]
     L.ib_spread.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int64, _vp * 3, ctypes.c_int32]
     L.ib_interp.argtypes = [_vp, _vp, ctypes.c_int64, _vp * 3, _vp]
@@ -85,20 +87,37 @@ def _load():
                                   ctypes.c_int32, ctypes.c_int32, _vp]
     L.ib_graph_launch.argtypes = [_vp, ctypes.c_int32]
     L.ib_graph_destroy.argtypes = [_vp]
-    for f in ("ib_workspace_size", "ib_init", "ib_step", "ib_sync", "ib_spread", "ib_interp",
+    # learned closure (include/ibgm_closure.h)
+    i32, i64, f32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float
+    L.ib_conv3d_pack.argtypes = [_vp, i32, i32, i32, i32, _vp, _vp]
+    L.ib_conv3d_fwd.argtypes = [_vp, i32, _ip, i32, _vp, _vp, i32, i32, _vp, i32, i32, _vp]
+    L.ib_conv3d_bwd_data.argtypes = [_vp, i32, _ip, _vp, i32, _vp, _vp, _vp]
+    L.ib_conv3d_bwd_weight.argtypes = [_vp, _vp, i32, _ip, i32, i32, i32, i32, _vp, _vp, _vp, _vp]
+    L.ib_mse_grad.argtypes = [_vp, _vp, i64, i32, _vp, _vp, _vp, _vp]
+    L.ib_adam_step.argtypes = [_vp, _vp, _vp, _vp, i64, f32, f32, f32, f32, i32, _vp]
+    L.ib_restrict.argtypes = [_vp, i32, _ip, i32, _vp, _vp]
+    L.ib_closure_gather.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(f32), _ip, i32, _ip, _vp,
+                                    i32, _ip, i32, i32, _vp, _vp]
+    L.ib_closure_apply.argtypes = [ctypes.POINTER(_vp), _ip, _vp, f32, _vp]
+    for f in ("ib_workspace_size", "ib_init", "ib_step", "ib_restart", "ib_sync", "ib_spread", "ib_interp",
               "ib_force", "ib_line_solve", "ib_destroy", "ib_profile_enable", "ib_profile_read",
               "ib_tune", "ib_tune_read", "ib_graph_create", "ib_graph_launch",
-              "ib_graph_destroy"):
+              "ib_graph_destroy") + CLOSURE_EXPORTED:
         getattr(L, f).restype = ctypes.c_int
     return L
 
 
+CLOSURE_EXPORTED = ("ib_conv3d_pack", "ib_conv3d_fwd", "ib_conv3d_bwd_data",
+                    "ib_conv3d_bwd_weight", "ib_mse_grad", "ib_adam_step", "ib_restrict",
+                    "ib_closure_gather", "ib_closure_apply")
+
+
 lib = _load()
 
-EXPORTED = ("ib_workspace_size", "ib_init", "ib_step", "ib_sync", "ib_spread", "ib_interp",
+EXPORTED = ("ib_workspace_size", "ib_init", "ib_step", "ib_restart", "ib_sync", "ib_spread", "ib_interp",
             "ib_force", "ib_line_solve", "ib_destroy", "ib_last_error", "ib_profile_enable",
             "ib_profile_count", "ib_profile_name", "ib_profile_read", "ib_tune", "ib_tune_read",
-            "ib_graph_create", "ib_graph_launch", "ib_graph_destroy")
+            "ib_graph_create", "ib_graph_launch", "ib_graph_destroy") + CLOSURE_EXPORTED
 
 
 def check(status: int):
@@ -247,6 +266,11 @@ class Simulation:
     # -- stepping --------------------------------------------------------
     def step(self, nsteps: int = 1):
         check(lib.ib_step(self.ctx, nsteps))
+        return self
+
+    def restart(self, step0: int = 0):
+        """Continue from whatever the state tensors now hold, as step step0."""
+        check(lib.ib_restart(self.ctx, step0))
         return self
 
     def sync(self) -> int:

@@ -328,3 +328,39 @@ def config_ensemble(nsims: int = 64, seed: int = 4, steps: int = 500,
         members.append(EnsembleMember(i, n, sg, stiffness_time_step(sg),
                                       ellipse(points_per_cell * n, 0.3, 0.2, sg)))
     return members, {"rho": rho, "mu": mu, "steps": steps, "chi": 0.6}
+
+
+# -------------------------------------------------- closure training family --
+
+@dataclass
+class ClosureCase:
+    """One fine trajectory of the closure's training family."""
+    seed: int
+    sigma: float
+    axes: tuple
+    dt_fine: float
+    structure: Structure
+    u0: list
+
+
+def closure_family(ntraj: int, seed: int = 5, n_fine: int = 256, npts: int = None):
+    """Ellipsoidal shells with seeded semi-axes in [0.15, 0.3], membrane
+    modulus log-uniform in [0.1, 10] (cotangent links) and a seeded random
+    smooth divergence-free velocity (|k| <= 4, max |u| = 0.1) on the n_fine^3
+    grid; the fine time step is (64 / n_fine) min(1e-3, 6e-4 / sigma): the
+    explicit membrane force limits it to about 6 mu h / sigma on the oracle
+    for this family (so the coarse companion, at twice h, takes twice the
+    step).  npts defaults to 65,536 (n_fine / 256)^2 points."""
+    rng = np.random.default_rng(seed)
+    if npts is None:
+        npts = max(256, int(65536 * (n_fine / 256) ** 2))
+    cases = []
+    for i in range(ntraj):
+        axes = tuple(float(a) for a in rng.uniform(0.15, 0.3, size=3))
+        sigma = float(math.exp(rng.uniform(math.log(0.1), math.log(10.0))))
+        vseed = int(rng.integers(0, 2 ** 31 - 1))
+        dt = (64.0 / n_fine) * min(1e-3, 6e-4 / sigma)
+        cases.append(ClosureCase(i, sigma, axes, dt,
+                                 ellipsoid_shell(npts, axes, sigma, weights="cotan"),
+                                 random_vector_potential_velocity_3d(n_fine, 4, 0.1, vseed)))
+    return cases

@@ -1,0 +1,254 @@
+"""GPU parity of the learned-closure kernels through the C ABI against the
+closure oracle (FP64 on the same BF16-rounded operands): the matrix-core
+convolution in every mode with ragged tiles, its two gradients, the loss,
+Adam, the MAC restriction and the gather, a whole-network gradient, and the
+gain test -- a network trained by these kernels on pairs the method generates
+brings held-out coarse solves closer to the restricted fine solve."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import closure as oc
+from paper_1305_3976_amd import closure as cl
+from paper_1305_3976_amd import ibgm, inputs
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+MODES = {"periodic": cl.PERIODIC, "valid": cl.VALID}
+
+
+def bf16_pair(shape, rng, scale=1.0):
+    """A BF16 device tensor and its exact FP64 value on the host."""
+    t = torch.as_tensor((rng.standard_normal(shape) * scale).astype(np.float32)).to(torch.bfloat16)
+    return t.to(DEV), t.double().numpy()
+
+
+def bf16_round(a):
+    return torch.as_tensor(np.asarray(a, dtype=np.float32)).to(torch.bfloat16).double().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-30))
+
+
+def pack(W, ci, co, ci_pad, transpose):
+    Wd = torch.as_tensor(W.astype(np.float32)).to(DEV).contiguous()
+    P = torch.empty(cl.packed_bytes(ci_pad), dtype=torch.uint8, device=DEV)
+    ibgm.check(ibgm.lib.ib_conv3d_pack(cl._p(Wd), ci, co, ci_pad, transpose, cl._p(P),
+                                       cl._stream()))
+    return P, Wd
+
+
+@pytest.mark.parametrize("mode,ci,ci_pad,co,dims,batch,out_f32,relu", [
+    ("periodic", 6, 16, 32, (40, 12, 6), 2, False, True),     # ragged x tile, wrap
+    ("periodic", 32, 32, 32, (32, 8, 4), 1, True, False),
+    ("valid", 32, 32, 32, (38, 9, 7), 2, False, True),         # E = (36, 7, 5): partial tiles
+    ("valid", 32, 32, 3, (36, 6, 5), 3, True, False),          # the output layer shape
+])
+def test_conv_forward(mode, ci, ci_pad, co, dims, batch, out_f32, relu):
+    rng = np.random.default_rng(10 + ci + co)
+    d0, d1, d2 = dims
+    x, xh = bf16_pair((batch, d2, d1, d0, ci_pad), rng)
+    xh[..., ci:] = 0.0
+    x = torch.as_tensor(xh.astype(np.float32)).to(torch.bfloat16).to(DEV)
+    W = rng.standard_normal((27, ci, co)) * np.sqrt(2.0 / (27 * ci))
+    b = rng.standard_normal(co) * 0.1
+    P, _ = pack(W, ci, co, ci_pad, 0)
+    bd = torch.as_tensor(b.astype(np.float32)).to(DEV)
+    ref = oc.conv3d(xh[..., :ci], bf16_round(W), b.astype(np.float32).astype(np.float64), mode)
+    if relu:
+        ref = oc.relu(ref)
+    E = ref.shape[1:4]
+    nv = batch * E[0] * E[1] * E[2]
+    stride = co if out_f32 else 32
+    y = torch.full((nv * stride,), 7.0, dtype=torch.float32 if out_f32 else torch.bfloat16, device=DEV)
+    flags = (cl.OUT_F32 if out_f32 else 0) | (cl.RELU if relu else 0)
+    ibgm.check(ibgm.lib.ib_conv3d_fwd(cl._p(x), batch, cl._i3(dims), ci_pad, cl._p(P), cl._p(bd),
+                                      MODES[mode], flags, cl._p(y), co, stride, cl._stream()))
+    got = y.double().cpu().numpy().reshape(ref.shape[:4] + (stride,))
+    # FP32 accumulation of exact BF16 products (a few ulp of the largest
+    # partial sums); BF16 output rounding (2^-9 relative)
+    err = np.abs(got[..., :co] - ref)
+    top = np.abs(ref).max()
+    if out_f32:
+        assert err.max() <= 2e-6 * top
+    else:
+        assert np.all(err <= 2 ** -8 * np.abs(ref) + 1e-5 * top)
+    if stride > co:
+        assert np.all(got[..., co:] == 7.0)        # channels past co_store untouched
+
+
+@pytest.mark.parametrize("mode,dims,batch", [("periodic", (40, 7, 6), 2), ("valid", (36, 8, 6), 2)])
+def test_conv_bwd_data_with_relu_mask(mode, dims, batch):
+    rng = np.random.default_rng(21)
+    ci, co = 32, 32
+    W = rng.standard_normal((27, ci, co)) * 0.05
+    T, _ = pack(W, ci, co, 32, 1)
+    E = cl.out_dims(dims, MODES[mode])
+    gy, gyh = bf16_pair((batch, E[2], E[1], E[0], 32), rng)
+    act, acth = bf16_pair((batch, dims[2], dims[1], dims[0], 32), rng)
+    gx = torch.empty(batch * dims[0] * dims[1] * dims[2] * 32, dtype=torch.bfloat16, device=DEV)
+    ibgm.check(ibgm.lib.ib_conv3d_bwd_data(cl._p(gy), batch, cl._i3(E), cl._p(T), MODES[mode],
+                                           cl._p(act), cl._p(gx), cl._stream()))
+    ref = oc.conv3d_transpose(gyh, bf16_round(W), mode) * (acth > 0)
+    got = gx.double().cpu().numpy().reshape(ref.shape)
+    assert rel(got, ref) <= 2 ** -8
+    assert np.all(got[acth <= 0] == 0.0)
+
+
+@pytest.mark.parametrize("mode,ci,ci_pad,co,dims,batch", [
+    ("periodic", 6, 16, 32, (40, 9, 6), 2),
+    ("valid", 32, 32, 32, (38, 8, 7), 2),
+    ("valid", 32, 32, 3, (36, 7, 6), 3),
+])
+def test_conv_bwd_weight(mode, ci, ci_pad, co, dims, batch):
+    rng = np.random.default_rng(31)
+    x, xh = bf16_pair((batch, dims[2], dims[1], dims[0], ci_pad), rng)
+    xh[..., ci:] = 0.0
+    x = torch.as_tensor(xh.astype(np.float32)).to(torch.bfloat16).to(DEV)
+    E = cl.out_dims(dims, MODES[mode])
+    g, gh = bf16_pair((batch, E[2], E[1], E[0], 32), rng)
+    gh[..., co:] = 0.0
+    g = torch.as_tensor(gh.astype(np.float32)).to(torch.bfloat16).to(DEV)
+    dW = torch.empty(27 * ci * co, dtype=torch.float32, device=DEV)
+    db = torch.empty(co, dtype=torch.float32, device=DEV)
+    ws = torch.empty(cl.WGRAD_WS, dtype=torch.uint8, device=DEV)
+    ibgm.check(ibgm.lib.ib_conv3d_bwd_weight(cl._p(x), cl._p(g), batch, cl._i3(dims), ci_pad,
+                                             MODES[mode], ci, co, cl._p(dW), cl._p(db), cl._p(ws),
+                                             cl._stream()))
+    rW, rb = oc.conv3d_weight_grad(xh[..., :ci], gh[..., :co], mode)
+    # exact BF16 products summed in FP32 in another order
+    assert rel(dW.double().cpu().numpy().reshape(rW.shape), rW) <= 1e-4
+    assert rel(db.double().cpu().numpy(), rb) <= 1e-4
+
+
+def test_mse_and_adam():
+    rng = np.random.default_rng(41)
+    nv, nch = 5000, 3
+    pred = rng.standard_normal((nv, nch)).astype(np.float32)
+    targ = rng.standard_normal((nv, nch)).astype(np.float32)
+    pd, td = torch.as_tensor(pred).to(DEV), torch.as_tensor(targ).to(DEV)
+    loss = torch.zeros(1, dtype=torch.float32, device=DEV)
+    grad = torch.empty(nv * 32, dtype=torch.bfloat16, device=DEV)
+    ws = torch.empty(4096, dtype=torch.uint8, device=DEV)
+    ibgm.check(ibgm.lib.ib_mse_grad(cl._p(pd), cl._p(td), nv, nch, cl._p(loss), cl._p(grad),
+                                    cl._p(ws), cl._stream()))
+    L, gref = oc.mse(pred.astype(np.float64), targ.astype(np.float64))
+    assert abs(float(loss) - L) <= 1e-5 * L
+    g = grad.double().cpu().numpy().reshape(nv, 32)
+    assert rel(g[:, :nch], gref) <= 2 ** -8 and np.all(g[:, nch:] == 0)
+    # Adam: 4 steps against the oracle's update
+    n = 1000
+    th = rng.standard_normal(n)
+    m = np.zeros(n)
+    v = np.zeros(n)
+    tt = torch.as_tensor(th.astype(np.float32)).to(DEV)
+    md, vd = torch.zeros(n, device=DEV), torch.zeros(n, device=DEV)
+    for t in range(1, 5):
+        gg = rng.standard_normal(n).astype(np.float32)
+        gd = torch.as_tensor(gg).to(DEV)
+        ibgm.check(ibgm.lib.ib_adam_step(cl._p(tt), cl._p(gd), cl._p(md), cl._p(vd), n, 1e-2, 0.9,
+                                         0.999, 1e-8, t, cl._stream()))
+        th, m, v = oc.adam_step(th, gg.astype(np.float64), m, v, t, 1e-2)
+    assert np.allclose(tt.double().cpu().numpy(), th, rtol=0, atol=1e-5)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_restrict_and_gather(dtype):
+    rng = np.random.default_rng(51)
+    n = (12, 8, 10)          # (n0, n1, n2)
+    f = rng.standard_normal((n[2], n[1], n[0]))
+    fd = torch.as_tensor(f).to(dtype).to(DEV)
+    tol = 1e-15 if dtype == torch.float64 else 1e-6
+    for kind in range(4):
+        got = cl.restrict(fd, kind).double().cpu().numpy()
+        ref = oc.restrict_cell(f) if kind == 3 else oc.restrict_face(f, kind)
+        assert np.allclose(got, ref, rtol=0, atol=tol * 4), kind
+    # gather: two bricks with wrapped origins, channel sums
+    srcs = [torch.as_tensor(rng.standard_normal((n[2], n[1], n[0])).astype(np.float32)).to(DEV)
+            for _ in range(3)]
+    org = np.array([[10, 7, 9], [-2, 0, 3]], dtype=np.int32)
+    dims = (5, 4, 3)
+    out = torch.empty(2 * 5 * 4 * 3 * 2, dtype=torch.float32, device=DEV)
+    cl.gather(srcs, [2.0, -1.0, 0.5], [0, 0, 1], n, torch.as_tensor(org).to(DEV), dims, True, 2, out)
+    got = out.cpu().numpy().reshape(2, 3, 4, 5, 2)
+    S = [s.cpu().numpy().astype(np.float64) for s in srcs]
+    for b in range(2):
+        for k in range(3):
+            for j in range(4):
+                for i in range(5):
+                    z, y, x = ((org[b, 2] + k) % n[2], (org[b, 1] + j) % n[1], (org[b, 0] + i) % n[0])
+                    assert abs(got[b, k, j, i, 0] - (2 * S[0][z, y, x] - S[1][z, y, x])) <= 1e-6
+                    assert abs(got[b, k, j, i, 1] - 0.5 * S[2][z, y, x]) <= 1e-6
+
+
+@pytest.mark.parametrize("mode", ["periodic", "valid"])
+def test_network_gradient_matches_oracle(mode):
+    rng = np.random.default_rng(61)
+    net = cl.ConvNet(seed=3)
+    # non-zero biases so every path carries signal
+    for i in range(3):
+        net.b[i].copy_(torch.as_tensor(rng.standard_normal(net.b[i].shape[0]).astype(np.float32) * 0.05))
+    net.pack()
+    batch = 2
+    dims = (34, 10, 9) if mode == "valid" else (32, 8, 6)
+    x, xh = bf16_pair((batch, dims[2], dims[1], dims[0], 16), rng)
+    xh[..., cl.CIN:] = 0.0
+    x = torch.as_tensor(xh.astype(np.float32)).to(torch.bfloat16).to(DEV)
+    E = cl.out_dims(dims, MODES[mode], 3)
+    tgt = rng.standard_normal((batch, E[2], E[1], E[0], 3)).astype(np.float32)
+    td = torch.as_tensor(tgt).to(DEV)
+    y = net.forward(x, batch, dims, MODES[mode])
+    net.backward(x, td, batch, dims, MODES[mode])
+    torch.cuda.synchronize()
+    (W1, b1), (W2, b2), (W3, b3) = [(bf16_round(W), b) for W, b in net.params_numpy()]
+    xo = xh[..., :cl.CIN]
+    # the oracle's layers on operands rounded to BF16 where the GPU stores
+    # BF16 (activations and their gradients), everything else in FP64
+    a1 = bf16_round(oc.relu(oc.conv3d(xo, W1, b1, mode)))
+    a2 = bf16_round(oc.relu(oc.conv3d(a1, W2, b2, mode)))
+    yo = oc.conv3d(a2, W3, b3, mode)
+    # (an activation whose FP32 and FP64 sums round to neighbouring BF16
+    # values differs by 2^-8 of itself)
+    assert rel(y.double().cpu().numpy().reshape(yo.shape), yo) <= 1e-3
+    L, gy = oc.mse(yo, tgt.astype(np.float64))
+    gy = bf16_round(gy)
+    dW3, db3 = oc.conv3d_weight_grad(a2, gy, mode)
+    g2 = bf16_round(oc.conv3d_transpose(gy, W3, mode) * (a2 > 0))
+    dW2, db2 = oc.conv3d_weight_grad(a1, g2, mode)
+    g1 = bf16_round(oc.conv3d_transpose(g2, W2, mode) * (a1 > 0))
+    dW1, db1 = oc.conv3d_weight_grad(xo, g1, mode)
+    got = net.grads_numpy()
+    for i, (rW, rb) in enumerate(((dW1, db1), (dW2, db2), (dW3, db3))):
+        eW, eb = rel(got[i][0], rW), rel(got[i][1], rb)
+        print("layer %d: rel err dW %.2e db %.2e" % (i + 1, eW, eb))
+        assert eW <= 2e-2 and eb <= 2e-2, (i, eW, eb)
+    assert abs(float(net.loss) - L) <= 1e-4 * L
+    # and against FP64 activations throughout (BF16 storage costs ~2^-8 per stage)
+    acts = oc.forward([(W1, b1), (W2, b2), (W3, b3)], xo, mode)
+    grads, _ = oc.backward([(W1, b1), (W2, b2), (W3, b3)], acts, oc.mse(acts[-1], tgt)[1], mode)
+    for i in range(3):
+        assert rel(got[i][0], grads[i][0]) <= 1e-1
+
+
+def test_closure_gain_on_held_out_trajectories():
+    """Small family (fine 64^3, coarse 32^3): train on 16 trajectories, judge
+    on 4 held-out ones; the corrected coarse velocity must be markedly closer
+    to the restricted fine velocity than the plain coarse one."""
+    ntr, nho, per = 16, 4, 12
+    cases = inputs.closure_family(ntr + nho, seed=5, n_fine=64)
+    tr = cl.PairSet(ntr * per, 32)
+    ho = cl.PairSet(nho * per, 32)
+    scales = cl.collect(cases[:ntr], 64, per, every=4, warmup=6, pairs=tr)
+    cl.collect(cases[ntr:], 64, per, every=4, warmup=6, pairs=ho, scales=scales)
+    assert tr.count == ntr * per and ho.count == nho * per
+    net = cl.ConvNet(seed=7)
+    losses = cl.train(net, tr, iters=1200, batch=4, lr=1e-3)
+    e0, e1 = cl.evaluate(net, ho, 0, ho.count)
+    t0, t1 = cl.evaluate(net, tr, 0, tr.count)
+    print("closure gain: held-out coarse error %.4g -> %.4g (ratio %.3f); train ratio %.3f; "
+          "loss %.4g -> %.4g" % (e0, e1, e1 / e0, t1 / t0, losses[:20].mean(), losses[-20:].mean()))
+    assert np.all(np.isfinite(losses))
+    assert losses[-20:].mean() < 0.5 * losses[:20].mean()
+    assert e1 < 0.7 * e0

@@ -50,6 +50,20 @@ def member_errors(ens, m, o):
                         [o.u[c][0] for c in range(2)], o.p[0], o.psi[0], o.X)
 
 
+def fp64_p_tolerance(n):
+    """p accumulates psi, which comes from solves with (1 - D_aa): on the unit
+    box their condition number is 1 + 4/h^2 = 1 + 4N^2, so the oracle's own p
+    is only accurate to about that times eps64, which passes 1e-12 from N ~ 48
+    on.  p is held to the larger of the two."""
+    return max(FP64_TOL, (1 + 4 * n * n) * 2.0 ** -52)
+
+
+def check_fp64(m, errs):
+    for k, e in errs.items():
+        lim = fp64_p_tolerance(m.n) if k == "p" else FP64_TOL
+        assert e <= lim, (m.index, k, e, lim)
+
+
 def mixed_p_tolerance(m, o, steps):
     """Bar for p under the mixed policy.  Storing u^{n+1} in FP32 perturbs it by
     about eps32 |u| per step; the psi sweeps answer the divergence of that
@@ -83,7 +97,7 @@ def test_members_match_oracle(small_oracle, precision, tol, branches):
         errs = member_errors(ens, m, o)
         print("member", m.index, "n", m.n, "sigma %.3g" % m.sigma, errs)
         for k, e in errs.items():
-            lim = tol
+            lim = fp64_p_tolerance(m.n) if (precision == 0 and k == "p") else tol
             if precision == 1 and k == "psi":
                 lim = MIXED_PSI_TOL
             if precision == 1 and k == "p":
@@ -108,11 +122,14 @@ def test_graph_replays_match_eager(branches):
         eager.step(4)
         graphed.launch(1)
         torch.cuda.synchronize()
-        for sa, sb in zip(all_states(eager), all_states(graphed)):
+        for sim, sa, sb in zip(eager.sims, all_states(eager), all_states(graphed)):
             errs = state_errors(sb["u"], sb["p"], sb["psi"], sb["X"],
                                 sa["u"], sa["p"], sa["psi"], sa["X"])
-            # equal up to the order of the atomic additions of spreading
-            assert max(errs.values()) <= 1e-13, (r, errs)
+            # equal up to the order of the atomic additions of spreading (which
+            # p sees through the conditioning of the psi solves)
+            for k, e in errs.items():
+                lim = fp64_p_tolerance(sim.cfg.n[0]) if k == "p" else 1e-13
+                assert e <= lim, (r, k, e, lim)
         # the program's own eager work between replays
         eager.step(2)
         graphed.step(2)
@@ -152,8 +169,7 @@ def test_tune_picks_valid_shapes_and_keeps_parity():
                 assert tx in (32, 64) and sm in (16, 32) and tx * ((n + sm - 1) // sm) <= 1024
     ens.run(steps, steps_per_launch=2)
     for m, o in zip(members, refs):
-        errs = member_errors(ens, m, o)
-        assert max(errs.values()) <= FP64_TOL, (m.index, errs)
+        check_fp64(m, member_errors(ens, m, o))
     ens.close()
 
 
