@@ -43,6 +43,9 @@ def parse():
                     help="approximate CPU budget of the oracle sample")
     ap.add_argument("--ensemble-steps", type=int, default=500,
                     help="steps of the batched 2-D ensemble (0 = skip it)")
+    ap.add_argument("--closure", choices=("full", "small", "off"), default="full",
+                    help="learned closure: 128^3 coarse vs 256^3 fine (full), 32^3 vs 64^3 "
+                         "(small) or skip")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB (3 times), the reference "
                          "for scaling hardware byte counters")
@@ -303,6 +306,13 @@ def main():
         print("# ensemble: %.1f member-steps/s, %.3f Gcell/s (%s)" % (
             line["ensemble"]["member_steps_per_s"], line["ensemble"]["gcell_updates_per_s"],
             line["ensemble"]["best_variant"]), file=sys.stderr, flush=True)
+    if args.closure != "off":
+        from paper_1305_3976_amd import closure_run
+        cargs = [] if args.closure == "full" else [
+            "--n-fine", "64", "--traj", "20", "--held", "4", "--snapshots", "12",
+            "--iters", "1200", "--crop", "26", "--rollout", "10"]
+        line["closure"] = closure_run.main(cargs)
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         ref, n, el, thr = oracle_sample(w, args.cpu_seconds)
         line["cpu_baseline"] = {"value": round(n / el, 5), "unit": "IB steps/s", "cores": thr,

@@ -157,6 +157,12 @@ ib_status ib_spread(ib_ctx *ctx, const double *X, const double *F,
                     const double *w, int64_t npts, void *const f_out[3],
                     int32_t accumulate);
 
+/* The Eulerian force density f of Step 2b as spread in the last step taken
+ * (at X^{n+1/2}), written densely into f_out[c] (grid dtype, zero where no
+ * point reached).  Enqueued on the context's stream; IB_E_STATE before the
+ * first step.  ib_spread does not disturb it; the next step replaces it. */
+ib_status ib_step_force(ib_ctx *ctx, void *const f_out[3]);
+
 /* Step 1a on given buffers: U[c][k] = sum_ij u_in[c]_ij delta_h(x - X_k) h^d.
  * X, U: FP64 device [dim][npts]; u_in[c]: grid dtype.  In a 2-D batch npts
  * must not exceed n_points and point k reads the layer the structure gave it. */

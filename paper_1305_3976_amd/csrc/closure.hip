@@ -9,10 +9,10 @@
 // channels] is one matrix-core instruction; 27 taps x (ci/16) of them build
 // the 32 x 32 output block.  A workgroup (4 waves) keeps every packed weight
 // fragment of the layer in LDS for its whole life and walks output tiles of
-// 32 x 4 x 2 voxels: it stages the tile's input halo (34 x 6 x 4 voxels, all
-// channels) in LDS, and each wave accumulates two rows.  Matrix-core lane
-// layout (32x32x16): lane l supplies A[row l%32][k 8(l/32)..+7] and
-// B[k 8(l/32)..+7][col l%32]; accumulator j of lane l is
+// 32 x 4 x 4 voxels: it stages the tile's input halo (34 x 6 x 6 voxels, all
+// channels) in LDS, and each wave accumulates the four rows of one z-slice.
+// Matrix-core lane layout (32x32x16): lane l supplies A[row l%32][k
+// 8(l/32)..+7] and B[k 8(l/32)..+7][col l%32]; accumulator j of lane l is
 // D[8(j/4) + 4(l/32) + j%4][l%32].
 #include <hip/hip_runtime.h>
 
@@ -29,7 +29,7 @@ typedef __bf16 bf16;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int TX = 32, TY = 4, TZ = 2;               // output tile (voxels)
+constexpr int TX = 32, TY = 4, TZ = 4;               // output tile (voxels); TZ = waves
 constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2;  // its input halo
 constexpr int NT = 256;                               // threads per workgroup
 constexpr int CO = 32;                                // output channels
@@ -40,6 +40,9 @@ __device__ __forceinline__ int wrapi(int i, int n) {
   return i < 0 ? i + n : i;
 }
 
+// Periodic index for -n <= i < 2n (one compare-and-add instead of a modulo).
+__device__ __forceinline__ int wrap1(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
 struct ConvArgs {
   const bf16 *x;      // [B][D2][D1][D0][CI]
   const bf16 *wp;     // packed fragments [27][CI/16][64][8]
@@ -47,7 +50,8 @@ struct ConvArgs {
   const bf16 *mask;   // [B][E2][E1][E0][32] or null: output *= (mask > 0)
   void *y;            // [B][E2][E1][E0][ystride]
   int B, D0, D1, D2, E0, E1, E2;
-  int off, wrap;
+  int off, wrap;  // wrap: 0 = zeros outside, 1 = periodic (dims >= TX + 2), 2 = periodic
+  int idx32;      // every input offset fits in 32 bits
   int relu, out_f32, co_store, ystride;
   int nt0, nt1, nt2, ntiles;
 };
@@ -79,10 +83,34 @@ __device__ __forceinline__ void load_halo(unsigned char *sh, const bf16 *x, int 
   }
 }
 
+struct TileXYZ {
+  int b, ox0, oy0, oz0;
+};
+
+__device__ __forceinline__ TileXYZ tile_xyz(int tile, int nt0, int nt1, int nt2) {
+  int r = tile;
+  const int t0 = r % nt0;
+  r /= nt0;
+  const int t1 = r % nt1;
+  r /= nt1;
+  const int t2 = r % nt2;
+  return {r / nt2, t0 * TX, t1 * TY, t2 * TZ};
+}
+
+// Forward convolution (and, with adjoint packing, the input gradient).
+// Wave w computes the 4 output rows (y = 0..3) of z-slice w of the tile.  For
+// each (tz, tx) it keeps the three weight fragments of ty = 0..2 in registers
+// and walks the 6 halo rows once: a halo row hy feeds output rows hy - ty, so
+// each A fragment read from LDS serves up to three matrix-core products.  A
+// tile's halo is fetched with all of a thread's loads in flight before any is
+// stored to LDS.
 template <int CI>
 __global__ __launch_bounds__(NT) void k_conv(ConvArgs a) {
   constexpr int KS = CI / 16;
   constexpr int VS = CI * 2 + 16;  // padded voxel stride in LDS (bytes)
+  constexpr int CH = CI / 8;
+  constexpr int NCHUNK = HX * HY * HZ * CH;
+  constexpr int PER = (NCHUNK + NT - 1) / NT;
   __shared__ __align__(16) unsigned char sw[27 * KS * 64 * 16];
   __shared__ __align__(16) unsigned char sh[HX * HY * HZ * VS];
   for (int c = threadIdx.x; c < 27 * KS * 64; c += NT)
@@ -90,51 +118,95 @@ __global__ __launch_bounds__(NT) void k_conv(ConvArgs a) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 31, grp = lane >> 5;
   const float bias = (a.bias && col < a.co_store) ? a.bias[col] : 0.f;
-  for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
-    int r = tile;
-    const int t0 = r % a.nt0;
-    r /= a.nt0;
-    const int t1 = r % a.nt1;
-    r /= a.nt1;
-    const int t2 = r % a.nt2;
-    const int b = r / a.nt2;
-    const int ox0 = t0 * TX, oy0 = t1 * TY, oz0 = t2 * TZ;
-    __syncthreads();  // previous tile's reads of sh (and the weight copy) done
-    load_halo<CI, VS>(sh, a.x, b, ox0, oy0, oz0, a.D0, a.D1, a.D2, a.off, a.wrap);
-    __syncthreads();
-    f32x16 acc[2];
-    for (int mi = 0; mi < 2; mi++)
-      for (int j = 0; j < 16; j++) acc[mi][j] = 0.f;
-    // rows m = 2 wave + mi: (y, z) = (m % TY, m / TY)
-    const int m0 = 2 * wave;
-    const int my0 = m0 % TY, mz0 = m0 / TY;
-    const int my1 = (m0 + 1) % TY, mz1 = (m0 + 1) / TY;
-#pragma unroll 1
-    for (int t = 0; t < 27; t++) {
-      const int tz = t / 9, ty = (t / 3) % 3, tx = t % 3;
-      const int hx = col + tx;
-      const unsigned char *r0 = sh + (((mz0 + tz) * HY + my0 + ty) * HX + hx) * VS + grp * 16;
-      const unsigned char *r1 = sh + (((mz1 + tz) * HY + my1 + ty) * HX + hx) * VS + grp * 16;
+  uint4 pre[PER];
+  auto fetch = [&](int tile) {
+    const TileXYZ t = tile_xyz(tile, a.nt0, a.nt1, a.nt2);
 #pragma unroll
-      for (int ks = 0; ks < KS; ks++) {
-        const bf16x8 bw = *reinterpret_cast<const bf16x8 *>(sw + ((t * KS + ks) * 64 + lane) * 16);
-        const bf16x8 a0 = *reinterpret_cast<const bf16x8 *>(r0 + ks * 32);
-        const bf16x8 a1 = *reinterpret_cast<const bf16x8 *>(r1 + ks * 32);
-        acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, bw, acc[0], 0, 0, 0);
-        acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, bw, acc[1], 0, 0, 0);
+    for (int q = 0; q < PER; q++) {
+      const int c = threadIdx.x + q * NT;
+      pre[q] = make_uint4(0, 0, 0, 0);
+      if (c < NCHUNK) {
+        const int v = c / CH, part = c - v * CH;
+        const int hx = v % HX, hy = (v / HX) % HY, hz = v / (HX * HY);
+        int gx = t.ox0 + hx + a.off, gy = t.oy0 + hy + a.off, gz = t.oz0 + hz + a.off;
+        bool in = true;
+        if (a.wrap == 1) {
+          gx = wrap1(gx, a.D0), gy = wrap1(gy, a.D1), gz = wrap1(gz, a.D2);
+        } else if (a.wrap) {
+          gx = wrapi(gx, a.D0), gy = wrapi(gy, a.D1), gz = wrapi(gz, a.D2);
+        } else {
+          in = gx >= 0 && gx < a.D0 && gy >= 0 && gy < a.D1 && gz >= 0 && gz < a.D2;
+        }
+        if (in) {
+          if (a.idx32) {
+            const uint32_t vox = ((uint32_t)(t.b * a.D2 + gz) * a.D1 + gy) * a.D0 + gx;
+            pre[q] = *reinterpret_cast<const uint4 *>(a.x + vox * CI + part * 8);
+          } else {
+            const size_t vox = (((size_t)t.b * a.D2 + gz) * a.D1 + gy) * a.D0 + gx;
+            pre[q] = *reinterpret_cast<const uint4 *>(a.x + vox * CI + part * 8);
+          }
+        }
+      }
+    }
+  };
+  for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+    fetch(tile);      // all of this thread's halo loads in flight at once
+    __syncthreads();  // the previous tile's reads of sh (and the weight copy) are done
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+      const int c = threadIdx.x + q * NT;
+      if (c < NCHUNK) {
+        const int v = c / CH, part = c - v * CH;
+        *reinterpret_cast<uint4 *>(sh + v * VS + part * 16) = pre[q];
+      }
+    }
+    __syncthreads();
+    f32x16 acc[TY];
+#pragma unroll
+    for (int m = 0; m < TY; m++)
+#pragma unroll
+      for (int j = 0; j < 16; j++) acc[m][j] = 0.f;
+#pragma unroll 1
+    for (int tz = 0; tz < 3; tz++) {
+#pragma unroll 1
+      for (int tx = 0; tx < 3; tx++) {
+        bf16x8 bw[3][KS];
+#pragma unroll
+        for (int ty = 0; ty < 3; ty++)
+#pragma unroll
+          for (int ks = 0; ks < KS; ks++)
+            bw[ty][ks] = *reinterpret_cast<const bf16x8 *>(
+                sw + (((9 * tz + 3 * ty + tx) * KS + ks) * 64 + lane) * 16);
+        const unsigned char *base = sh + ((wave + tz) * HY * HX + col + tx) * VS + grp * 16;
+#pragma unroll
+        for (int hy = 0; hy < HY; hy++) {
+#pragma unroll
+          for (int ks = 0; ks < KS; ks++) {
+            const bf16x8 av = *reinterpret_cast<const bf16x8 *>(base + hy * HX * VS + ks * 32);
+#pragma unroll
+            for (int ty = 0; ty < 3; ty++) {
+              const int my = hy - ty;
+              if (my >= 0 && my < TY)
+                acc[my] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bw[ty][ks], acc[my], 0, 0, 0);
+            }
+          }
+        }
       }
     }
     // epilogue: lane holds output channel `col` of 16 voxels per row
-    for (int mi = 0; mi < 2; mi++) {
-      const int oy = oy0 + (mi ? my1 : my0), oz = oz0 + (mi ? mz1 : mz0);
+    const TileXYZ t = tile_xyz(tile, a.nt0, a.nt1, a.nt2);
+    const int oz = t.oz0 + wave;
+#pragma unroll
+    for (int my = 0; my < TY; my++) {
+      const int oy = t.oy0 + my;
       if (oy >= a.E1 || oz >= a.E2 || col >= a.co_store) continue;
-      const size_t rowv = (((size_t)b * a.E2 + oz) * a.E1 + oy) * a.E0;
+      const size_t rowv = (((size_t)t.b * a.E2 + oz) * a.E1 + oy) * a.E0;
 #pragma unroll
       for (int j = 0; j < 16; j++) {
-        const int ox = ox0 + 8 * (j >> 2) + 4 * grp + (j & 3);
+        const int ox = t.ox0 + 8 * (j >> 2) + 4 * grp + (j & 3);
         if (ox >= a.E0) continue;
         const size_t vox = rowv + ox;
-        float v = acc[mi][j] + bias;
+        float v = acc[my][j] + bias;
         if (a.relu) v = fmaxf(v, 0.f);
         if (a.mask && !((float)a.mask[vox * CO + col] > 0.f)) v = 0.f;
         if (a.out_f32)
@@ -471,6 +543,8 @@ ib_status launch_conv(const bf16 *x, int32_t batch, const int32_t *in_dims, int3
   if (nt >= INT32_MAX) return fail(IB_E_INVALID, "too many tiles");
   a.ntiles = (int)nt;
   const int grid = (int)(nt < WG_CONV ? nt : WG_CONV);
+  if (wrap && (a.D0 < HX || a.D1 < HY || a.D2 < HZ)) a.wrap = 2;
+  a.idx32 = (vi * ci_pad < ((int64_t)1 << 31)) ? 1 : 0;
   if (ci_pad == 16) k_conv<16><<<grid, NT, 0, st>>>(a);
   else k_conv<32><<<grid, NT, 0, st>>>(a);
   HIP_CHECK_LAUNCH("conv3d");

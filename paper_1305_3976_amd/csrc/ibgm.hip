@@ -104,6 +104,7 @@ struct ib_ctx {
   double *l_dt, *l_mom_alpha, *l_mom_invc, *l_psi_invc;
   // tile shapes chosen by ib_tune, per axis and recurrence type (0 = float)
   bool tuned;
+  bool have_force;  // a step has spread its force into the workspace
   SweepTune tune[3][2];
   // profiling
   bool prof;
@@ -612,6 +613,7 @@ static void enqueue_step(ib_ctx *c) {
   for (int s = 1; s < DIM - 1; s++) sweep<T, SW_PLAIN>(c, KP_PSI_X_PLAIN, q, order[s], 1, c->stream);
   sweep<T, SW_PFINAL>(c, KP_PSI_X_PFINAL, q, order[DIM - 1], 1, c->stream);
   c->step = n + 1;
+  c->have_force = true;
 }
 
 static void enqueue_any(ib_ctx *c);
@@ -854,6 +856,31 @@ extern "C" ib_status ib_spread(ib_ctx *c, const double *X, const double *F, cons
   } else {
     if (c->dim == 2) launch_spread<double, 2, true>(c, X, F, w, npts, f_out);
     else launch_spread<double, 3, true>(c, X, F, w, npts, f_out);
+  }
+  HIP_TRY(hipGetLastError());
+  return IB_OK;
+}
+
+template <typename T, int DIM>
+static void launch_force_dense(ib_ctx *c, void *const f_out[3]) {
+  const unsigned nb = (unsigned)((c->g.ncell + 255) / 256);
+  k_force_dense<T, DIM><<<nb, 256, 0, c->stream>>>(
+      (const T *)c->f[0], (const T *)c->f[1], (const T *)(DIM == 3 ? c->f[2] : c->f[0]),
+      c->t_flag, c->g, c->tg, (T *)f_out[0], (T *)f_out[1], (T *)(DIM == 3 ? f_out[2] : f_out[0]));
+}
+
+extern "C" ib_status ib_step_force(ib_ctx *c, void *const f_out[3]) {
+  if (!c) return fail(IB_E_STATE, "null context");
+  if (!c->have_force) return fail(IB_E_STATE, "no step has been taken yet");
+  if (!f_out) return fail(IB_E_INVALID, "null output");
+  for (int i = 0; i < c->dim; i++)
+    if (!f_out[i]) return fail(IB_E_INVALID, "null output component %d", i);
+  if (c->f32) {
+    if (c->dim == 2) launch_force_dense<float, 2>(c, f_out);
+    else launch_force_dense<float, 3>(c, f_out);
+  } else {
+    if (c->dim == 2) launch_force_dense<double, 2>(c, f_out);
+    else launch_force_dense<double, 3>(c, f_out);
   }
   HIP_TRY(hipGetLastError());
   return IB_OK;

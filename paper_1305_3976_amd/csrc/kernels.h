@@ -605,6 +605,26 @@ __global__ void __launch_bounds__(256) k_spread_tiles(SpreadArgs<T, DIM> a) {
 
 // ------------------------------------------ Eulerian: Steps 3a-3b fused --
 
+// Dense copy of the force density spread in the last step: f where the
+// tile was flagged as holding force, 0 elsewhere (the spreading never writes
+// unflagged tiles).
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256) k_force_dense(const T *f0, const T *f1, const T *f2,
+                                                      const int *flag, Grid g, TileGrid tg,
+                                                      T *o0, T *o1, T *o2) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= g.ncell) return;
+  const int i = (int)(idx % g.n0);
+  const int j = (int)((idx / g.n0) % g.n1);
+  const int k = (int)(idx / ((int64_t)g.n0 * g.n1));
+  const int64_t tile =
+      i / TS + (int64_t)tg.nt[0] * (j / TS + (int64_t)tg.nt[1] * (DIM == 3 ? k / TS : k));
+  const bool forced = flag[tile] != 0;
+  o0[idx] = forced ? f0[idx] : T(0);
+  o1[idx] = forced ? f1[idx] : T(0);
+  if (DIM == 3) o2[idx] = forced ? f2[idx] : T(0);
+}
+
 // One thread per cell.  For each component c at its face:
 //   N_c  = skew advection (Morinishi 2nd-order staggered: 1/2 divergence form
 //          + 1/2 advective form),

@@ -70,6 +70,7 @@ def _load():
     L.ib_spread.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int64, _vp * 3, ctypes.c_int32]
     L.ib_interp.argtypes = [_vp, _vp, ctypes.c_int64, _vp * 3, _vp]
     L.ib_force.argtypes = [_vp, _vp, _vp]
+    L.ib_step_force.argtypes = [_vp, _vp * 3]
     L.ib_line_solve.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                 ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
                                 ctypes.c_double, ctypes.c_double, _vp]
@@ -100,8 +101,8 @@ def _load():
                                     i32, _ip, i32, i32, _vp, _vp]
     L.ib_closure_apply.argtypes = [ctypes.POINTER(_vp), _ip, _vp, f32, _vp]
     for f in ("ib_workspace_size", "ib_init", "ib_step", "ib_restart", "ib_sync", "ib_spread", "ib_interp",
-              "ib_force", "ib_line_solve", "ib_destroy", "ib_profile_enable", "ib_profile_read",
-              "ib_tune", "ib_tune_read", "ib_graph_create", "ib_graph_launch",
+              "ib_force", "ib_step_force", "ib_line_solve", "ib_destroy", "ib_profile_enable",
+              "ib_profile_read", "ib_tune", "ib_tune_read", "ib_graph_create", "ib_graph_launch",
               "ib_graph_destroy") + CLOSURE_EXPORTED:
         getattr(L, f).restype = ctypes.c_int
     return L
@@ -115,7 +116,8 @@ CLOSURE_EXPORTED = ("ib_conv3d_pack", "ib_conv3d_fwd", "ib_conv3d_bwd_data",
 lib = _load()
 
 EXPORTED = ("ib_workspace_size", "ib_init", "ib_step", "ib_restart", "ib_sync", "ib_spread", "ib_interp",
-            "ib_force", "ib_line_solve", "ib_destroy", "ib_last_error", "ib_profile_enable",
+            "ib_force", "ib_step_force", "ib_line_solve", "ib_destroy", "ib_last_error",
+            "ib_profile_enable",
             "ib_profile_count", "ib_profile_name", "ib_profile_read", "ib_tune", "ib_tune_read",
             "ib_graph_create", "ib_graph_launch", "ib_graph_destroy") + CLOSURE_EXPORTED
 
@@ -300,6 +302,16 @@ class Simulation:
         F = torch.empty_like(X)
         check(lib.ib_force(self.ctx, _ptr(X), _ptr(F)))
         return F
+
+    def step_force(self, out=None):
+        """The force density spread in the last step (grid dtype, dense)."""
+        d = self.cfg.dim
+        if out is None:
+            out = [torch.empty(self.cfg.shape, dtype=self.cfg.grid_dtype, device=self.X.device)
+                   for _ in range(d)]
+        ptrs = (_vp * 3)(*[out[c].data_ptr() if c < d else None for c in range(3)])
+        check(lib.ib_step_force(self.ctx, ptrs))
+        return out
 
     # -- tuning --------------------------------------------------------------
     def tune(self, reps: int = 3):

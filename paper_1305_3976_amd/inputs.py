@@ -213,7 +213,6 @@ def random_vector_potential_velocity_3d(n: int, kmax: int = 4, amp: float = 0.1,
     rng = np.random.default_rng(seed)
     h = 1.0 / n
     g = np.arange(n) * h
-    Z, Y, Xg = np.meshgrid(g, g, g, indexing="ij")
     A = []
     for c in range(3):
         off = [0.0, 0.0, 0.0]
@@ -224,8 +223,11 @@ def random_vector_potential_velocity_3d(n: int, kmax: int = 4, amp: float = 0.1,
             if not k.any():
                 continue
             a, b = rng.standard_normal(2)
-            ph = 2 * np.pi * (k[0] * (Xg + off[0]) + k[1] * (Y + off[1]) + k[2] * (Z + off[2]))
-            acc += a * np.cos(ph) + b * np.sin(ph)
+            # a cos(phase) + b sin(phase) = Re((a - i b) e^{i phase}), the
+            # phase 2 pi k.(x + off) separating into one factor per axis
+            e = [np.exp(2j * np.pi * k[ax] * (g + off[ax])) for ax in range(3)]
+            acc += ((a - 1j * b) * e[2][:, None, None] * e[1][None, :, None]
+                    * e[0][None, None, :]).real
         A.append(acc)
     # axis numbering: array axes (2, 1, 0) = (z, y, x)
     def d(q, ax):  # forward difference along grid axis ax (0 = x)

@@ -148,3 +148,30 @@ def test_shell3d_plane_marching_explicit(precision, tol):
     print("shell3d tiled precision", precision, errs)
     check(errs, tol)
     g.close()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_step_force_is_the_spread_link_force(dim):
+    """ib_step_force returns f of Step 2b: the link force at X^{n+1/2} spread
+    to the grid (checked with ib_force and ib_spread at the same positions)."""
+    if dim == 2:
+        w = inputs.config_ellipse_64(steps=3)
+        w.u0 = inputs.random_streamfunction_velocity_2d(64, 4, 0.1, seed=3)
+    else:
+        w = inputs.config_shell_256(steps=3, n=32, npts=1024)
+        w.u0 = inputs.random_vector_potential_velocity_3d(32, 4, 0.1, seed=3)
+    g = gpu_sim(w, 0)
+    with pytest.raises(Exception):
+        g.step_force()                     # no step taken yet
+    g.step(2)
+    Xn = g.X.clone()
+    g.step(1)
+    Xh = 0.5 * (Xn + g.X)                  # X^{n+1/2} (AB2 step, n >= 1)
+    f = g.step_force()
+    F = g.force(Xh)
+    wt = torch.as_tensor(w.structure.w).to(g.X.device)
+    ref = g.spread(Xh, F, wt)
+    torch.cuda.synchronize()
+    for c in range(dim):
+        assert rel_l2(f[c].cpu().numpy(), ref[c].cpu().numpy()) <= 1e-12, c
+    g.close()
