@@ -38,6 +38,9 @@ def parse():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--points", type=int, default=65536)
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--tune", action="store_true",
+                    help="let ib_tune pick the sweep tiles (the library defaults are faster "
+                         "on the 256^3 step)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="approximate CPU budget of the oracle sample")
@@ -78,13 +81,14 @@ def step_bytes(b: int, ncell: int, dim: int) -> float:
     return ((4 * dim + 1) * b + 8 + mom + psi) * ncell
 
 
-def run_gpu(w, precision, steps, warmup):
+def run_gpu(w, precision, steps, warmup, tune=False):
     import torch
     from paper_1305_3976_amd import ibgm
     cfg = ibgm.Config(w.dim, w.n, w.h, rho=w.rho, mu=w.mu, dt=w.dt, chi=w.chi,
                       precision=precision)
     sim = ibgm.Simulation(cfg, w.u0, w.structure)
     stream = sim.stream
+    picks = sim.tune(3) if tune else None
     sim.step(warmup)
     sim.sync()
     # timed region: K steps with per-kernel HIP events on the library's stream
@@ -111,7 +115,7 @@ def run_gpu(w, precision, steps, warmup):
     sim.close()
     del sim
     torch.cuda.empty_cache()
-    return ms, ms_plain, wall, kern
+    return ms, ms_plain, wall, kern, picks
 
 
 def run_ensemble(steps, spl_choices=(2, 10), seed=4):
@@ -246,12 +250,13 @@ def main():
     for prec, tag in ((1, "mixed"), (0, "fp64")):
         if prec == 0 and args.no_fp64:
             continue
-        ms, ms_plain, wall, kern = run_gpu(w, prec, args.steps, args.warmup)
-        res[tag] = (ms, ms_plain, wall, kern)
+        ms, ms_plain, wall, kern, picks = run_gpu(w, prec, args.steps, args.warmup,
+                                                  args.tune)
+        res[tag] = (ms, ms_plain, wall, kern, picks)
         print("# %s: %.3f ms/step (profiled), %.3f ms/step (plain)" % (
             tag, ms / args.steps, ms_plain / args.steps), file=sys.stderr, flush=True)
 
-    ms, ms_plain, wall, kern = res["mixed"]
+    ms, ms_plain, wall, kern, picks = res["mixed"]
     b = 4
     rows = {}
     for name, (tot, cnt) in kern.items():
@@ -291,9 +296,11 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None},
         "kernels": rows,
+        "tuned_tiles": None if picks is None else {
+            "%d/%s" % (a, "f64" if r else "f32"): list(v) for (a, r), v in picks.items()},
     }
     if "fp64" in res:
-        ms64, ms64_plain, _, kern64 = res["fp64"]
+        ms64, ms64_plain, _, kern64, _ = res["fp64"]
         s64 = args.steps / (ms64_plain * 1e-3)
         line["fp64"] = {"value": round(s64, 3), "unit": "IB steps/s",
                         "ms_per_step": round(ms64_plain / args.steps, 4),

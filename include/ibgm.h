@@ -23,8 +23,15 @@
  *   Precision.  IB_PREC_FP64: every grid array is FP64.  IB_PREC_MIXED: the
  *               velocity-like grid arrays (u, nl_prev, psi, div_prev, the
  *               workspace and spread forces) are FP32, while p, X, U stay
- *               FP64.  Pressure-increment recurrences always run in FP64
- *               registers; momentum recurrences in the storage precision.
+ *               FP64.  IB_PREC_MIXED_STATE64: as MIXED, but the velocity u
+ *               is FP64 (the explicit step computes in FP64, the momentum
+ *               sweeps solve FP32 increments, u += increment in FP64), which
+ *               keeps D.u^{n+1} -- and so psi and p -- free of the FP32
+ *               rounding of u.  "grid dtype" below is FP32 for both mixed
+ *               policies; u_in of ib_interp and the u buffers take the
+ *               velocity dtype.  Pressure-increment recurrences always run in
+ *               FP64 registers; momentum recurrences in the storage
+ *               precision.
  *   Streams.    Work is enqueued on the hipStream_t given to ib_init (or to
  *               ib_line_solve) and returns before it completes.  Device faults
  *               surface at the next call that synchronises (ib_sync).
@@ -56,7 +63,13 @@ typedef enum {
 } ib_status;
 
 typedef enum { IB_F64 = 0, IB_F32 = 1 } ib_dtype;
-typedef enum { IB_PREC_FP64 = 0, IB_PREC_MIXED = 1 } ib_precision;
+typedef enum {
+  IB_PREC_FP64 = 0,         /* every grid array FP64 */
+  IB_PREC_MIXED = 1,        /* FP32 grid arrays; FP64 p, X, U */
+  IB_PREC_MIXED_STATE64 = 2 /* FP32 line solves, spreading and work arrays
+                               (nl_prev, psi, div_prev, workspace); FP64
+                               velocity u, p, X, U */
+} ib_precision;
 
 /* flags */
 #define IB_FLAG_NO_ADVECTION 1 /* drop the advection term (Stokes flow) */
@@ -89,7 +102,7 @@ typedef struct {
 /* Device state, caller-owned, borrowed by the context until ib_destroy.
  * "grid dtype" = FP64 (IB_PREC_FP64) or FP32 (IB_PREC_MIXED). */
 typedef struct {
-  void *u[3];       /* u^n per component, grid dtype, [n2][n1][n0]; updated in place */
+  void *u[3];       /* u^n per component, velocity dtype, [n2][n1][n0]; updated in place */
   void *nl_prev[3]; /* N(u^{n-1}) (skew advection), grid dtype; overwritten each step */
   void *psi;        /* psi^{n-1/2}, grid dtype, cell centred */
   void *div_prev;   /* D.u^n, grid dtype, cell centred (written by ib_init if step0 == 0) */
@@ -164,7 +177,7 @@ ib_status ib_spread(ib_ctx *ctx, const double *X, const double *F,
 ib_status ib_step_force(ib_ctx *ctx, void *const f_out[3]);
 
 /* Step 1a on given buffers: U[c][k] = sum_ij u_in[c]_ij delta_h(x - X_k) h^d.
- * X, U: FP64 device [dim][npts]; u_in[c]: grid dtype.  In a 2-D batch npts
+ * X, U: FP64 device [dim][npts]; u_in[c]: velocity dtype.  In a 2-D batch npts
  * must not exceed n_points and point k reads the layer the structure gave it. */
 ib_status ib_interp(ib_ctx *ctx, const double *X, int64_t npts,
                     void *const u_in[3], double *U);

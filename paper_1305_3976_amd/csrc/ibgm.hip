@@ -13,6 +13,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "errors.h"
@@ -51,13 +52,15 @@ enum KernelId {
   KP_INTERP_EVOLVE = 0, KP_FORCE, KP_SPREAD, KP_EXPLICIT, KP_DIVERGENCE,
   KP_MOM_X_PLAIN, KP_MOM_S_PLAIN, KP_MOM_X_FINAL, KP_MOM_S_FINAL,
   KP_PSI_X_FIRST, KP_PSI_S_FIRST, KP_PSI_X_PLAIN, KP_PSI_S_PLAIN,
-  KP_PSI_X_PFINAL, KP_PSI_S_PFINAL, KP_LINE_X, KP_LINE_S, KP_INTERP, KP_SORT, KP_COUNT
+  KP_PSI_X_PFINAL, KP_PSI_S_PFINAL, KP_LINE_X, KP_LINE_S, KP_INTERP, KP_SORT, KP_ADD, KP_GAUGE,
+  KP_COUNT
 };
 static const char *kKernelNames[KP_COUNT] = {
     "interp_evolve", "force", "spread", "explicit", "divergence",
     "mom_x_plain", "mom_s_plain", "mom_x_final", "mom_s_final",
     "psi_x_first", "psi_s_first", "psi_x_plain", "psi_s_plain",
-    "psi_x_pfinal", "psi_s_pfinal", "line_x", "line_s", "interp", "spread_sort"};
+    "psi_x_pfinal", "psi_s_pfinal", "line_x", "line_s", "interp", "spread_sort", "add_increment",
+    "psi_gauge"};
 
 struct PendingEvent {
   int id;
@@ -80,8 +83,9 @@ struct ib_ctx {
   int dim;
   Grid g;
   int64_t np;
-  bool f32;
-  size_t tsz;  // bytes per grid value
+  bool f32;    // work arrays (N, psi, div, workspace) in FP32
+  bool u64;    // velocity state in FP64 while the work arrays are FP32
+  size_t tsz;  // bytes per work-array value
   // workspace
   void *delta[3], *f[3], *divn;
   double *Xn1, *Xh, *F;
@@ -105,6 +109,7 @@ struct ib_ctx {
   // tile shapes chosen by ib_tune, per axis and recurrence type (0 = float)
   bool tuned;
   bool have_force;  // a step has spread its force into the workspace
+  double *gauge, *gauge_part;  // psi means per layer and their partial sums
   SweepTune tune[3][2];
   // profiling
   bool prof;
@@ -369,7 +374,8 @@ static ib_status check_params(const ib_grid_params *p) {
   if (!(std::isfinite(p->mu) && p->mu >= 0)) return fail(IB_E_INVALID, "mu must be finite and >= 0");
   if (!(std::isfinite(p->chi) && p->chi >= 0 && p->chi <= 1))
     return fail(IB_E_INVALID, "chi must lie in [0, 1]");
-  if (p->precision != IB_PREC_FP64 && p->precision != IB_PREC_MIXED)
+  if (p->precision != IB_PREC_FP64 && p->precision != IB_PREC_MIXED &&
+      p->precision != IB_PREC_MIXED_STATE64)
     return fail(IB_E_INVALID, "unknown precision %d", p->precision);
   if (p->step0 < 0) return fail(IB_E_INVALID, "step0 must be >= 0");
   if (p->flags & ~IB_FLAG_NO_ADVECTION) return fail(IB_E_INVALID, "unknown flags 0x%x", p->flags);
@@ -390,9 +396,16 @@ static TileGrid tile_grid(const ib_grid_params *p) {
 // weights per component and axis, spread values); the spreading tile tables
 // (counts, flags, touched list, starts, block sums), the point sort (tile,
 // rank); the touched-list length; one status word.
+// psi gauge (mixed policies): per layer, GAUGE_BLOCKS partial sums and the mean
+constexpr int GAUGE_BLOCKS = 256;
+static int64_t gauge_layers(const ib_grid_params *p) { return p->dim == 2 ? p->n[2] : 1; }
+static size_t gauge_bytes(const ib_grid_params *p) {
+  return align256(sizeof(double) * (size_t)gauge_layers(p) * (GAUGE_BLOCKS + 1));
+}
+
 static size_t workspace_bytes(const ib_grid_params *p, int64_t np) {
   const size_t nc = (size_t)p->n[0] * p->n[1] * p->n[2];
-  const size_t t = p->precision == IB_PREC_MIXED ? 4 : 8;
+  const size_t t = p->precision == IB_PREC_FP64 ? 8 : 4;
   const size_t npp = (size_t)(np > 0 ? np : 1);
   const size_t lag = sizeof(double) * (size_t)p->dim * npp;
   const TileGrid tg = tile_grid(p);
@@ -400,7 +413,7 @@ static size_t workspace_bytes(const ib_grid_params *p, int64_t np) {
   return 7 * align256(nc * t) + 3 * align256(lag) + align256(sizeof(int) * 9 * npp) +
          align256(t * 36 * npp) + align256(t * 3 * npp) + 3 * align256(sizeof(int) * tg.ntiles) +
          align256(sizeof(int) * (tg.ntiles + 1)) + align256(sizeof(int) * nb) +
-         2 * align256(sizeof(int) * npp) + 256 + 256;
+         2 * align256(sizeof(int) * npp) + 256 + 256 + gauge_bytes(p);
 }
 
 extern "C" ib_status ib_workspace_size(const ib_grid_params *prm, int64_t n_points,
@@ -508,11 +521,11 @@ static void launch_spread(ib_ctx *c, const double *X, const double *F, const dou
   });
 }
 
-template <typename T, int DIM>
+template <typename T, int DIM, typename V = T>
 static void launch_explicit(ib_ctx *c, bool first) {
-  ExplicitArgs<T, DIM> a{};
+  ExplicitArgs<T, DIM, V> a{};
   for (int i = 0; i < 3; i++) {
-    a.u[i] = (const T *)(i < DIM ? c->buf.u[i] : nullptr);
+    a.u[i] = (const V *)(i < DIM ? c->buf.u[i] : nullptr);
     a.nl[i] = (T *)(i < DIM ? c->buf.nl_prev[i] : nullptr);
     a.f[i] = (const T *)(i < DIM ? c->f[i] : nullptr);
     a.delta[i] = (T *)(i < DIM ? c->delta[i] : nullptr);
@@ -534,40 +547,60 @@ static void launch_explicit(ib_ctx *c, bool first) {
     if (c->g.n0 % EX == 0 && c->g.n1 % EY == 0 && c->g.ncell < INT32_MAX) {
       const dim3 grid((c->g.n0 / EX) * (c->g.n1 / EY) * ((c->g.n2 + EZ - 1) / EZ));
       launch(c, KP_EXPLICIT, [&] {
-        hipLaunchKernelGGL((k_explicit3<T>), grid, dim3(EX * EY), 0, c->stream, a);
+        hipLaunchKernelGGL((k_explicit3<T, V>), grid, dim3(EX * EY), 0, c->stream, a);
       });
       return;
     }
   }
   launch(c, KP_EXPLICIT, [&] {
-    hipLaunchKernelGGL((k_explicit<T, DIM>), dim3((unsigned)((c->g.ncell + 255) / 256)),
+    hipLaunchKernelGGL((k_explicit<T, DIM, V>), dim3((unsigned)((c->g.ncell + 255) / 256)),
                        dim3(256), 0, c->stream, a);
   });
 }
 
-template <typename T, int DIM>
+// D.u of the velocity state (type V) into `out` (work type T).
+template <typename T, int DIM, typename V = T>
 static void launch_divergence(ib_ctx *c, void *out) {
   launch(c, KP_DIVERGENCE, [&] {
-    hipLaunchKernelGGL((k_divergence<T, DIM>), dim3((unsigned)((c->g.ncell + 255) / 256)),
-                       dim3(256), 0, c->stream, (const T *)c->buf.u[0],
-                       (const T *)c->buf.u[1], (const T *)(DIM == 3 ? c->buf.u[2] : nullptr),
+    hipLaunchKernelGGL((k_divergence<V, DIM, T>), dim3((unsigned)((c->g.ncell + 255) / 256)),
+                       dim3(256), 0, c->stream, (const V *)c->buf.u[0],
+                       (const V *)c->buf.u[1], (const V *)(DIM == 3 ? c->buf.u[2] : nullptr),
                        (T *)out, c->g, 1.0 / c->prm.h);
   });
 }
 
-// One full IB-GM step (Steps 1a-3f) at step index n.
-template <typename T, int DIM>
+// div_prev = D.u^0 at a fresh start.
+static void seed_divergence(ib_ctx *c) {
+  void *o = c->buf.div_prev;
+  if (c->u64) {
+    if (c->dim == 2) launch_divergence<float, 2, double>(c, o);
+    else launch_divergence<float, 3, double>(c, o);
+  } else if (c->f32) {
+    if (c->dim == 2) launch_divergence<float, 2>(c, o);
+    else launch_divergence<float, 3>(c, o);
+  } else {
+    if (c->dim == 2) launch_divergence<double, 2>(c, o);
+    else launch_divergence<double, 3>(c, o);
+  }
+}
+
+// One full IB-GM step (Steps 1a-3f) at step index n.  T: work arrays; V:
+// velocity state (V = double with T = float is the FP64-state policy: the
+// last momentum sweep then leaves its increment in the work array and
+// u += d runs in FP64).
+template <typename T, int DIM, typename V = T>
 static void enqueue_step(ib_ctx *c) {
+  constexpr bool kState64 = !std::is_same<T, V>::value;
   const int64_t n = c->step;
   const bool first = n == 0;
   // Steps 1a-1c
-  launch_interp<T, DIM>(c, KP_INTERP_EVOLVE, c->buf.X, c->np, c->buf.u, c->buf.U_prev,
+  launch_interp<V, DIM>(c, KP_INTERP_EVOLVE, c->buf.X, c->np, c->buf.u, c->buf.U_prev,
                         true, first);
   // Step 2a (+ commit X^{n+1}) and Step 2b
   launch_force<DIM>(c, c->Xh, c->F, true);
   launch_spread<T, DIM, false>(c, c->Xh, c->F, c->w, c->np, c->f);
   // Steps 3a-3b
-  launch_explicit<T, DIM>(c, first);
+  launch_explicit<T, DIM, V>(c, first);
   // split order of this step
   int order[3];
   const int shift = c->prm.rotate_split ? (int)(n % DIM) : 0;
@@ -584,16 +617,25 @@ static void enqueue_step(ib_ctx *c) {
   m.invc_layer = c->l_mom_invc;
   for (int i = 0; i < 3; i++) {
     m.f[i] = m.o[i] = (T *)(i < DIM ? c->delta[i] : nullptr);
-    m.u[i] = (T *)(i < DIM ? c->buf.u[i] : nullptr);
+    m.u[i] = kState64 ? nullptr : (T *)(i < DIM ? c->buf.u[i] : nullptr);
   }
   for (int s = 0; s < DIM; s++) {
-    if (s < DIM - 1) sweep<T, SW_PLAIN, T>(c, KP_MOM_X_PLAIN, m, order[s], DIM, c->stream);
+    if (s < DIM - 1 || kState64) sweep<T, SW_PLAIN, T>(c, KP_MOM_X_PLAIN, m, order[s], DIM, c->stream);
     else sweep<T, SW_FINAL, T>(c, KP_MOM_X_FINAL, m, order[s], DIM, c->stream);
+  }
+  if constexpr (kState64) {
+    launch(c, KP_ADD, [&] {
+      hipLaunchKernelGGL((k_add_increment<T, DIM>), dim3((unsigned)((c->g.ncell + 255) / 256)),
+                         dim3(256), 0, c->stream, (double *)c->buf.u[0], (double *)c->buf.u[1],
+                         (double *)(DIM == 3 ? c->buf.u[2] : c->buf.u[0]), (const T *)c->delta[0],
+                         (const T *)c->delta[1], (const T *)(DIM == 3 ? c->delta[2] : c->delta[0]),
+                         c->g.ncell);
+    });
   }
   // Steps 3e-3f: D.u^{n+1} into div_new, then the psi sweeps: the first
   // solves for -(rho/dt) div_new (the scale rides on 1/c) into psi, the last
   // also updates p and hands div_new to div_prev
-  launch_divergence<T, DIM>(c, c->divn);
+  launch_divergence<T, DIM, V>(c, c->divn);
   SweepArgs<T> q{};
   q.g = c->g;
   q.dim = DIM;
@@ -611,6 +653,21 @@ static void enqueue_step(ib_ctx *c) {
   q.p = c->buf.p;
   q.half_chi_mu = 0.5 * c->prm.chi * c->prm.mu;
   for (int s = 1; s < DIM - 1; s++) sweep<T, SW_PLAIN>(c, KP_PSI_X_PLAIN, q, order[s], 1, c->stream);
+  if (c->f32) {
+    // FP32 work arrays: measure the mean of psi (zero in exact arithmetic)
+    // before the last sweep, which removes it
+    const int64_t layers = DIM == 2 ? c->g.n2 : 1;
+    const int64_t per = c->g.ncell / layers;
+    int64_t nb = (per + 256 * 16 - 1) / (256 * 16);
+    nb = nb < 1 ? 1 : (nb > GAUGE_BLOCKS ? GAUGE_BLOCKS : nb);
+    launch(c, KP_GAUGE, [&] {
+      hipLaunchKernelGGL((k_layer_partial<T>), dim3((unsigned)nb, (unsigned)layers), dim3(256), 0,
+                         c->stream, (const T *)c->buf.psi, per, c->gauge_part);
+      hipLaunchKernelGGL(k_layer_mean, dim3((unsigned)layers), dim3(256), 0, c->stream,
+                         (const double *)c->gauge_part, (int)nb, per, c->gauge);
+    });
+    q.gauge = c->gauge;
+  }
   sweep<T, SW_PFINAL>(c, KP_PSI_X_PFINAL, q, order[DIM - 1], 1, c->stream);
   c->step = n + 1;
   c->have_force = true;
@@ -713,7 +770,8 @@ extern "C" ib_status ib_init(ib_ctx **out, const ib_grid_params *prm, const ib_b
   c->g.n2 = prm->n[2];
   c->g.ncell = (int64_t)c->g.n0 * c->g.n1 * c->g.n2;
   c->np = np;
-  c->f32 = prm->precision == IB_PREC_MIXED;
+  c->f32 = prm->precision != IB_PREC_FP64;
+  c->u64 = prm->precision == IB_PREC_MIXED_STATE64;
   c->tsz = c->f32 ? 4 : 8;
   c->mom_alpha = ma; c->mom_invc = mi; c->psi_alpha = pa; c->psi_invc = pi;
   c->nlinks = st->n_links;
@@ -741,7 +799,9 @@ extern "C" ib_status ib_init(ib_ctx **out, const ib_grid_params *prm, const ib_b
   c->tile_of = (int *)w; w += pb;
   c->rank_of = (int *)w; w += pb;
   c->t_nlist = (int *)w; w += 256;
-  c->flag = (int *)w;
+  c->flag = (int *)w; w += 256;
+  c->gauge = (double *)w;  // [layers] means, then [layers][GAUGE_BLOCKS] partials
+  c->gauge_part = c->gauge + gauge_layers(prm);
   // upload the structure
   auto bail = [&](ib_status e) { ib_destroy(c); return e; };
   if (hipMalloc(&c->ptr, sizeof(int32_t) * (np + 1)) != hipSuccess ||
@@ -780,15 +840,7 @@ extern "C" ib_status ib_init(ib_ctx **out, const ib_grid_params *prm, const ib_b
       hipMemsetAsync(c->t_flag, 0, tb, c->stream) != hipSuccess ||
       hipMemsetAsync(c->flag, 0, 256, c->stream) != hipSuccess)
     return bail(fail(IB_E_DEVICE, "clearing the workspace failed"));
-  if (prm->step0 == 0) {
-    if (c->f32) {
-      if (d == 2) launch_divergence<float, 2>(c, buf->div_prev);
-      else launch_divergence<float, 3>(c, buf->div_prev);
-    } else {
-      if (d == 2) launch_divergence<double, 2>(c, buf->div_prev);
-      else launch_divergence<double, 3>(c, buf->div_prev);
-    }
-  }
+  if (prm->step0 == 0) seed_divergence(c);
   // the host arrays above go out of scope: wait for the uploads
   if (hipStreamSynchronize(c->stream) != hipSuccess)
     return bail(fail(IB_E_DEVICE, "initialisation on the stream failed"));
@@ -803,13 +855,7 @@ extern "C" ib_status ib_restart(ib_ctx *c, int64_t step0) {
   if (c->prof) return fail(IB_E_STATE, "disable profiling before a restart");
   c->step = step0;
   if (step0 == 0) {
-    if (c->f32) {
-      if (c->dim == 2) launch_divergence<float, 2>(c, c->buf.div_prev);
-      else launch_divergence<float, 3>(c, c->buf.div_prev);
-    } else {
-      if (c->dim == 2) launch_divergence<double, 2>(c, c->buf.div_prev);
-      else launch_divergence<double, 3>(c, c->buf.div_prev);
-    }
+    seed_divergence(c);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(IB_E_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
   }
@@ -897,7 +943,7 @@ extern "C" ib_status ib_interp(ib_ctx *c, const double *X, int64_t npts, void *c
   for (int i = 0; i < c->dim; i++)
     if (!u_in[i]) return fail(IB_E_INVALID, "null input component %d", i);
   if (npts == 0) return IB_OK;
-  if (c->f32) {
+  if (c->f32 && !c->u64) {
     if (c->dim == 2) launch_interp<float, 2>(c, KP_INTERP, X, npts, u_in, U, false, false);
     else launch_interp<float, 3>(c, KP_INTERP, X, npts, u_in, U, false, false);
   } else {
@@ -1007,7 +1053,10 @@ extern "C" ib_status ib_profile_read(ib_ctx *c, int32_t id, double *total_ms,
 // ----------------------------------------------------------- autotuner --
 
 static void enqueue_any(ib_ctx *c) {
-  if (c->f32) {
+  if (c->u64) {
+    if (c->dim == 2) enqueue_step<float, 2, double>(c);
+    else enqueue_step<float, 3, double>(c);
+  } else if (c->f32) {
     if (c->dim == 2) enqueue_step<float, 2>(c);
     else enqueue_step<float, 3>(c);
   } else {

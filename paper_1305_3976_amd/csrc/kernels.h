@@ -633,9 +633,9 @@ __global__ void __launch_bounds__(256) k_force_dense(const T *f0, const T *f1, c
 // and stores d*_c (the delta-form right-hand side of the first sweep) and
 // N_c into nl (for the next step).  f_c is read only in tiles the spreading
 // flagged as holding force (zero elsewhere).
-template <typename T, int DIM>
+template <typename T, int DIM, typename V = T>
 struct ExplicitArgs {
-  const T *u[3];
+  const V *u[3];  // velocity state (V = double under the FP64-state policy)
   T *nl[3];
   const T *f[3];
   T *delta[3];
@@ -649,9 +649,9 @@ struct ExplicitArgs {
   int first, advect;
 };
 
-template <typename T, int DIM>
-__global__ void __launch_bounds__(256) k_explicit(ExplicitArgs<T, DIM> a) {
-  using C = T;
+template <typename T, int DIM, typename V = T>
+__global__ void __launch_bounds__(256) k_explicit(ExplicitArgs<T, DIM, V> a) {
+  using C = V;  // arithmetic in the precision of the velocity state
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= a.g.ncell) return;
   const int64_t n0 = a.g.n0, n1 = a.g.n1, n2 = a.g.n2;
@@ -675,7 +675,7 @@ __global__ void __launch_bounds__(256) k_explicit(ExplicitArgs<T, DIM> a) {
   const C dt = (C)((DIM == 2 && a.dt_layer) ? a.dt_layer[k] : a.dt);
 #pragma unroll
   for (int ci = 0; ci < DIM; ci++) {
-    const T *__restrict__ ui = a.u[ci];
+    const V *__restrict__ ui = a.u[ci];
     const C u0 = (C)ui[idx];
     C dv = 0, ad = 0, lap = 0;
 #pragma unroll
@@ -688,7 +688,7 @@ __global__ void __launch_bounds__(256) k_explicit(ExplicitArgs<T, DIM> a) {
         dv += ap * ap - am * am;
         ad += C(0.5) * (ap * (up - u0) + am * (u0 - um));
       } else {
-        const T *__restrict__ uj = a.u[cj];
+        const V *__restrict__ uj = a.u[cj];
         const C Uj0 = C(0.5) * ((C)uj[idx + dm[ci]] + (C)uj[idx]);
         const C Uj1 = C(0.5) * ((C)uj[idx + dp[cj] + dm[ci]] + (C)uj[idx + dp[cj]]);
         dv += Uj1 * C(0.5) * (u0 + up) - Uj0 * C(0.5) * (um + u0);
@@ -721,9 +721,9 @@ constexpr int ENT = EX * EY;             // threads per workgroup
 constexpr int VPT = (EH * EW + ENT - 1) / ENT;  // velocity entries per thread
 constexpr int PPT = (PH * PW + ENT - 1) / ENT;  // p* entries per thread
 
-template <typename T>
-__global__ void __launch_bounds__(ENT) k_explicit3(ExplicitArgs<T, 3> a) {
-  using C = T;
+template <typename T, typename V = T>
+__global__ void __launch_bounds__(ENT) k_explicit3(ExplicitArgs<T, 3, V> a) {
+  using C = V;  // arithmetic in the precision of the velocity state
   __shared__ C U[3][3][EH * EW];
   __shared__ double PS[PH * PW];
   const int n0 = a.g.n0, n1 = a.g.n1, n2 = a.g.n2;
@@ -789,7 +789,7 @@ __global__ void __launch_bounds__(ENT) k_explicit3(ExplicitArgs<T, 3> a) {
     C vr[3][VPT];
     double pr[PPT];
     if (more) {
-      const T *u0p = a.u[0] + pbase(k + 2), *u1p = a.u[1] + pbase(k + 2),
+      const V *u0p = a.u[0] + pbase(k + 2), *u1p = a.u[1] + pbase(k + 2),
               *u2p = a.u[2] + pbase(k + 2);
 #pragma unroll
       for (int q = 0; q < VPT; q++) {
@@ -871,10 +871,11 @@ __global__ void __launch_bounds__(ENT) k_explicit3(ExplicitArgs<T, 3> a) {
   }
 }
 
-// D.u at every cell (used once, to seed div_prev = D.u^0).
-template <typename T, int DIM>
+// D.u at every cell: Step 3e's right-hand side, and the seed div_prev = D.u^0
+// (u in the velocity type T, D.u stored in the work type TD).
+template <typename T, int DIM, typename TD = T>
 __global__ void __launch_bounds__(256) k_divergence(const T *u0, const T *u1,
-                                                     const T *u2, T *out, Grid g,
+                                                     const T *u2, TD *out, Grid g,
                                                      double inv_h) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= g.ncell) return;
@@ -885,7 +886,20 @@ __global__ void __launch_bounds__(256) k_divergence(const T *u0, const T *u1,
   if (DIM == 3)
     s += (double)u2[idx + ((k + 1 == n2) ? -(n2 - 1) * n0 * n1 : n0 * n1)] -
          (double)u2[idx];
-  out[idx] = (T)(s * inv_h);
+  out[idx] = (TD)(s * inv_h);
+}
+
+// FP64-state policy: u^{n+1} = u^n + d (the last momentum increment, stored
+// in the work precision), accumulated in FP64.
+template <typename TD, int DIM>
+__global__ void __launch_bounds__(256) k_add_increment(double *u0, double *u1, double *u2,
+                                                        const TD *d0, const TD *d1,
+                                                        const TD *d2, int64_t ncell) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= ncell) return;
+  u0[idx] += (double)d0[idx];
+  u1[idx] += (double)d1[idx];
+  if (DIM == 3) u2[idx] += (double)d2[idx];
 }
 
 // ------------------------------------------------------------ line solves --
@@ -918,6 +932,7 @@ struct SweepArgs {
   double alpha, inv_c; // factored-form coefficients (inv_c may carry a rhs scale)
   const double *alpha_layer, *invc_layer;  // 2-D batches: per-layer coefficients
   double half_chi_mu;  // PFINAL
+  const double *gauge; // PFINAL: per-layer mean of psi removed before use (or null)
   Grid g;
   int32_t G;           // threads per line (x kernel: power of two <= 64)
   int32_t dim;
@@ -931,6 +946,7 @@ __device__ __forceinline__ void sweep_store(const SweepArgs<T> &a, int fld, int6
   } else if (MODE == SW_FINAL) {
     a.u[fld][idx] = (T)((double)a.u[fld][idx] + x);
   } else {  // SW_PFINAL
+    if (a.gauge) x -= a.gauge[a.dim == 2 ? idx / ((int64_t)a.g.n0 * a.g.n1) : 0];
     a.f[fld][idx] = (T)x;
     const T dn = a.divn[idx];
     const double dsum = (double)dn + (double)a.divp[idx];
@@ -1117,6 +1133,11 @@ __global__ void __launch_bounds__(256) k_sweep_x(SweepArgs<T> a) {
       for (int q = 0; q < M; q++) pre0[q] += r[q];
       vstore<T, M>(a.u[fld] + o, pre0);
     } else if constexpr (MODE == SW_PFINAL) {
+      if (a.gauge) {
+        const double gz = a.gauge[a.dim == 2 ? lay : 0];
+#pragma unroll
+        for (int q = 0; q < M; q++) r[q] -= gz;
+      }
       vstore<T, M>(a.f[fld] + o, r);
 #pragma unroll
       for (int q = 0; q < M; q++) pre2[q] = pre2[q] + r[q] - a.half_chi_mu * (pre0[q] + pre1[q]);
@@ -1394,6 +1415,12 @@ __global__ void __launch_bounds__(LB) k_sweep_sb(SweepArgs<T> a, int axis) {
     for (int q = 0; q < M; q++)
       if (q < cnt) cu.st(s + q, (T)((R)pu[q] + r[q]));
   } else if constexpr (MODE == SW_PFINAL) {
+    if (a.gauge) {
+      // 2-D batches sweep y only, so the remaining index is the layer
+      const R gz = (R)a.gauge[a.dim == 2 ? other : 0];
+#pragma unroll
+      for (int q = 0; q < M; q++) r[q] -= gz;
+    }
     const Col<T> cf(a.f[fld] + tb, rem * (int64_t)sizeof(T), tx, stride);
     const Col<T> cdp(a.divp + tb, rem * (int64_t)sizeof(T), tx, stride);
     const Col<double> cp(a.p + tb, rem * (int64_t)sizeof(double), tx, stride);
@@ -1405,6 +1432,45 @@ __global__ void __launch_bounds__(LB) k_sweep_sb(SweepArgs<T> a, int axis) {
         cdp.st(s + q, pdn[q]);
       }
   }
+}
+
+// Gauge of psi.  On the periodic box the mean of psi is zero in exact
+// arithmetic (the mean of D.u vanishes and every (1 - D_aa) maps a constant to
+// itself), but with FP32 work arrays the rounding of D.u^{n+1} has a mean that
+// the psi solve passes on multiplied by rho/dt, and p would accumulate it.
+// These two kernels measure the mean of psi before the last sweep (which
+// keeps the mean) per independent layer (one in 3-D), in FP64; the last
+// sweep removes it.
+template <typename T>
+__global__ void __launch_bounds__(256) k_layer_partial(const T *f, int64_t per_layer,
+                                                       double *partial) {
+  __shared__ double red[256];
+  const int64_t base = (int64_t)blockIdx.y * per_layer;
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < per_layer;
+       i += (int64_t)gridDim.x * 256)
+    s += (double)f[base + i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256) k_layer_mean(const double *partial, int nblk,
+                                                    int64_t per_layer, double *mean) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += 256) s += partial[(int64_t)blockIdx.x * nblk + i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) mean[blockIdx.x] = red[0] / (double)per_layer;
 }
 
 }  // namespace ibgm

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libibgm.so")
 
 IB_OK, IB_E_INVALID, IB_E_UNSUPPORTED, IB_E_DEVICE, IB_E_NONFINITE, IB_E_STATE = range(6)
 IB_F64, IB_F32 = 0, 1
-IB_PREC_FP64, IB_PREC_MIXED = 0, 1
+IB_PREC_FP64, IB_PREC_MIXED, IB_PREC_MIXED_STATE64 = 0, 1, 2
 IB_FLAG_NO_ADVECTION = 1
 IB_GRAPH_BRANCHES = 1
 
@@ -191,6 +191,11 @@ class Config:
 
     @property
     def grid_dtype(self):
+        """dtype of the work arrays (nl_prev, psi, div_prev, spread forces)."""
+        return torch.float64 if self.precision == IB_PREC_FP64 else torch.float32
+
+    @property
+    def velocity_dtype(self):
         return torch.float32 if self.precision == IB_PREC_MIXED else torch.float64
 
     @property
@@ -215,7 +220,7 @@ class Simulation:
         gd = cfg.grid_dtype
         shp = cfg.shape
         to = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt).reshape(shp).to(dev).contiguous()
-        self.u = [to(u0[c], gd) for c in range(d)]
+        self.u = [to(u0[c], cfg.velocity_dtype) for c in range(d)]
         self.nl_prev = [to(nl_prev[c], gd) if nl_prev is not None else torch.zeros(shp, dtype=gd, device=dev)
                         for c in range(d)]
         self.psi = to(psi, gd) if psi is not None else torch.zeros(shp, dtype=gd, device=dev)

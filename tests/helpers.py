@@ -33,3 +33,10 @@ def field_errors(gpu_state, orc, dim):
     errs["psi"] = rel_l2(gpu_state["psi"], orc.psi)
     errs["X"] = rel_l2(gpu_state["X"], orc.X)
     return errs
+
+
+def psi_vs_p(psi, psi_ref, p_ref):
+    """psi error measured against the scale of p (psi is p's per-step
+    increment, often orders of magnitude smaller)."""
+    scale = max(np.linalg.norm(psi_ref), np.linalg.norm(p_ref), 1e-30)
+    return float(np.linalg.norm(np.asarray(psi) - np.asarray(psi_ref)) / scale)
