@@ -396,11 +396,16 @@ static TileGrid tile_grid(const ib_grid_params *p) {
 // weights per component and axis, spread values); the spreading tile tables
 // (counts, flags, touched list, starts, block sums), the point sort (tile,
 // rank); the touched-list length; one status word.
-// psi gauge (mixed policies): per layer, GAUGE_BLOCKS partial sums and the mean
-constexpr int GAUGE_BLOCKS = 256;
+// psi gauge (mixed policies): per layer, gauge_blocks() partial sums and the mean
 static int64_t gauge_layers(const ib_grid_params *p) { return p->dim == 2 ? p->n[2] : 1; }
+static int64_t gauge_blocks(int64_t per_layer) {  // ~4096 values per block, 1..4096 blocks
+  const int64_t nb = (per_layer + 4095) / 4096;
+  return nb < 1 ? 1 : (nb > 4096 ? 4096 : nb);
+}
 static size_t gauge_bytes(const ib_grid_params *p) {
-  return align256(sizeof(double) * (size_t)gauge_layers(p) * (GAUGE_BLOCKS + 1));
+  const int64_t L = gauge_layers(p);
+  const int64_t per = (int64_t)p->n[0] * p->n[1] * (p->dim == 2 ? 1 : p->n[2]);
+  return align256(sizeof(double) * (size_t)(L * (gauge_blocks(per) + 1)));
 }
 
 static size_t workspace_bytes(const ib_grid_params *p, int64_t np) {
@@ -658,8 +663,7 @@ static void enqueue_step(ib_ctx *c) {
     // before the last sweep, which removes it
     const int64_t layers = DIM == 2 ? c->g.n2 : 1;
     const int64_t per = c->g.ncell / layers;
-    int64_t nb = (per + 256 * 16 - 1) / (256 * 16);
-    nb = nb < 1 ? 1 : (nb > GAUGE_BLOCKS ? GAUGE_BLOCKS : nb);
+    const int64_t nb = gauge_blocks(per);
     launch(c, KP_GAUGE, [&] {
       hipLaunchKernelGGL((k_layer_partial<T>), dim3((unsigned)nb, (unsigned)layers), dim3(256), 0,
                          c->stream, (const T *)c->buf.psi, per, c->gauge_part);
@@ -800,7 +804,7 @@ extern "C" ib_status ib_init(ib_ctx **out, const ib_grid_params *prm, const ib_b
   c->rank_of = (int *)w; w += pb;
   c->t_nlist = (int *)w; w += 256;
   c->flag = (int *)w; w += 256;
-  c->gauge = (double *)w;  // [layers] means, then [layers][GAUGE_BLOCKS] partials
+  c->gauge = (double *)w;  // [layers] means, then [layers][gauge_blocks] partials
   c->gauge_part = c->gauge + gauge_layers(prm);
   // upload the structure
   auto bail = [&](ib_status e) { ib_destroy(c); return e; };

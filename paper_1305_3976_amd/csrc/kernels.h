@@ -1445,11 +1445,28 @@ template <typename T>
 __global__ void __launch_bounds__(256) k_layer_partial(const T *f, int64_t per_layer,
                                                        double *partial) {
   __shared__ double red[256];
-  const int64_t base = (int64_t)blockIdx.y * per_layer;
+  const T *g = f + (int64_t)blockIdx.y * per_layer;
   double s = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < per_layer;
-       i += (int64_t)gridDim.x * 256)
-    s += (double)f[base + i];
+  // 16-byte loads where the layer is 16-byte aligned and a whole number of
+  // vectors long (the FP32 3-D and power-of-two 2-D cases), else scalars
+  using V = typename Vec16<T>::type;
+  constexpr int VN = Vec16<T>::n;
+  if (per_layer % VN == 0 && (reinterpret_cast<uintptr_t>(g) & 15) == 0) {
+    const V *gv = reinterpret_cast<const V *>(g);
+    const int64_t nv = per_layer / VN;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nv;
+         i += (int64_t)gridDim.x * 256) {
+      const V v = gv[i];
+      if constexpr (VN == 4)
+        s += ((double)v.x + (double)v.y) + ((double)v.z + (double)v.w);
+      else
+        s += (double)v.x + (double)v.y;
+    }
+  } else {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < per_layer;
+         i += (int64_t)gridDim.x * 256)
+      s += (double)g[i];
+  }
   red[threadIdx.x] = s;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
