@@ -780,6 +780,18 @@ __global__ void __launch_bounds__(ENT) k_explicit3(ExplicitArgs<T, 3, V> a) {
   double ps_below = a.p[pbm + cell] + (double)a.psi[pbm + cell];
   const int c = (ty + 1) * EW + (tx + 1);  // this column in a velocity plane
   const int pc = (ty + 1) * PW + (tx + 1);
+  // this cell's N^{n-1} and f, one plane ahead of their use
+  C nlp[3], fc[3];
+  auto cell_terms = [&](int kk, C *nl_out, C *f_out) {
+    const int64_t kp = (int64_t)kk * plane;
+    const bool forced = a.flag[tflag_row + tplane * (kk / TS)] != 0;
+#pragma unroll
+    for (int ci = 0; ci < 3; ci++) {
+      nl_out[ci] = a.first ? C(0) : (C)(a.nl[ci] + kp)[cell];
+      f_out[ci] = forced ? (C)(a.f[ci] + kp)[cell] : C(0);
+    }
+  };
+  cell_terms(k0, nlp, fc);
   __syncthreads();
   for (int kz = 0; kz < EZ && k0 + kz < n2; kz++) {
     const int k = k0 + kz;
@@ -802,15 +814,10 @@ __global__ void __launch_bounds__(ENT) k_explicit3(ExplicitArgs<T, 3, V> a) {
 #pragma unroll
       for (int q = 0; q < PPT; q++) pr[q] = pp[poff[q]] + (double)sp_[poff[q]];
     }
-    // this cell's N^{n-1} and f
+    // N^{n-1} and f of plane k+1 (this thread alone reads and writes them)
+    C nln[3], fcn[3];
+    if (more) cell_terms(k + 1, nln, fcn);
     const int64_t kp = (int64_t)k * plane;
-    const bool forced = a.flag[tflag_row + tplane * (k / TS)] != 0;
-    C nlp[3], fc[3];
-#pragma unroll
-    for (int ci = 0; ci < 3; ci++) {
-      nlp[ci] = a.first ? C(0) : (C)(a.nl[ci] + kp)[cell];
-      fc[ci] = forced ? (C)(a.f[ci] + kp)[cell] : C(0);
-    }
     // 2. compute plane k from LDS
     const double ps0 = PS[pc];
     const double psm[3] = {PS[pc - 1], PS[pc - PW], ps_below};
@@ -850,6 +857,10 @@ __global__ void __launch_bounds__(ENT) k_explicit3(ExplicitArgs<T, 3, V> a) {
     }
     ps_below = ps0;
     // 3. rotate: plane k+2 replaces plane k-1, plane k+1 of p* replaces k
+    if (more) {
+#pragma unroll
+      for (int ci = 0; ci < 3; ci++) nlp[ci] = nln[ci], fc[ci] = fcn[ci];
+    }
     __syncthreads();
     if (more) {
 #pragma unroll
