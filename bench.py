@@ -29,6 +29,12 @@ import numpy as np
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 
+# HBM bytes per launch of the dominant kernel from hardware counters (FETCH_SIZE
+# x 2.0 + WRITE_SIZE x 1.0, calibrated on a device copy), taken on the kernel
+# as it is built now; see profiles/hbm_counters_shell3d_256.md.  None when not
+# measured for the current build.
+TRAFFIC_BYTES = {"explicit": 1.0747e9}
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -189,6 +195,25 @@ def ens_classes_sizes(members):
     return [(n, None) for n in sorted({m.n for m in members})]
 
 
+def device_copy_rate(mib: int = 1024, reps: int = 5) -> float:
+    """Achievable HBM rate: a 1 GiB device-to-device copy (read + write bytes
+    per second), timed with HIP events."""
+    import torch
+    src = torch.ones(mib * 2 ** 20 // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    rate = 2 * src.numel() * 4 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return rate
+
+
 def oracle_sample(w, budget_s):
     import oracle
     P = oracle.make_params(w.dim, w.n, w.h, rho=w.rho, mu=w.mu, dt=w.dt, chi=w.chi)
@@ -240,6 +265,7 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    copy_gbs = device_copy_rate()
     from paper_1305_3976_amd import inputs
     w = inputs.config_shell_256(steps=args.steps, n=args.n, npts=args.points)
     ncell = w.n[0] * w.n[1] * w.n[2]
@@ -294,7 +320,12 @@ def main():
         "step_alg_bytes_GB": round(step_bytes(b, ncell, w.dim) / 1e9, 4),
         "step_GB_s": round(step_bytes(b, ncell, w.dim) / (ms_plain / args.steps * 1e-3) / 1e9, 1),
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None},
+                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                     "traffic": (round(TRAFFIC_BYTES[dom] / 1e9, 4)
+                                 if dom in TRAFFIC_BYTES and args.n == 256 else None),
+                     "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE x 2 + WRITE_SIZE)",
+                     "achievable_copy_GB_s": round(copy_gbs, 1),
+                     "frac_of_copy": round(ach / copy_gbs, 4)},
         "kernels": rows,
         "tuned_tiles": None if picks is None else {
             "%d/%s" % (a, "f64" if r else "f32"): list(v) for (a, r), v in picks.items()},
