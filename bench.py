@@ -138,7 +138,7 @@ def run_ensemble(steps, spl_choices=(2, 10), seed=4):
                             precision=ibgm.IB_PREC_MIXED)
     st = ens.stream
     t0 = time.perf_counter()
-    picks = ens.tune(reps=3)
+    picks = ens.tune(reps=10)
     tune_s = time.perf_counter() - t0
     ens.step(1)
     ens.sync()

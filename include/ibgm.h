@@ -204,8 +204,9 @@ ib_status ib_destroy(ib_ctx *ctx);
  * lane of x lines; row width and chunk length of strided lines) on this
  * context's grid, for each axis and recurrence precision, `reps` launches
  * each, on the context's own scratch fields (synchronises; call between
- * steps, not during capture), and use the fastest from then on.
- * ib_tune_read reports the choice (0 = library default). */
+ * steps, not during capture), and use the fastest for the plain sweeps
+ * from then on (the last momentum and psi sweeps keep the library's
+ * shapes).  ib_tune_read reports the choice (0 = library default). */
 ib_status ib_tune(ib_ctx *ctx, int32_t reps);
 ib_status ib_tune_read(const ib_ctx *ctx, int32_t axis, int32_t fp64_recurrence,
                        int32_t *x_chunk, int32_t *s_rows, int32_t *s_chunk);

@@ -345,7 +345,9 @@ static const SweepTune *tune_of(const ib_ctx *c, int axis, bool r64) {
 // strided id is id_x + 1).  R is the recurrence type of the strided kernel.
 template <typename T, int MODE, typename R = double>
 static void sweep(ib_ctx *c, int id_x, SweepArgs<T> a, int axis, int nf, hipStream_t st) {
-  const SweepTune *tu = tune_of(c, axis, sizeof(R) == 8);
+  // the tuner times plain sweeps; the sweeps with epilogue operands (FINAL,
+  // PFINAL) hold more registers per element and keep the library's shapes
+  const SweepTune *tu = MODE == SW_PLAIN ? tune_of(c, axis, sizeof(R) == 8) : nullptr;
   if (axis == 0)
     launch(c, id_x, [&] { dispatch_x<T, MODE>(a, nf, st, tu); });
   else
