@@ -535,11 +535,17 @@ __global__ void __launch_bounds__(256) k_spread_tiles(SpreadArgs<T, DIM> a) {
     // fall inside the tile are visited
     const int npts = c_pref[ncomb];
     const int64_t np = a.np;
-    for (int pi = threadIdx.x; pi < npts; pi += blockDim.x) {
+    // one thread per (candidate point, component) in 2-D, where tiles hold
+    // few candidates; per candidate point (all components) in 3-D, where the
+    // points' shared stencil rows keep one thread busy (measured faster)
+    constexpr int PER = DIM == 2 ? DIM : 1;
+    for (int it = threadIdx.x; it < npts * PER; it += blockDim.x) {
+      const int pi = it / PER;
       int slot = 0;
       while (c_pref[slot + 1] <= pi) slot++;
       const int64_t k = c_start[slot] + (pi - c_pref[slot]);
-      for (int c = 0; c < DIM; c++) {
+      const int c_lo = PER == 1 ? 0 : it - pi * PER, c_hi = PER == 1 ? DIM : c_lo + 1;
+      for (int c = c_lo; c < c_hi; c++) {
         int b[3], tlo[3], thi[3];
         bool any = true;
         for (int ax = 0; ax < 3; ax++) {
