@@ -571,25 +571,38 @@ __global__ void __launch_bounds__(256) k_spread_tiles(SpreadArgs<T, DIM> a) {
           any &= t0 <= t1;
         }
         if (!any) continue;
+        // the 4 weights per axis in registers (loaded together), then the
+        // in-tile part of the stencil, fully unrolled and predicated
         const C val = a.st.val[c * np + k];
-        for (int t2 = tlo[2]; t2 < thi[2]; t2++) {
-          int kk = b[2];
-          C rz = C(1);
-          if (DIM == 3) {
-            kk = b[2] + t2;
-            kk -= kk >= nn[2] ? nn[2] : 0;
-            rz = a.st.wt[((c * 3 + 2) * 4 + t2) * np + k];
-          }
-          for (int t1 = tlo[1]; t1 < thi[1]; t1++) {
-            int jj = b[1] + t1;
-            jj -= jj >= nn[1] ? nn[1] : 0;
-            const C rw = val * rz * a.st.wt[((c * 3 + 1) * 4 + t1) * np + k];
-            const int lrow = ((kk - lo[2]) * TS + (jj - lo[1])) * TS;
-            for (int t0 = tlo[0]; t0 < thi[0]; t0++) {
-              int ii = b[0] + t0;
-              ii -= ii >= nn[0] ? nn[0] : 0;
-              atomicAdd(&acc[c][lrow + ii - lo[0]], rw * a.st.wt[((c * 3 + 0) * 4 + t0) * np + k]);
-            }
+        C wx[4], wy[4], wz[4];
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+          wx[t] = a.st.wt[((c * 3 + 0) * 4 + t) * np + k];
+          wy[t] = a.st.wt[((c * 3 + 1) * 4 + t) * np + k];
+          wz[t] = DIM == 3 ? a.st.wt[((c * 3 + 2) * 4 + t) * np + k] : C(1);
+        }
+        // in-tile coordinate of the first in-tile stencil cell per axis (the
+        // in-tile cells of a stencil are contiguous: a wrap leaves one side
+        // of it outside the tile)
+        int l0[3];
+#pragma unroll
+        for (int ax = 0; ax < 3; ax++) {
+          int cell = b[ax] + tlo[ax];
+          cell -= (ax < DIM && cell >= nn[ax]) ? nn[ax] : 0;
+          l0[ax] = ax < DIM ? cell - lo[ax] - tlo[ax] : 0;
+        }
+#pragma unroll
+        for (int t2 = 0; t2 < (DIM == 3 ? 4 : 1); t2++) {
+          if (DIM == 3 && (t2 < tlo[2] || t2 >= thi[2])) continue;
+          const int lz = DIM == 3 ? l0[2] + t2 : 0;
+#pragma unroll
+          for (int t1 = 0; t1 < 4; t1++) {
+            if (t1 < tlo[1] || t1 >= thi[1]) continue;
+            const C rw = val * wz[t2] * wy[t1];
+            const int lrow = (lz * TS + l0[1] + t1) * TS + l0[0];
+#pragma unroll
+            for (int t0 = 0; t0 < 4; t0++)
+              if (t0 >= tlo[0] && t0 < thi[0]) atomicAdd(&acc[c][lrow + t0], rw * wx[t0]);
           }
         }
       }
