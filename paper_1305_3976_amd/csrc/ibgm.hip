@@ -523,8 +523,15 @@ static void launch_spread(ib_ctx *c, const double *X, const double *F, const dou
   a.g = c->g;
   a.tg = c->tg;
   const unsigned grid = (unsigned)std::min<int64_t>(c->tg.ntiles, 4096);
+  // dense structures (many points per tile of the grid) give each touched
+  // tile thousands of candidates: four times the threads per tile then hide
+  // more latency; sparse ones keep 256 so small tiles do not idle threads
+  const bool dense = np > 4 * c->tg.ntiles;
   launch(c, KP_SPREAD, [&] {
-    hipLaunchKernelGGL((k_spread_tiles<T, DIM, ADD>), dim3(grid), dim3(256), 0, c->stream, a);
+    if (dense)
+      hipLaunchKernelGGL((k_spread_tiles<T, DIM, ADD, 1024>), dim3(grid), dim3(1024), 0, c->stream, a);
+    else
+      hipLaunchKernelGGL((k_spread_tiles<T, DIM, ADD, 256>), dim3(grid), dim3(256), 0, c->stream, a);
   });
 }
 

@@ -479,8 +479,8 @@ struct SpreadArgs {
 // Workgroups loop over the touched tiles (a bounded loop: at most ntiles
 // entries).  For each tile: gather (point, stencil row) items of the source
 // tiles into LDS, then write the tile's cells (f = sum, or f += sum).
-template <typename T, int DIM, bool ADD>
-__global__ void __launch_bounds__(256) k_spread_tiles(SpreadArgs<T, DIM> a) {
+template <typename T, int DIM, bool ADD, int NT = 256>
+__global__ void __launch_bounds__(NT) k_spread_tiles(SpreadArgs<T, DIM> a) {
   using C = T;
   constexpr int CELLS = DIM == 3 ? TS * TS * TS : TS * TS;
   __shared__ C acc[DIM][CELLS];
