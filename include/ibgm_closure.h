@@ -45,6 +45,12 @@ extern "C" {
 
 #define IB_CONV_RELU 1    /* ReLU on the output */
 #define IB_CONV_OUT_F32 2 /* FP32 output (default BF16) */
+#define IB_CONV_NARROW 4  /* weights in the narrow packing (co <= 16, ci_pad 32) */
+
+#define IB_CONV_PACK_FORWARD 0
+#define IB_CONV_PACK_ADJOINT 1
+#define IB_CONV_PACK_NARROW 2
+#define IB_CONV_PACKED_NARROW_BYTES ((size_t)27 * 64 * 16)
 
 #define IB_CONV_OUT_CHANNELS 32 /* output channels of every convolution (padded) */
 #define IB_CONV_PACKED_BYTES(ci_pad) ((size_t)27 * ((ci_pad) / 16) * 64 * 16)
@@ -54,17 +60,21 @@ extern "C" {
   ((size_t)IB_CONV_WGRAD_BLOCKS * (27 * 32 * 32 + 32) * sizeof(float))
 
 /* Pack FP32 weights W[27][ci][co] (ci <= ci_pad, co <= 32, ci_pad 16 or 32)
- * into the operand layout of ib_conv3d_fwd (transpose = 0).  transpose = 1
- * packs the weights of the adjoint convolution instead: taps reversed
- * (t -> 26 - t) and channel roles swapped, W'[t][co][ci] = W[26 - t][ci][co],
- * for a convolution with input channels co (ci_pad must then be 32) and
- * output channels ci; ib_conv3d_bwd_data takes this packing. */
+ * into the operand layout of ib_conv3d_fwd (transpose = IB_CONV_PACK_FORWARD,
+ * IB_CONV_PACKED_BYTES(ci_pad) bytes).  IB_CONV_PACK_ADJOINT packs the
+ * weights of the adjoint convolution instead: taps reversed (t -> 26 - t) and
+ * channel roles swapped, W'[t][co][ci] = W[26 - t][ci][co], for a convolution
+ * with input channels co (ci_pad must then be 32) and output channels ci;
+ * ib_conv3d_bwd_data takes this packing.  IB_CONV_PACK_NARROW (co <= 16,
+ * ci_pad 32, IB_CONV_PACKED_NARROW_BYTES) is the operand layout of the
+ * 16-wide forward kernel, selected by IB_CONV_NARROW. */
 ib_status ib_conv3d_pack(const float *W, int32_t ci, int32_t co, int32_t ci_pad,
                          int32_t transpose, void *packed, void *hip_stream);
 
 /* y = act(conv(x, W) + bias) for a batch of `batch` bricks of in_dims (x, y,
  * z sizes) with ci_pad input channels; output dims follow from `mode`.
- * flags: IB_CONV_RELU, IB_CONV_OUT_F32.  Channels co < co_store of each
+ * flags: IB_CONV_RELU, IB_CONV_OUT_F32, IB_CONV_NARROW (weights in the
+ * narrow packing: ci_pad 32, co_store <= 16).  Channels co < co_store of each
  * output voxel are written at y + voxel * y_stride + co (y_stride >= co_store;
  * 32 for a hidden activation).  bias: FP32 [co_store] or NULL. */
 ib_status ib_conv3d_fwd(const uint16_t *x, int32_t batch, const int32_t in_dims[3],

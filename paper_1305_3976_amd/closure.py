@@ -28,7 +28,8 @@ from .ibgm import _vp, check, lib
 
 CIN, HID, COUT = 9, 32, 3
 PERIODIC, VALID, FULL = 0, 1, 2
-RELU, OUT_F32 = 1, 2
+RELU, OUT_F32, NARROW = 1, 2, 4
+PACK_FORWARD, PACK_ADJOINT, PACK_NARROW = 0, 1, 2
 WGRAD_WS = 256 * (27 * 32 * 32 + 32) * 4
 
 
@@ -85,8 +86,9 @@ class ConvNet:
         self.b = [self._view(self.theta, 2 * i + 1) for i in range(3)]
         self.gW = [self._view(self.grad, 2 * i) for i in range(3)]
         self.gb = [self._view(self.grad, 2 * i + 1) for i in range(3)]
-        self.P = [torch.empty(packed_bytes(cp), dtype=torch.uint8, device=dev)
-                  for _, _, cp in self.LAYERS]
+        # the output layer (3 channels) uses the 16-wide matrix-core packing
+        self.P = [torch.empty(packed_bytes(cp) if i < 2 else 27 * 64 * 16, dtype=torch.uint8,
+                              device=dev) for i, (_, _, cp) in enumerate(self.LAYERS)]
         self.T = [None] + [torch.empty(packed_bytes(32), dtype=torch.uint8, device=dev)
                            for _ in range(2)]
         self.wg_ws = torch.empty(WGRAD_WS, dtype=torch.uint8, device=dev)
@@ -104,9 +106,10 @@ class ConvNet:
     def pack(self, stream=None):
         st = _stream(stream)
         for i, (ci, co, cp) in enumerate(self.LAYERS):
-            check(lib.ib_conv3d_pack(_p(self.W[i]), ci, co, cp, 0, _p(self.P[i]), st))
+            check(lib.ib_conv3d_pack(_p(self.W[i]), ci, co, cp,
+                                     PACK_NARROW if i == 2 else PACK_FORWARD, _p(self.P[i]), st))
             if i > 0:
-                check(lib.ib_conv3d_pack(_p(self.W[i]), ci, co, 32, 1, _p(self.T[i]), st))
+                check(lib.ib_conv3d_pack(_p(self.W[i]), ci, co, 32, PACK_ADJOINT, _p(self.T[i]), st))
 
     def _buffers(self, batch, dims, mode):
         key = (batch, tuple(dims), mode)
@@ -139,7 +142,7 @@ class ConvNet:
         check(lib.ib_conv3d_fwd(_p(B["a1"]), batch, _i3(d1), 32, _p(self.P[1]), _p(self.b[1]),
                                 mode, RELU, _p(B["a2"]), 32, 32, st))
         check(lib.ib_conv3d_fwd(_p(B["a2"]), batch, _i3(d2), 32, _p(self.P[2]), _p(self.b[2]),
-                                mode, OUT_F32, _p(B["y"]), COUT, COUT, st))
+                                mode, OUT_F32 | NARROW, _p(B["y"]), COUT, COUT, st))
         return B["y"]
 
     def backward(self, x, target, batch, dims, mode, stream=None):

@@ -46,8 +46,8 @@ def conv_rates(net: cl.ConvNet, nc: int, reps: int = 10):
                                       cl._p(net.b[1]), cl.PERIODIC, cl.RELU, cl._p(B["a2"]), 32, 32,
                                       st), cl.HID, cl.HID),
         (lambda: cl.lib.ib_conv3d_fwd(cl._p(B["a2"]), 1, cl._i3(d), 32, cl._p(net.P[2]),
-                                      cl._p(net.b[2]), cl.PERIODIC, cl.OUT_F32, cl._p(B["y"]), 3, 3,
-                                      st), cl.HID, cl.COUT),
+                                      cl._p(net.b[2]), cl.PERIODIC, cl.OUT_F32 | cl.NARROW,
+                                      cl._p(B["y"]), 3, 3, st), cl.HID, cl.COUT),
     ]
     out = []
     for fn, ci, co in calls:

@@ -28,6 +28,7 @@ namespace {
 typedef __bf16 bf16;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int TX = 32, TY = 4, TZ = 4;               // output tile (voxels); TZ = waves
 constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2;  // its input halo
@@ -218,6 +219,116 @@ __global__ __launch_bounds__(NT) void k_conv(ConvArgs a) {
   }
 }
 
+// Narrow output (co <= 16, ci = 32): v_mfma_f32_16x16x32_bf16 computes 16
+// voxels x 16 output channels with all 32 input channels in one instruction
+// (lane l supplies A[row l%16][k 8(l/16)..+7] and B[k 8(l/16)..+7][col l%16];
+// accumulator j of lane l is D[4(l/16) + j][l%16]), half the work of the
+// 32-wide instruction for a layer with 3 real outputs.  Same tiles, halo and
+// row reuse as k_conv; each output row is two 16-voxel halves.
+__global__ __launch_bounds__(NT) void k_conv_n16(ConvArgs a) {
+  constexpr int CI = 32;
+  constexpr int VS = CI * 2 + 16;
+  constexpr int CH = CI / 8;
+  constexpr int NCHUNK = HX * HY * HZ * CH;
+  constexpr int PER = (NCHUNK + NT - 1) / NT;
+  __shared__ __align__(16) unsigned char sw[27 * 64 * 16];
+  __shared__ __align__(16) unsigned char sh[HX * HY * HZ * VS];
+  for (int c = threadIdx.x; c < 27 * 64; c += NT)
+    reinterpret_cast<uint4 *>(sw)[c] = reinterpret_cast<const uint4 *>(a.wp)[c];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 15, grp = lane >> 4;
+  const float bias = (a.bias && col < a.co_store) ? a.bias[col] : 0.f;
+  uint4 pre[PER];
+  for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+    const TileXYZ t = tile_xyz(tile, a.nt0, a.nt1, a.nt2);
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+      const int c = threadIdx.x + q * NT;
+      pre[q] = make_uint4(0, 0, 0, 0);
+      if (c < NCHUNK) {
+        const int v = c / CH, part = c - v * CH;
+        const int hx = v % HX, hy = (v / HX) % HY, hz = v / (HX * HY);
+        int gx = t.ox0 + hx + a.off, gy = t.oy0 + hy + a.off, gz = t.oz0 + hz + a.off;
+        bool in = true;
+        if (a.wrap == 1) {
+          gx = wrap1(gx, a.D0), gy = wrap1(gy, a.D1), gz = wrap1(gz, a.D2);
+        } else if (a.wrap) {
+          gx = wrapi(gx, a.D0), gy = wrapi(gy, a.D1), gz = wrapi(gz, a.D2);
+        } else {
+          in = gx >= 0 && gx < a.D0 && gy >= 0 && gy < a.D1 && gz >= 0 && gz < a.D2;
+        }
+        if (in) {
+          const size_t vox = (((size_t)t.b * a.D2 + gz) * a.D1 + gy) * a.D0 + gx;
+          pre[q] = *reinterpret_cast<const uint4 *>(a.x + vox * CI + part * 8);
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+      const int c = threadIdx.x + q * NT;
+      if (c < NCHUNK) {
+        const int v = c / CH, part = c - v * CH;
+        *reinterpret_cast<uint4 *>(sh + v * VS + part * 16) = pre[q];
+      }
+    }
+    __syncthreads();
+    f32x4 acc[TY][2];
+#pragma unroll
+    for (int m = 0; m < TY; m++)
+#pragma unroll
+      for (int h = 0; h < 2; h++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) acc[m][h][j] = 0.f;
+#pragma unroll 1
+    for (int tz = 0; tz < 3; tz++) {
+#pragma unroll 1
+      for (int tx = 0; tx < 3; tx++) {
+        bf16x8 bw[3];
+#pragma unroll
+        for (int ty = 0; ty < 3; ty++)
+          bw[ty] = *reinterpret_cast<const bf16x8 *>(sw + ((9 * tz + 3 * ty + tx) * 64 + lane) * 16);
+        const unsigned char *base = sh + ((wave + tz) * HY * HX + col + tx) * VS + grp * 16;
+#pragma unroll
+        for (int hy = 0; hy < HY; hy++) {
+#pragma unroll
+          for (int h = 0; h < 2; h++) {
+            const bf16x8 av = *reinterpret_cast<const bf16x8 *>(base + (hy * HX + 16 * h) * VS);
+#pragma unroll
+            for (int ty = 0; ty < 3; ty++) {
+              const int my = hy - ty;
+              if (my >= 0 && my < TY)
+                acc[my][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bw[ty], acc[my][h], 0, 0, 0);
+            }
+          }
+        }
+      }
+    }
+    const int oz = t.oz0 + wave;
+#pragma unroll
+    for (int my = 0; my < TY; my++) {
+      const int oy = t.oy0 + my;
+      if (oy >= a.E1 || oz >= a.E2 || col >= a.co_store) continue;
+      const size_t rowv = (((size_t)t.b * a.E2 + oz) * a.E1 + oy) * a.E0;
+#pragma unroll
+      for (int h = 0; h < 2; h++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          const int ox = t.ox0 + 16 * h + 4 * grp + j;
+          if (ox >= a.E0) continue;
+          const size_t vox = rowv + ox;
+          float v = acc[my][h][j] + bias;
+          if (a.relu) v = fmaxf(v, 0.f);
+          if (a.mask && !((float)a.mask[vox * CO + col] > 0.f)) v = 0.f;
+          if (a.out_f32)
+            reinterpret_cast<float *>(a.y)[vox * a.ystride + col] = v;
+          else
+            reinterpret_cast<bf16 *>(a.y)[vox * a.ystride + col] = (bf16)v;
+        }
+    }
+  }
+}
+
 // ------------------------------------------------------ weight gradient --
 
 struct WgradArgs {
@@ -338,10 +449,18 @@ __global__ void k_wgrad_reduce(const float *part, int nblk, int ci, int co, floa
 // ------------------------------------------------------ small kernels --
 
 // packed[t][ks][l][e] = W[t][ci = 16 ks + 8 (l/32) + e][co = l % 32] (0 outside);
-// transposed: W'[t][c'][c''] = W[26 - t][c''][c'] with c' the input channel.
+// transposed: W'[t][c'][c''] = W[26 - t][c''][c'] with c' the input channel;
+// narrow: packed[t][l][e] = W[t][ci = 8 (l/16) + e][co = l % 16].
 __global__ void k_pack(const float *W, int ci, int co, int ci_pad, int transpose, bf16 *out) {
   const int KS = ci_pad / 16;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (transpose == IB_CONV_PACK_NARROW) {
+    if (i >= 27 * 64 * 8) return;
+    const int e = i & 7, l = (i >> 3) & 63, t = i >> 9;
+    const int kin = 8 * (l >> 4) + e, kout = l & 15;
+    out[i] = (bf16)((kin < ci && kout < co) ? W[((size_t)t * ci + kin) * co + kout] : 0.f);
+    return;
+  }
   if (i >= 27 * KS * 64 * 8) return;
   const int e = i & 7, l = (i >> 3) & 63, ks = (i >> 9) % KS, t = (i >> 9) / KS;
   const int kin = 16 * ks + 8 * (l >> 5) + e, kout = l & 31;
@@ -520,7 +639,7 @@ ib_status check_dims(const int32_t *d, int32_t batch, int grow, int64_t *nvox_in
 ib_status launch_conv(const bf16 *x, int32_t batch, const int32_t *in_dims, int32_t ci_pad,
                       const void *packed, const float *bias, int32_t mode, int relu,
                       int out_f32, const bf16 *mask, void *y, int32_t co_store,
-                      int32_t y_stride, hipStream_t st) {
+                      int32_t y_stride, hipStream_t st, bool narrow = false) {
   int off, wrap, grow;
   ib_status s = mode_off(mode, &off, &wrap, &grow);
   if (s != IB_OK) return s;
@@ -545,7 +664,8 @@ ib_status launch_conv(const bf16 *x, int32_t batch, const int32_t *in_dims, int3
   const int grid = (int)(nt < WG_CONV ? nt : WG_CONV);
   if (wrap && (a.D0 < HX || a.D1 < HY || a.D2 < HZ)) a.wrap = 2;
   a.idx32 = (vi * ci_pad < ((int64_t)1 << 31)) ? 1 : 0;
-  if (ci_pad == 16) k_conv<16><<<grid, NT, 0, st>>>(a);
+  if (narrow) k_conv_n16<<<grid, NT, 0, st>>>(a);
+  else if (ci_pad == 16) k_conv<16><<<grid, NT, 0, st>>>(a);
   else k_conv<32><<<grid, NT, 0, st>>>(a);
   HIP_CHECK_LAUNCH("conv3d");
   return IB_OK;
@@ -559,9 +679,11 @@ extern "C" ib_status ib_conv3d_pack(const float *W, int32_t ci, int32_t co, int3
   if (ci_pad != 16 && ci_pad != 32) return fail(IB_E_INVALID, "ci_pad must be 16 or 32");
   if (ci < 1 || co < 1 || co > 32 || ci > 32)
     return fail(IB_E_INVALID, "channels out of range (ci %d, co %d)", ci, co);
-  if (!transpose && ci > ci_pad) return fail(IB_E_INVALID, "ci > ci_pad");
-  if (transpose && ci_pad != 32) return fail(IB_E_INVALID, "the adjoint packing needs ci_pad 32");
-  const int n = 27 * (ci_pad / 16) * 64 * 8;
+  if (transpose < 0 || transpose > IB_CONV_PACK_NARROW) return fail(IB_E_INVALID, "unknown packing %d", transpose);
+  if (transpose != 1 && ci > ci_pad) return fail(IB_E_INVALID, "ci > ci_pad");
+  if (transpose && ci_pad != 32) return fail(IB_E_INVALID, "the adjoint and narrow packings need ci_pad 32");
+  if (transpose == IB_CONV_PACK_NARROW && co > 16) return fail(IB_E_INVALID, "the narrow packing needs co <= 16");
+  const int n = transpose == IB_CONV_PACK_NARROW ? 27 * 64 * 8 : 27 * (ci_pad / 16) * 64 * 8;
   k_pack<<<(n + 255) / 256, 256, 0, (hipStream_t)hip_stream>>>(W, ci, co, ci_pad, transpose,
                                                                 reinterpret_cast<bf16 *>(packed));
   HIP_CHECK_LAUNCH("pack");
@@ -572,10 +694,14 @@ extern "C" ib_status ib_conv3d_fwd(const uint16_t *x, int32_t batch, const int32
                                    int32_t ci_pad, const void *packed, const float *bias,
                                    int32_t mode, int32_t flags, void *y, int32_t co_store,
                                    int32_t y_stride, void *hip_stream) {
-  if (flags & ~(IB_CONV_RELU | IB_CONV_OUT_F32)) return fail(IB_E_INVALID, "unknown flags");
+  if (flags & ~(IB_CONV_RELU | IB_CONV_OUT_F32 | IB_CONV_NARROW))
+    return fail(IB_E_INVALID, "unknown flags");
+  if ((flags & IB_CONV_NARROW) && (ci_pad != 32 || co_store > 16))
+    return fail(IB_E_INVALID, "IB_CONV_NARROW needs ci_pad 32 and co_store <= 16");
   return launch_conv(reinterpret_cast<const bf16 *>(x), batch, in_dims, ci_pad, packed, bias,
                      mode, (flags & IB_CONV_RELU) != 0, (flags & IB_CONV_OUT_F32) != 0, nullptr,
-                     y, co_store, y_stride, (hipStream_t)hip_stream);
+                     y, co_store, y_stride, (hipStream_t)hip_stream,
+                     (flags & IB_CONV_NARROW) != 0);
 }
 
 extern "C" ib_status ib_conv3d_bwd_data(const uint16_t *gy, int32_t batch,

@@ -40,13 +40,16 @@ def pack(W, ci, co, ci_pad, transpose):
     return P, Wd
 
 
-@pytest.mark.parametrize("mode,ci,ci_pad,co,dims,batch,out_f32,relu", [
-    ("periodic", 6, 16, 32, (40, 12, 6), 2, False, True),     # ragged x tile, wrap
-    ("periodic", 32, 32, 32, (32, 8, 4), 1, True, False),
-    ("valid", 32, 32, 32, (38, 9, 7), 2, False, True),         # E = (36, 7, 5): partial tiles
-    ("valid", 32, 32, 3, (36, 6, 5), 3, True, False),          # the output layer shape
+@pytest.mark.parametrize("mode,ci,ci_pad,co,dims,batch,out_f32,relu,narrow", [
+    ("periodic", 6, 16, 32, (40, 12, 6), 2, False, True, False),     # ragged x tile, wrap
+    ("periodic", 32, 32, 32, (32, 8, 4), 1, True, False, False),
+    ("valid", 32, 32, 32, (38, 9, 7), 2, False, True, False),         # E = (36, 7, 5): partial tiles
+    ("valid", 32, 32, 3, (36, 6, 5), 3, True, False, False),          # the output layer shape
+    ("valid", 32, 32, 3, (38, 9, 7), 2, True, False, True),           # ... on the 16-wide kernel
+    ("periodic", 32, 32, 3, (40, 7, 6), 2, True, True, True),
+    ("periodic", 32, 32, 16, (33, 5, 4), 1, False, True, True),
 ])
-def test_conv_forward(mode, ci, ci_pad, co, dims, batch, out_f32, relu):
+def test_conv_forward(mode, ci, ci_pad, co, dims, batch, out_f32, relu, narrow):
     rng = np.random.default_rng(10 + ci + co)
     d0, d1, d2 = dims
     x, xh = bf16_pair((batch, d2, d1, d0, ci_pad), rng)
@@ -54,16 +57,16 @@ def test_conv_forward(mode, ci, ci_pad, co, dims, batch, out_f32, relu):
     x = torch.as_tensor(xh.astype(np.float32)).to(torch.bfloat16).to(DEV)
     W = rng.standard_normal((27, ci, co)) * np.sqrt(2.0 / (27 * ci))
     b = rng.standard_normal(co) * 0.1
-    P, _ = pack(W, ci, co, ci_pad, 0)
+    P, _ = pack(W, ci, co, ci_pad, cl.PACK_NARROW if narrow else cl.PACK_FORWARD)
     bd = torch.as_tensor(b.astype(np.float32)).to(DEV)
     ref = oc.conv3d(xh[..., :ci], bf16_round(W), b.astype(np.float32).astype(np.float64), mode)
     if relu:
         ref = oc.relu(ref)
     E = ref.shape[1:4]
     nv = batch * E[0] * E[1] * E[2]
-    stride = co if out_f32 else 32
+    stride = co if out_f32 else (16 if narrow else 32)
     y = torch.full((nv * stride,), 7.0, dtype=torch.float32 if out_f32 else torch.bfloat16, device=DEV)
-    flags = (cl.OUT_F32 if out_f32 else 0) | (cl.RELU if relu else 0)
+    flags = (cl.OUT_F32 if out_f32 else 0) | (cl.RELU if relu else 0) | (cl.NARROW if narrow else 0)
     ibgm.check(ibgm.lib.ib_conv3d_fwd(cl._p(x), batch, cl._i3(dims), ci_pad, cl._p(P), cl._p(bd),
                                       MODES[mode], flags, cl._p(y), co, stride, cl._stream()))
     got = y.double().cpu().numpy().reshape(ref.shape[:4] + (stride,))
