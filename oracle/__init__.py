@@ -26,7 +26,10 @@ _ip = ctypes.POINTER(ctypes.c_int32)
 
 def build(force: bool = False) -> str:
     """Compile ibo.c into libibo.so with gcc (OpenMP over independent loops)."""
-    if force or not os.path.exists(_LIB):
+    stale = (not os.path.exists(_LIB)
+             or os.path.getmtime(_LIB) < max(os.path.getmtime(_SRC),
+                                             os.path.getmtime(os.path.join(_HERE, "ibo.h"))))
+    if force or stale:
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(
             ["gcc", "-O2", "-fPIC", "-shared", "-fopenmp", "-Wall", "-o", tmp,
@@ -69,7 +72,7 @@ def lib():
                                  ctypes.c_int64, _dp]
         L.ibo_spread.argtypes = [ctypes.POINTER(Params), _dp, _dp, _dp,
                                  ctypes.c_int64, _dp * 3]
-        L.ibo_link_force.argtypes = [ctypes.c_int32, ctypes.c_int64, _dp,
+        L.ibo_link_force.argtypes = [ctypes.c_int32, ctypes.c_int64, _dp, _dp,
                                      ctypes.c_int64, _ip, _ip, _dp, _dp, _dp]
         L.ibo_advection.argtypes = [ctypes.POINTER(Params), _dp * 3, _dp * 3]
         L.ibo_laplacian.argtypes = [ctypes.POINTER(Params), _dp, _dp]
@@ -166,16 +169,19 @@ def spread(P: Params, X, F, w):
     return f
 
 
-def link_force(X, links):
+def link_force(X, links, period=None):
+    """Step 2a; period = box lengths per axis for nearest-image link vectors
+    (None: no images)."""
     X = np.ascontiguousarray(X, dtype=np.float64)
     a, b, k, l0 = links
     a = np.ascontiguousarray(a, dtype=np.int32)
     b = np.ascontiguousarray(b, dtype=np.int32)
     k = np.ascontiguousarray(k, dtype=np.float64)
     l0 = np.ascontiguousarray(l0, dtype=np.float64)
+    per = None if period is None else np.ascontiguousarray(period, dtype=np.float64)
     F = np.zeros_like(X)
-    lib().ibo_link_force(X.shape[0], X.shape[1], _p(X), len(a), _pi(a), _pi(b),
-                         _p(k), _p(l0), _p(F))
+    lib().ibo_link_force(X.shape[0], X.shape[1], _p(X), None if per is None else _p(per),
+                         len(a), _pi(a), _pi(b), _p(k), _p(l0), _p(F))
     return F
 
 

@@ -263,16 +263,21 @@ void ibo_spread(const ibo_params *P, const double *X, const double *F,
  * and Lagrangian Grids": each connection pulls its two points together with
  * kappa (X_b - X_a)(1 - l0/|X_b - X_a|).  For a closed fiber with
  * kappa = sigma/h_s^2 and l0 = L h_s this is sigma D_s^-(D_s^+ X (1 - L/|D_s^+
- * X|)) of eq:forceDensityDefinition. */
-void ibo_link_force(int32_t dim, int64_t np, const double *X, int64_t nlinks,
-                    const int32_t *la, const int32_t *lb, const double *lk,
-                    const double *ll0, double *F) {
+ * X|)) of eq:forceDensityDefinition.  The box is periodic, and a fiber may
+ * close through its periodic copy (the axial fibers of Sec. "Cylindrical
+ * Shell in 3D"): X_b - X_a is taken as the nearest periodic image, i.e. an
+ * integer number of box lengths period[c] is removed from each component
+ * (period == NULL: no images). */
+void ibo_link_force(int32_t dim, int64_t np, const double *X, const double *period,
+                    int64_t nlinks, const int32_t *la, const int32_t *lb,
+                    const double *lk, const double *ll0, double *F) {
   memset(F, 0, sizeof(double) * (size_t)(dim * np));
   for (int64_t e = 0; e < nlinks; e++) {
     int64_t a = la[e], b = lb[e];
     double dx[3] = {0, 0, 0}, len2 = 0.0;
     for (int32_t c = 0; c < dim; c++) {
       dx[c] = X[c * np + b] - X[c * np + a];
+      if (period) dx[c] -= period[c] * round(dx[c] / period[c]);
       len2 += dx[c] * dx[c];
     }
     double t = lk[e];
@@ -458,7 +463,8 @@ int ibo_step(ibo_sim *s) {
   for (int64_t i = 0; i < d * np; i++) Xh[i] = 0.5 * (Xn1[i] + s->X[i]);
 
   /* Step 2a: force density at X^{n+1/2}. */
-  ibo_link_force(d, np, Xh, s->nlinks, s->link_a, s->link_b, s->link_k,
+  const double box[3] = {P->n[0] * P->h, P->n[1] * P->h, P->n[2] * P->h};
+  ibo_link_force(d, np, Xh, box, s->nlinks, s->link_a, s->link_b, s->link_k,
                  s->link_l0, F);
   /* Step 2b: spread it to the grid. */
   ibo_spread(P, Xh, F, s->w, np, f);

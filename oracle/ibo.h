@@ -77,10 +77,12 @@ void ibo_spread(const ibo_params *prm, const double *X, const double *F,
                 const double *w, int64_t np, double *const f[3]);
 
 /* Step 2a in force-connection form: for each link (a, b, kappa, l0),
- * F_a += kappa (X_b - X_a)(1 - l0/|X_b - X_a|) and F_b gets the opposite. */
-void ibo_link_force(int32_t dim, int64_t np, const double *X, int64_t nlinks,
-                    const int32_t *la, const int32_t *lb, const double *lk,
-                    const double *ll0, double *F);
+ * F_a += kappa (X_b - X_a)(1 - l0/|X_b - X_a|) and F_b gets the opposite,
+ * X_b - X_a being the nearest periodic image in a box of lengths period[]
+ * (NULL: no images). */
+void ibo_link_force(int32_t dim, int64_t np, const double *X, const double *period,
+                    int64_t nlinks, const int32_t *la, const int32_t *lb,
+                    const double *lk, const double *ll0, double *F);
 
 /* Skew-symmetric advection N(u) = 1/2 u.grad u + 1/2 div(uu) on the MAC
  * grid with the second-order staggered stencils of Morinishi et al. */

@@ -146,6 +146,43 @@ def test_link_force_equals_fiber_formula():
     assert np.abs(F - Fref).max() < 1e-11 * np.abs(Fref).max()
 
 
+def test_link_force_periodic_image():
+    """A fiber that closes through the periodic box (Sec. "Cylindrical Shell
+    in 3D"): with nearest-image link vectors the force does not depend on
+    which periodic copy of each point is stored.  Reference: the same fiber
+    unwrapped (all links short) with no images."""
+    rng = np.random.default_rng(11)
+    box = np.array([1.25, 0.8])
+    S = inputs.ellipse(96, 0.2, 0.15, 1.3, L=0.5, center=(0.05, 0.75))
+    X = S.X + 1e-3 * rng.standard_normal(S.X.shape)
+    Fref = oracle.link_force(X, S.links)
+    Xw = np.mod(X, box[:, None])                       # wrapped into the box
+    Xw[:, :7] += box[:, None] * rng.integers(-2, 3, size=(2, 7))  # other copies
+    F = oracle.link_force(Xw, S.links, period=box)
+    assert np.abs(F - Fref).max() < 1e-9 * np.abs(Fref).max()
+    # without images the wrapped fiber is torn apart
+    assert np.abs(oracle.link_force(Xw, S.links) - Fref).max() > np.abs(Fref).max()
+
+
+def test_cylinder_initial_force_is_the_ring_force():
+    """At t = 0 every axial fiber of the cylinder sits at its rest length
+    (|X_r| = L = 1, through the periodic seam), so the force is the zero-
+    rest-length ring force of each elliptical cross-section, in y-z, with no
+    x component (Sec. "Cylindrical Shell in 3D")."""
+    N = 16
+    S = inputs.cylinder_shell(N)
+    ns, nr = 19 * N // 4, 3 * N
+    F = oracle.link_force(S.X, S.links, period=(1.0, 1.0, 1.0))
+    ring = inputs.ellipse(ns, 5 / 28, 7 / 20, 1.0)
+    Fr = oracle.link_force(ring.X, ring.links)
+    scale = np.abs(Fr).max()
+    Fc = F.reshape(3, nr, ns)
+    assert np.abs(Fc[0]).max() < 1e-9 * scale
+    assert np.abs(Fc[1:] - Fr[:, None, :]).max() < 1e-9 * scale
+    # the seam links are what the images fix
+    assert np.abs(oracle.link_force(S.X, S.links)[0]).max() > scale
+
+
 def test_link_force_network_conserves_momentum():
     S = inputs.ellipsoid_shell(200)
     F = oracle.link_force(S.X, S.links)
