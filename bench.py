@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--closure", choices=("full", "small", "off"), default="full",
                     help="learned closure: 128^3 coarse vs 256^3 fine (full), 32^3 vs 64^3 "
                          "(small) or skip")
+    ap.add_argument("--cylinder", type=int, nargs="*", default=[256, 128], metavar="N",
+                    help="grid sizes of the 3-D cylinder row (100 steps each, mixed and "
+                         "FP64); none to skip")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB (3 times), the reference "
                          "for scaling hardware byte counters")
@@ -122,6 +125,44 @@ def run_gpu(w, precision, steps, warmup, tune=False):
     del sim
     torch.cuda.empty_cache()
     return ms, ms_plain, wall, kern, picks
+
+
+# Wall time in seconds of the paper's first 100 steps of the cylinder on its
+# CPU cluster (Table CylinderScaling): one core and its fastest partition.
+PAPER_CYLINDER_100 = {128: {"P=1": 401.0, "P=128 (32,2,2)": 7.76},
+                      256: {"P=1": 2600.0, "P=128 (32,2,2)": 30.2}}
+
+
+def run_cylinder(sizes, steps=100, warmup=5, fp64=True):
+    """The 3-D cylindrical shell of Sec. "Cylindrical Shell in 3D" (N_s = 19N/4
+    by N_r = 3N points, axial rest length L = 1, dt = 0.04/N), timed over the
+    paper's 100 steps; the paper's wall times are context (CPU cluster)."""
+    from paper_1305_3976_amd import inputs
+    out = []
+    for n in sizes:
+        w = inputs.config_cylinder(n, steps=steps)
+        for prec, tag in ((1, "mixed"), (0, "fp64")):
+            if prec == 0 and not fp64:
+                continue
+            ms, ms_plain, _, kern, _ = run_gpu(w, prec, steps, warmup)
+            top = sorted(kern.items(), key=lambda kv: -kv[1][0])[:6]
+            paper = PAPER_CYLINDER_100.get(n, {})
+            row = {"n": n, "points": w.structure.np, "links": w.structure.nlinks,
+                   "precision": tag, "steps": steps,
+                   "ms_per_step": round(ms_plain / steps, 4),
+                   "wall_s_100_steps": round(ms_plain * 1e-3 * 100 / steps, 4),
+                   "gcell_updates_per_s": round(n ** 3 * steps / (ms_plain * 1e-3) / 1e9, 3),
+                   "top_kernels_avg_us": {k: round(t / c * 1e3, 2) for k, (t, c) in top},
+                   "paper_wall_s_100_steps": paper}
+            for key, t in paper.items():
+                row["ratio_vs_paper_" + key.split()[0]] = round(t / (ms_plain * 1e-3 * 100 / steps), 1)
+            out.append(row)
+            print("# cylinder N=%d %s: %.3f ms/step" % (n, tag, ms_plain / steps),
+                  file=sys.stderr, flush=True)
+    return {"workload": "cylinder3d: N^3, mu=0.01, dt=0.04/N, sigma_s=sigma_r=1, L=1, "
+                        "r1=5/28, r2=7/20",
+            "note": "paper times are FP64 (assumed) on a CPU cluster: context, not a target",
+            "runs": out}
 
 
 def run_ensemble(steps, spl_choices=(2, 10), seed=4):
@@ -339,6 +380,8 @@ def main():
                         "step_GB_s": round(step_bytes(8, ncell, w.dim) / (ms64_plain / args.steps * 1e-3) / 1e9, 1),
                         "kernels_avg_us": {k: round(t / c * 1e3, 2) for k, (t, c) in kern64.items()}}
         line["mixed_vs_fp64_speedup"] = round(steps_s / s64, 3)
+    if args.cylinder:
+        line["cylinder"] = run_cylinder(args.cylinder, fp64=not args.no_fp64)
     if args.ensemble_steps:
         line["ensemble"] = run_ensemble(args.ensemble_steps)
         print("# ensemble: %.1f member-steps/s, %.3f Gcell/s (%s)" % (

@@ -118,7 +118,10 @@ typedef struct {
  * Step 2a: link e pulls a[e], b[e] together with
  * kappa[e] (X_b - X_a)(1 - l0[e]/|X_b - X_a|); a fiber of the paper with
  * stiffness sigma, rest strain L and spacing h_s has kappa = sigma/h_s^2,
- * l0 = L h_s and spreading weight w = h_s). */
+ * l0 = L h_s and spreading weight w = h_s).  X_b - X_a is the nearest
+ * periodic image in the box [0, n[c] h): a fiber may close through its
+ * periodic copy, as the axial fibers of the cylinder of Sec. "Cylindrical
+ * Shell in 3D" do; a link must be shorter than half the box. */
 typedef struct {
   int64_t n_links;
   const int32_t *a, *b;      /* host, point indices in [0, n_points) */

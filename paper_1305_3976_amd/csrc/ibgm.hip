@@ -469,6 +469,7 @@ static void launch_force(ib_ctx *c, const double *Xh, double *F, bool commit) {
   a.Xn1 = commit ? c->Xn1 : nullptr;
   a.X = c->buf.X;
   a.np = c->np;
+  for (int i = 0; i < DIM; i++) a.box[i] = c->prm.n[i] * c->prm.h;
   launch(c, KP_FORCE, [&] {
     hipLaunchKernelGGL((k_force<DIM>), dim3((unsigned)((c->np + 255) / 256)), dim3(256), 0,
                        c->stream, a);

@@ -232,7 +232,10 @@ __global__ void __launch_bounds__(256) k_interp(InterpArgs<T, DIM> a) {
 
 // One thread per point: gather the link forces at X^{n+1/2} over the point's
 // incident links (CSR by point), F_k = sum kappa (X_l - X_k)(1 - l0/|X_l - X_k|).
-// When Xn1 != null also commit X <- X^{n+1} for the point.
+// X_l - X_k is the nearest periodic image (the box is periodic and a fiber
+// may close through its periodic copy, as the axial fibers of the cylinder
+// of Sec. "Cylindrical Shell in 3D" do).  When Xn1 != null also commit
+// X <- X^{n+1} for the point.
 template <int DIM>
 struct ForceArgs {
   const int32_t *ptr, *nbr;
@@ -242,6 +245,7 @@ struct ForceArgs {
   const double *Xn1;
   double *X;
   int64_t np;
+  double box[DIM];  // periodic box length per axis
 };
 
 template <int DIM>
@@ -259,6 +263,7 @@ __global__ void __launch_bounds__(256) k_force(ForceArgs<DIM> a) {
     double d[DIM], len2 = 0.0;
     for (int c = 0; c < DIM; c++) {
       d[c] = a.Xh[c * a.np + l] - xk[c];
+      d[c] -= a.box[c] * round(d[c] / a.box[c]);
       len2 += d[c] * d[c];
     }
     double t = a.kap[e];

@@ -290,6 +290,16 @@ def config_shell_256(steps: int = 200, n: int = 256, npts: int = 65536) -> Workl
 
 # ------------------------------------------------------- batched ensemble --
 
+def config_cylinder(n: int = 256, steps: int = 100) -> Workload:
+    """3-D cylindrical shell of Sec. "Cylindrical Shell in 3D": N^3 periodic
+    unit cube, rho = 1, mu = 0.01, dt = 0.04/N, sigma_s = sigma_r = 1, L = 1,
+    r1 = 5/28, r2 = 7/20, N_s = 19N/4 circumferential by N_r = 3N axial
+    fibers (933,888 points at N = 256), fluid at rest; the paper times the
+    first 100 steps."""
+    return Workload("cylinder3d_%d" % n, 3, (n, n, n), 1.0, 0.01, 0.04 / n, steps,
+                    cylinder_shell(n), zero_velocity(3, (n, n, n)))
+
+
 def stiffness_time_step(sigma: float) -> float:
     """Time step for a thin ellipse of stiffness sigma, from the step sizes the
     paper uses for its thin-ellipse runs at N = 512 (Sec. "Thin Ellipse":

@@ -45,7 +45,8 @@ def test_interp_spread_force_match_oracle(dim, prec):
     assert np.abs(U - Uo).max() <= tol * np.abs(Uo).max()
 
     F = sim.force(Xd).cpu().numpy()
-    Fo = oracle.link_force(X, S.links)
+    box = [sim.cfg.n[c] * sim.cfg.h for c in range(dim)]
+    Fo = oracle.link_force(X, S.links, period=box)
     assert np.abs(F - Fo).max() <= 1e-13 * np.abs(Fo).max()
 
     wd = torch.tensor(S.w, device="cuda")

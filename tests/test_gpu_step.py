@@ -178,6 +178,33 @@ def test_step_force_is_the_spread_link_force(dim):
 
 
 @pytest.fixture(scope="module")
+def shell256_oracle():
+    w = inputs.config_shell_256(steps=2)
+    return w, oracle_sim(w).advance(w.steps)
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_shell256_full_size(shell256_oracle, precision):
+    """The timed 3-D workload itself (256^3, 65,536-point shell, dt = 5e-4)
+    against the oracle after two steps, every field."""
+    w, o = shell256_oracle
+    g = gpu_sim(w, precision)
+    g.step(w.steps)
+    assert g.sync() == w.steps
+    st = g.state()
+    errs = field_errors(st, o, 3)
+    errs["psi"] = psi_vs_p(st["psi"], o.psi, o.p)
+    print("shell256 precision", precision, errs)
+    for k, e in errs.items():
+        if precision == 0:
+            lim = max(FP64_TOL, (1 + 4 * 256 ** 2) * 2.0 ** -52) if k in ("p", "psi") else FP64_TOL
+        else:
+            lim = MIXED_TOL
+        assert e <= lim, (k, e, lim)
+    g.close()
+
+
+@pytest.fixture(scope="module")
 def ellipse512_oracle():
     w = inputs.config_ellipse_512(steps=100)
     o = oracle_sim(w).advance(w.steps)
