@@ -289,7 +289,10 @@ static void go_sb(SweepArgs<T> a, int axis, int nf, hipStream_t st) {
   const int G = (int)((N + M - 1) / M);
   const int64_t other = axis == 1 ? a.g.n2 : a.g.n1;
   dim3 grid((unsigned)((a.g.n0 + TX - 1) / TX), (unsigned)other, nf);
-  hipLaunchKernelGGL((k_sweep_sb<T, R, M, MODE, LB, TX>), grid, dim3(TX, G), 0, st, a, axis);
+  if (N % M == 0)
+    hipLaunchKernelGGL((k_sweep_sb<T, R, M, MODE, LB, TX, true>), grid, dim3(TX, G), 0, st, a, axis);
+  else
+    hipLaunchKernelGGL((k_sweep_sb<T, R, M, MODE, LB, TX, false>), grid, dim3(TX, G), 0, st, a, axis);
 }
 
 template <typename T, typename R, int M, int MODE, int TX>

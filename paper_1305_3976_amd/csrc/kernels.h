@@ -1314,46 +1314,49 @@ __global__ void __launch_bounds__(LB) k_sweep_s(SweepArgs<T> a, int axis) {
 // a wave one 64-wide row of x (256 or 512 contiguous bytes per access), TX =
 // 32 halves the block for register-heavy FP64 recurrences; threadIdx.y is
 // the chunk of M line elements.  Each array is addressed by a buffer resource
-// based at the block's first column: the lane offset is one VGPR and the
-// element offset pos * stride a wave-uniform scalar, so no per-element
-// 64-bit addresses are held.  Reads past the end of an array return 0 and
+// based at the block's first column; a thread's lane and chunk start are one
+// VGPR offset, and element q of its chunk adds q * stride, a scalar (q is a
+// compile-time index), so no per-element addresses are held and no offset
+// has to be made wave-uniform.  Reads past the end of an array return 0 and
 // writes are dropped by the resource's range check.  Requires
 // (N - 1) * stride * sizeof(double) + 64 * sizeof(double) < 2^31.
 template <typename T>
 struct Col {
   __amdgpu_buffer_rsrc_t r;
-  int vo;  // lane byte offset
+  int vo;  // byte offset of the thread's first element (lane + chunk start)
   int sb;  // byte stride between line elements
-  __device__ __forceinline__ Col(const void *base, int64_t bytes, int lane, int64_t stride) {
+  __device__ __forceinline__ Col(const void *base, int64_t bytes, int lane, int64_t stride,
+                                 int pos0) {
     const int64_t lim = bytes < 0x7fffffff ? bytes : 0x7fffffff;
     r = __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)lim, 0x00020000);
-    vo = lane * (int)sizeof(T);
     sb = (int)(stride * (int64_t)sizeof(T));
+    vo = lane * (int)sizeof(T) + pos0 * sb;
   }
-  __device__ __forceinline__ T ld(int pos) const {
+  __device__ __forceinline__ T ld(int q) const {
     if constexpr (sizeof(T) == 4) {
-      return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, vo, pos * sb, 0));
+      return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, vo, q * sb, 0));
     } else {
-      const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, vo, pos * sb, 0);
+      const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, vo, q * sb, 0);
       return __hiloint2double((int)v[1], (int)v[0]);
     }
   }
-  __device__ __forceinline__ void st(int pos, T x) const {
+  __device__ __forceinline__ void st(int q, T x) const {
     if constexpr (sizeof(T) == 4) {
-      __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), r, vo, pos * sb, 0);
+      __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(x), r, vo, q * sb, 0);
     } else {
       typedef unsigned int u2 __attribute__((ext_vector_type(2)));
       u2 v;
       v[0] = (unsigned)__double2loint(x);
       v[1] = (unsigned)__double2hiint(x);
-      __builtin_amdgcn_raw_buffer_store_b64(v, r, vo, pos * sb, 0);
+      __builtin_amdgcn_raw_buffer_store_b64(v, r, vo, q * sb, 0);
     }
   }
 };
 
 // R: recurrence type (double, or float for the benign momentum systems under
-// the mixed policy).
-template <typename T, typename R, int M, int MODE, int LB, int TX>
+// the mixed policy).  EVEN: the line length is G * M, so every chunk is full
+// and the per-element guards drop out.
+template <typename T, typename R, int M, int MODE, int LB, int TX, bool EVEN>
 __global__ void __launch_bounds__(LB) k_sweep_sb(SweepArgs<T> a, int axis) {
   __shared__ R sA[LB], sB[LB];
   const int tx = threadIdx.x, g = threadIdx.y, G = blockDim.y;
@@ -1367,42 +1370,26 @@ __global__ void __launch_bounds__(LB) k_sweep_sb(SweepArgs<T> a, int axis) {
   const int64_t rem = ncell - tb;                                          // elements to the end
   const bool live = x0 + tx < n0;
   const int s = g * M;
-  const int cnt = s >= N ? 0 : (N - s < M ? N - s : M);
+  const int cnt = EVEN ? M : (s >= N ? 0 : (N - s < M ? N - s : M));
   // 2-D batches sweep y only, so the remaining index is the layer
   const R al = (R)(a.alpha_layer ? a.alpha_layer[other] : a.alpha);
   const R ic = (R)(a.invc_layer ? a.invc_layer[other] : a.inv_c);
   const int slot = g * TX + tx;
+  auto col = [&](const auto *base) {
+    using E = std::remove_cv_t<std::remove_pointer_t<decltype(base)>>;
+    return Col<E>(base + tb, rem * (int64_t)sizeof(E), tx, stride, s);
+  };
 
   R r[M];
-  // epilogue operands are fetched together with the right-hand side
-  constexpr int MU = MODE == SW_FINAL ? M : 1, MP = MODE == SW_PFINAL ? M : 1;
-  T pu[MU], pdn[MP], pdp[MP];
-  double pp[MP];
   {
-    const Col<T> cf(a.f[fld] + tb, rem * (int64_t)sizeof(T), tx, stride);
+    const auto cf = col(a.f[fld]);
 #pragma unroll
-    for (int q = 0; q < M; q++) r[q] = q < cnt ? (R)cf.ld(s + q) : R(0);
-    if constexpr (MODE == SW_FINAL) {
-      const Col<T> cu(a.u[fld] + tb, rem * (int64_t)sizeof(T), tx, stride);
-#pragma unroll
-      for (int q = 0; q < M; q++) pu[q] = q < cnt ? cu.ld(s + q) : T(0);
-    }
-    if constexpr (MODE == SW_PFINAL) {
-      const Col<T> cdn(a.divn + tb, rem * (int64_t)sizeof(T), tx, stride);
-      const Col<T> cdp(a.divp + tb, rem * (int64_t)sizeof(T), tx, stride);
-      const Col<double> cp(a.p + tb, rem * (int64_t)sizeof(double), tx, stride);
-#pragma unroll
-      for (int q = 0; q < M; q++) {
-        pdn[q] = q < cnt ? cdn.ld(s + q) : T(0);
-        pdp[q] = q < cnt ? cdp.ld(s + q) : T(0);
-        pp[q] = q < cnt ? cp.ld(s + q) : 0.0;
-      }
-    }
+    for (int q = 0; q < M; q++) r[q] = (EVEN || q < cnt) ? (R)cf.ld(q) : R(0);
   }
   R z = 0, A = 1;
 #pragma unroll
   for (int q = 0; q < M; q++)
-    if (q < cnt) {
+    if (EVEN || q < cnt) {
       z = al * z + r[q] * ic;
       r[q] = z;
       A *= al;
@@ -1421,13 +1408,14 @@ __global__ void __launch_bounds__(LB) k_sweep_sb(SweepArgs<T> a, int axis) {
       Bt = sA[h * TX + tx] * Bt + sB[h * TX + tx];
       At = sA[h * TX + tx] * At;
     }
-    const R win = Ap * (Bt / (R(1) - At)) + Bp;
-    R pw = al;
+    // the incoming value decays by al per element: a running product keeps
+    // one register live instead of the M powers of al
+    R cw = Ap * (Bt / (R(1) - At)) + Bp;
 #pragma unroll
     for (int q = 0; q < M; q++)
-      if (q < cnt) {
-        r[q] += pw * win;
-        pw *= al;
+      if (EVEN || q < cnt) {
+        cw *= al;
+        r[q] += cw;
       }
   }
   __syncthreads();
@@ -1435,7 +1423,7 @@ __global__ void __launch_bounds__(LB) k_sweep_sb(SweepArgs<T> a, int axis) {
   A = 1;
 #pragma unroll
   for (int q = M - 1; q >= 0; q--)
-    if (q < cnt) {
+    if (EVEN || q < cnt) {
       t = al * t + r[q];
       r[q] = t;
       A *= al;
@@ -1454,26 +1442,30 @@ __global__ void __launch_bounds__(LB) k_sweep_sb(SweepArgs<T> a, int axis) {
       Bt = sA[h * TX + tx] * Bt + sB[h * TX + tx];
       At = sA[h * TX + tx] * At;
     }
-    const R xin = As * (Bt / (R(1) - At)) + Bs;
-    R pw = al;
+    R cx = As * (Bt / (R(1) - At)) + Bs;
 #pragma unroll
     for (int q = M - 1; q >= 0; q--)
-      if (q < cnt) {
-        r[q] += pw * xin;
-        pw *= al;
+      if (EVEN || q < cnt) {
+        cx *= al;
+        r[q] += cx;
       }
   }
   if (!live) return;
   if (MODE == SW_PLAIN) {
-    const Col<T> co(a.o[fld] + tb, rem * (int64_t)sizeof(T), tx, stride);
+    const auto co = col(a.o[fld]);
 #pragma unroll
     for (int q = 0; q < M; q++)
-      if (q < cnt) co.st(s + q, (T)r[q]);
+      if (EVEN || q < cnt) co.st(q, (T)r[q]);
   } else if constexpr (MODE == SW_FINAL) {
-    const Col<T> cu(a.u[fld] + tb, rem * (int64_t)sizeof(T), tx, stride);
+    // epilogue operands are read only now: held from the start they would
+    // cost M registers through both passes (fewer resident waves)
+    const auto cu = col(a.u[fld]);
+    T pu[M];
+#pragma unroll
+    for (int q = 0; q < M; q++) pu[q] = (EVEN || q < cnt) ? cu.ld(q) : T(0);
 #pragma unroll
     for (int q = 0; q < M; q++)
-      if (q < cnt) cu.st(s + q, (T)((R)pu[q] + r[q]));
+      if (EVEN || q < cnt) cu.st(q, (T)((R)pu[q] + r[q]));
   } else if constexpr (MODE == SW_PFINAL) {
     if (a.gauge) {
       // 2-D batches sweep y only, so the remaining index is the layer
@@ -1481,15 +1473,25 @@ __global__ void __launch_bounds__(LB) k_sweep_sb(SweepArgs<T> a, int axis) {
 #pragma unroll
       for (int q = 0; q < M; q++) r[q] -= gz;
     }
-    const Col<T> cf(a.f[fld] + tb, rem * (int64_t)sizeof(T), tx, stride);
-    const Col<T> cdp(a.divp + tb, rem * (int64_t)sizeof(T), tx, stride);
-    const Col<double> cp(a.p + tb, rem * (int64_t)sizeof(double), tx, stride);
+    const auto cf = col(a.f[fld]);
+    const auto cdn = col(a.divn);
+    const auto cdp = col(a.divp);
+    const auto cp = col(a.p);
+    T pdn[M], pdp[M];
+    double pp[M];
+#pragma unroll
+    for (int q = 0; q < M; q++) {
+      const bool in = EVEN || q < cnt;
+      pdn[q] = in ? cdn.ld(q) : T(0);
+      pdp[q] = in ? cdp.ld(q) : T(0);
+      pp[q] = in ? cp.ld(q) : 0.0;
+    }
 #pragma unroll
     for (int q = 0; q < M; q++)
-      if (q < cnt) {
-        cf.st(s + q, (T)r[q]);
-        cp.st(s + q, pp[q] + (double)r[q] - a.half_chi_mu * ((double)pdn[q] + (double)pdp[q]));
-        cdp.st(s + q, pdn[q]);
+      if (EVEN || q < cnt) {
+        cf.st(q, (T)r[q]);
+        cp.st(q, pp[q] + (double)r[q] - a.half_chi_mu * ((double)pdn[q] + (double)pdp[q]));
+        cdp.st(q, pdn[q]);
       }
   }
 }
