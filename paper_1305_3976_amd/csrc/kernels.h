@@ -1080,18 +1080,8 @@ __global__ void __launch_bounds__(256) k_sweep_x(SweepArgs<T> a) {
   const double ic = a.invc_layer ? a.invc_layer[lay] : a.inv_c;
 
   double r[M];
-  // epilogue operands are fetched together with the right-hand side so the
-  // wave's loads are in flight at once
-  double pre0[VEC && MODE != SW_PLAIN ? M : 1], pre1[VEC && MODE == SW_PFINAL ? M : 1],
-      pre2[VEC && MODE == SW_PFINAL ? M : 1];
   if (VEC) {
     vload<T, M>(a.f[fld] + base + s, r);
-    if constexpr (VEC && MODE == SW_FINAL) vload<T, M>(a.u[fld] + base + s, pre0);
-    if constexpr (VEC && MODE == SW_PFINAL) {
-      vload<T, M>(a.divn + base + s, pre0);
-      vload<T, M>(a.divp + base + s, pre1);
-      vload<double, M>(a.p + base + s, pre2);
-    }
   } else {
 #pragma unroll
     for (int q = 0; q < M; q++) r[q] = q < cnt ? (double)a.f[fld][base + s + q] : 0.0;
@@ -1100,7 +1090,7 @@ __global__ void __launch_bounds__(256) k_sweep_x(SweepArgs<T> a) {
   double z = 0.0, A = 1.0;
 #pragma unroll
   for (int q = 0; q < M; q++)
-    if (q < cnt) {
+    if (VEC || q < cnt) {
       z = al * z + r[q] * ic;
       r[q] = z;
       A *= al;
@@ -1131,12 +1121,13 @@ __global__ void __launch_bounds__(256) k_sweep_x(SweepArgs<T> a) {
     win = Ae * wlast + Be;
   }
   {
-    double pw = al;
+    // running product: one register instead of the M powers of al
+    double cw = win;
 #pragma unroll
     for (int q = 0; q < M; q++)
-      if (q < cnt) {
-        r[q] += pw * win;
-        pw *= al;
+      if (VEC || q < cnt) {
+        cw *= al;
+        r[q] += cw;
       }
   }
   // backward recurrence over the chunk from zero
@@ -1144,7 +1135,7 @@ __global__ void __launch_bounds__(256) k_sweep_x(SweepArgs<T> a) {
   A = 1.0;
 #pragma unroll
   for (int q = M - 1; q >= 0; q--)
-    if (q < cnt) {
+    if (VEC || q < cnt) {
       t = al * t + r[q];
       r[q] = t;
       A *= al;
@@ -1175,12 +1166,12 @@ __global__ void __launch_bounds__(256) k_sweep_x(SweepArgs<T> a) {
     xin = An * x0 + Bn;
   }
   {
-    double pw = al;
+    double cx = xin;
 #pragma unroll
     for (int q = M - 1; q >= 0; q--)
-      if (q < cnt) {
-        r[q] += pw * xin;
-        pw *= al;
+      if (VEC || q < cnt) {
+        cx *= al;
+        r[q] += cx;
       }
   }
   if (!live) return;
@@ -1189,10 +1180,18 @@ __global__ void __launch_bounds__(256) k_sweep_x(SweepArgs<T> a) {
     if (MODE == SW_PLAIN) {
       vstore<T, M>(a.o[fld] + o, r);
     } else if constexpr (MODE == SW_FINAL) {
+      // epilogue operands are read only now (held from the start they would
+      // cost M registers through both passes)
+      double pre0[M];
+      vload<T, M>(a.u[fld] + o, pre0);
 #pragma unroll
       for (int q = 0; q < M; q++) pre0[q] += r[q];
       vstore<T, M>(a.u[fld] + o, pre0);
     } else if constexpr (MODE == SW_PFINAL) {
+      double pre0[M], pre1[M], pre2[M];
+      vload<T, M>(a.divn + o, pre0);
+      vload<T, M>(a.divp + o, pre1);
+      vload<double, M>(a.p + o, pre2);
       if (a.gauge) {
         const double gz = a.gauge[a.dim == 2 ? lay : 0];
 #pragma unroll
