@@ -85,6 +85,7 @@ struct ib_ctx {
   int64_t np;
   bool f32;    // work arrays (N, psi, div, workspace) in FP32
   bool u64;    // velocity state in FP64 while the work arrays are FP32
+  int resident3;  // workgroups of the 3-D explicit kernel resident on the device at once
   size_t tsz;  // bytes per work-array value
   // workspace
   void *delta[3], *f[3], *divn;
@@ -563,9 +564,15 @@ static void launch_explicit(ib_ctx *c, bool first) {
   a.advect = !(c->prm.flags & IB_FLAG_NO_ADVECTION);
   if constexpr (DIM == 3) {
     if (c->g.n0 % EX == 0 && c->g.n1 % EY == 0 && c->g.ncell < INT32_MAX) {
-      const dim3 grid((c->g.n0 / EX) * (c->g.n1 / EY) * ((c->g.n2 + EZ - 1) / EZ));
+      // one round of resident workgroups (c->resident3, from ib_init) split
+      // over the (x, y) column tiles
+      const int resident = std::max(1, c->resident3);
+      const int64_t cols = (c->g.n0 / EX) * (c->g.n1 / EY);
+      const int64_t zb = std::max<int64_t>(1, std::min<int64_t>(c->g.n2, resident / cols));
+      a.ez = (int)((c->g.n2 + zb - 1) / zb);
+      const int64_t nblk = cols * ((c->g.n2 + a.ez - 1) / a.ez);
       launch(c, KP_EXPLICIT, [&] {
-        hipLaunchKernelGGL((k_explicit3<T, V>), grid, dim3(EX * EY), 0, c->stream, a);
+        hipLaunchKernelGGL((k_explicit3<T, V>), dim3((unsigned)nblk), dim3(EX * EY), 0, c->stream, a);
       });
       return;
     }
@@ -789,6 +796,19 @@ extern "C" ib_status ib_init(ib_ctx **out, const ib_grid_params *prm, const ib_b
   c->np = np;
   c->f32 = prm->precision != IB_PREC_FP64;
   c->u64 = prm->precision == IB_PREC_MIXED_STATE64;
+  if (prm->dim == 3) {
+    // compute units times the workgroups of the 3-D explicit kernel each
+    // holds at once (register and LDS limits of this build)
+    int dev = 0, ncu = 0, per = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    const void *fn = prm->precision == IB_PREC_FP64
+                         ? (const void *)k_explicit3<double, double>
+                         : (c->u64 ? (const void *)k_explicit3<float, double>
+                                   : (const void *)k_explicit3<float, float>);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, EX * EY, 0) != hipSuccess) per = 1;
+    c->resident3 = std::max(1, ncu) * std::max(1, per);
+  }
   c->tsz = c->f32 ? 4 : 8;
   c->mom_alpha = ma; c->mom_invc = mi; c->psi_alpha = pa; c->psi_invc = pi;
   c->nlinks = st->n_links;

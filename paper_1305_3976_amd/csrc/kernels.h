@@ -696,6 +696,7 @@ struct ExplicitArgs {
   TileGrid tg;
   double inv_h, inv_h2, dt, mu, inv_rho;
   int first, advect;
+  int ez;  // planes per workgroup of the 3-D plane-marching kernel
 };
 
 template <typename T, int DIM, typename V = T>
@@ -756,14 +757,16 @@ __global__ void __launch_bounds__(256) k_explicit(ExplicitArgs<T, DIM, V> a) {
 }
 
 // 3-D explicit step on a 2.5-D blocking: a workgroup owns an EX x EY tile of
-// (x, y) columns and marches EZ planes along z.  Three planes of u, v, w
+// (x, y) columns and marches a.ez planes along z; the host sizes ez so the
+// whole grid is one round of resident workgroups (no tail round), which
+// also cuts the prologues and z-halo re-reads.  Three planes of u, v, w
 // (tile plus a one-cell halo) and the current plane of p* = p + psi (tile
 // plus its -x, -y halo) sit in LDS, so each value is fetched from HBM about
 // once instead of once per stencil use.  The loads are software-pipelined:
 // while plane k is computed from LDS, plane k+2 of the velocities, plane k+1
 // of p* and this cell's N^{n-1} and f are already in flight into registers.
 // Same arithmetic as k_explicit.
-constexpr int EX = 64, EY = 4, EZ = 16;
+constexpr int EX = 64, EY = 4;
 constexpr int EW = EX + 2, EH = EY + 2;  // velocity plane with halo
 constexpr int PW = EX + 1, PH = EY + 1;  // p* plane with -x, -y halo
 constexpr int ENT = EX * EY;             // threads per workgroup
@@ -784,6 +787,7 @@ __global__ void __launch_bounds__(ENT) k_explicit3(ExplicitArgs<T, 3, V> a) {
   const int nbx = n0 / EX, nby = n1 / EY;
   const int nb = gridDim.x;
   const int b = (nb % 8 == 0) ? (blockIdx.x % 8) * (nb / 8) + blockIdx.x / 8 : blockIdx.x;
+  const int EZ = a.ez;
   const int i0 = (b % nbx) * EX, j0 = ((b / nbx) % nby) * EY, k0 = (b / (nbx * nby)) * EZ;
   const int plane = n0 * n1;  // < 2^31 (checked on the host)
   auto wrap = [](int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); };
