@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--cylinder", type=int, nargs="*", default=[256, 128], metavar="N",
                     help="grid sizes of the 3-D cylinder row (100 steps each, mixed and "
                          "FP64); none to skip")
+    ap.add_argument("--cylinder-only", action="store_true",
+                    help="run only the cylinder row (for profiling it alone) and print it")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB (3 times), the reference "
                          "for scaling hardware byte counters")
@@ -306,6 +308,11 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.cylinder_only:
+        print(json.dumps({"cylinder": run_cylinder(args.cylinder or [256],
+                                                   steps=args.steps, warmup=args.warmup,
+                                                   fp64=not args.no_fp64)}), flush=True)
+        return
     copy_gbs = device_copy_rate()
     from paper_1305_3976_amd import inputs
     w = inputs.config_shell_256(steps=args.steps, n=args.n, npts=args.points)

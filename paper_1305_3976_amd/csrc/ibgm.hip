@@ -800,8 +800,9 @@ extern "C" ib_status ib_init(ib_ctx **out, const ib_grid_params *prm, const ib_b
     // compute units times the workgroups of the 3-D explicit kernel each
     // holds at once (register and LDS limits of this build)
     int dev = 0, ncu = 0, per = 0;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      ncu = 1;
     const void *fn = prm->precision == IB_PREC_FP64
                          ? (const void *)k_explicit3<double, double>
                          : (c->u64 ? (const void *)k_explicit3<float, double>

@@ -180,16 +180,22 @@ __global__ void __launch_bounds__(256) k_interp(InterpArgs<T, DIM> a) {
                             nn[ax], w[ax]);
   const T *__restrict__ uc = a.u[c];
   C acc = 0;
+  // fully unrolled: all 64 loads of the stencil are issued before the first
+  // use (left to itself the compiler keeps the outer loop for FP32 and waits
+  // on memory four times per point)
   if (DIM == 3) {
+#pragma unroll
     for (int t2 = 0; t2 < 4; t2++) {
       int64_t kk = b[2] + t2;
       kk -= kk >= nn[2] ? nn[2] : 0;
       C acc1 = 0;
+#pragma unroll
       for (int t1 = 0; t1 < 4; t1++) {
         int64_t jj = b[1] + t1;
         jj -= jj >= nn[1] ? nn[1] : 0;
         const T *row = uc + (kk * nn[1] + jj) * nn[0];
         C acc0 = 0;
+#pragma unroll
         for (int t0 = 0; t0 < 4; t0++) {
           int64_t ii = b[0] + t0;
           ii -= ii >= nn[0] ? nn[0] : 0;
