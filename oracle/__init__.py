@@ -43,7 +43,7 @@ class Params(ctypes.Structure):
                 ("h", ctypes.c_double), ("rho", ctypes.c_double),
                 ("mu", ctypes.c_double), ("dt", ctypes.c_double),
                 ("chi", ctypes.c_double), ("rotate", ctypes.c_int32),
-                ("no_advection", ctypes.c_int32)]
+                ("no_advection", ctypes.c_int32), ("walls_y", ctypes.c_int32)]
 
 
 class _Sim(ctypes.Structure):
@@ -75,6 +75,9 @@ def lib():
         L.ibo_link_force.argtypes = [ctypes.c_int32, ctypes.c_int64, _dp, _dp,
                                      ctypes.c_int64, _ip, _ip, _dp, _dp, _dp]
         L.ibo_advection.argtypes = [ctypes.POINTER(Params), _dp * 3, _dp * 3]
+        L.ibo_vel_laplacian.argtypes = [ctypes.POINTER(Params), ctypes.c_int32, _dp, _dp]
+        L.ibo_line_solve_bc.argtypes = [_dp, _ip, ctypes.c_int32, ctypes.c_double,
+                                        ctypes.c_double, ctypes.c_int32]
         L.ibo_laplacian.argtypes = [ctypes.POINTER(Params), _dp, _dp]
         L.ibo_divergence.argtypes = [ctypes.POINTER(Params), _dp * 3, _dp]
         L.ibo_gradient.argtypes = [ctypes.POINTER(Params), _dp, _dp * 3]
@@ -97,7 +100,7 @@ def _pi(a: np.ndarray):
 
 
 def make_params(dim, n, h, rho=1.0, mu=0.0, dt=1e-3, chi=0.6, rotate=True,
-                no_advection=False) -> Params:
+                no_advection=False, walls_y=False) -> Params:
     nn = list(n) + [1] * (3 - len(n))
     P = Params()
     P.dim = dim
@@ -106,6 +109,7 @@ def make_params(dim, n, h, rho=1.0, mu=0.0, dt=1e-3, chi=0.6, rotate=True,
     P.h, P.rho, P.mu, P.dt, P.chi = h, rho, mu, dt, chi
     P.rotate = 1 if rotate else 0
     P.no_advection = 1 if no_advection else 0
+    P.walls_y = 1 if walls_y else 0
     return P
 
 
@@ -140,6 +144,23 @@ def line_solve(field_, axis: int, diag: float, off: float):
     shp = f.shape[::-1] + (1,) * (3 - f.ndim)
     n = np.array(shp, dtype=np.int32)
     rc = lib().ibo_line_solve(_p(f), _pi(n), axis, diag, off)
+    if rc != 0:
+        raise ValueError("line solve failed")
+    return f
+
+
+BC_PERIODIC, BC_DIRICHLET_CELL, BC_DIRICHLET_FACE, BC_NEUMANN_CELL = 0, 1, 2, 3
+
+
+def line_solve_bc(field_, axis: int, diag: float, off: float, bc: int):
+    """line_solve with a channel boundary kind along `axis` (the BC_* values:
+    periodic, Dirichlet for cell-centred unknowns (ghost -x), Dirichlet for a
+    face unknown on the wall (element 0 held at 0), Neumann for cell-centred
+    unknowns (ghost +x))."""
+    f = np.ascontiguousarray(field_, dtype=np.float64).copy()
+    shp = f.shape[::-1] + (1,) * (3 - f.ndim)
+    n = np.array(shp, dtype=np.int32)
+    rc = lib().ibo_line_solve_bc(_p(f), _pi(n), axis, diag, off, bc)
     if rc != 0:
         raise ValueError("line solve failed")
     return f
@@ -196,6 +217,14 @@ def laplacian(P: Params, q):
     q = np.ascontiguousarray(q, dtype=np.float64)
     out = np.zeros_like(q)
     lib().ibo_laplacian(ctypes.byref(P), _p(q), _p(out))
+    return out
+
+
+def vel_laplacian(P: Params, c: int, q):
+    """Laplacian of velocity component c, with the channel's walls if set."""
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    out = np.zeros_like(q)
+    lib().ibo_vel_laplacian(ctypes.byref(P), c, _p(q), _p(out))
     return out
 
 

@@ -56,6 +56,22 @@ static double at(const ibo_params *P, const double *q, int64_t i, int64_t j,
   return q[ii + (int64_t)P->n[0] * (jj + (int64_t)P->n[1] * kk)];
 }
 
+/* Velocity component c at integer index (i, j, k).  Periodic, except across
+ * the channel's walls (walls_y): a tangential component (c != 1, stored at
+ * cell centres in y) takes the no-slip ghost value -u of the cell across the
+ * wall; v (c == 1) is stored on the y faces, face 0 is the wall (both walls,
+ * periodically) and holds 0, so plain periodic indexing already gives the
+ * wall value there. */
+static double vel(const ibo_params *P, int32_t c, const double *q, int64_t i, int64_t j,
+                  int64_t k) {
+  if (P->walls_y && c != 1) {
+    const int64_t n1 = P->n[1];
+    if (j < 0) return -at(P, q, i, -1 - j, k);
+    if (j >= n1) return -at(P, q, i, 2 * n1 - 1 - j, k);
+  }
+  return at(P, q, i, j, k);
+}
+
 static int valid_params(const ibo_params *P) {
   if (P->dim != 2 && P->dim != 3) return 0;
   for (int a = 0; a < P->dim; a++)
@@ -173,6 +189,67 @@ int ibo_line_solve(double *field, const int32_t n[3], int32_t axis,
         continue;
       }
       for (int32_t i = 0; i < N; i++) field[base + i * stride] = x[i];
+    }
+    free(buf);
+  }
+  (void)n2;
+  return err ? -1 : 0;
+}
+
+/* eq:TriDiagX with the channel's boundary kinds along one axis.  The wall
+ * rows are written out: a ghost value -x (Dirichlet, cell-centred) or +x
+ * (Neumann, cell-centred) across the wall folds into the diagonal of the
+ * first and last rows; a face unknown on the wall (element 0, and element N
+ * on the opposite wall) is zero, so rows 1..N-1 form the system.  Each is a
+ * plain Thomas solve. */
+int ibo_line_solve_bc(double *field, const int32_t n[3], int32_t axis, double diag,
+                      double off, int32_t bc) {
+  if (bc == IBO_BC_PERIODIC) return ibo_line_solve(field, n, axis, diag, off);
+  if (axis < 0 || axis > 2 || bc < 1 || bc > 3) return -1;
+  const int32_t N = n[axis];
+  if (N < 3) return -1;
+  const int64_t n0 = n[0], n1 = n[1], n2 = n[2];
+  const int64_t stride = axis == 0 ? 1 : (axis == 1 ? n0 : n0 * n1);
+  const int64_t nlines = n0 * n1 * n2 / N;
+  int err = 0;
+#pragma omp parallel
+  {
+    double *buf = (double *)malloc(sizeof(double) * 7 * (size_t)N);
+    if (!buf) {
+#pragma omp atomic write
+      err = 1;
+    }
+#pragma omp for
+    for (int64_t L = 0; L < nlines; L++) {
+      if (!buf) continue;
+      double *a = buf, *b = buf + N, *c = buf + 2 * N, *d = buf + 3 * N, *x = buf + 4 * N,
+             *cp = buf + 5 * N, *dp = buf + 6 * N;
+      int64_t base;
+      if (axis == 0) base = L * n0;
+      else if (axis == 1) base = (L % n0) + (L / n0) * n0 * n1;
+      else base = L;
+      const int32_t first = bc == IBO_BC_DIRICHLET_FACE ? 1 : 0;
+      const int32_t m = N - first;
+      for (int32_t r = 0; r < m; r++) {
+        a[r] = off;
+        b[r] = diag;
+        c[r] = off;
+        d[r] = field[base + (r + first) * stride];
+      }
+      if (bc == IBO_BC_DIRICHLET_CELL) {
+        b[0] = diag - off;
+        b[m - 1] = diag - off;
+      } else if (bc == IBO_BC_NEUMANN_CELL) {
+        b[0] = diag + off;
+        b[m - 1] = diag + off;
+      }
+      if (thomas(m, a, b, c, d, x, cp, dp) != 0) {
+#pragma omp atomic write
+        err = 1;
+        continue;
+      }
+      if (first) field[base] = 0.0;
+      for (int32_t r = 0; r < m; r++) field[base + (r + first) * stride] = x[r];
     }
     free(buf);
   }
@@ -309,17 +386,21 @@ void ibo_advection(const ibo_params *P, const double *const u[3],
     for (int64_t kk = 0; kk < n2; kk++)
       for (int64_t jj = 0; jj < n1; jj++)
         for (int64_t ii = 0; ii < n0; ii++) {
+          if (P->walls_y && ci == 1 && jj == 0) {  /* v on the wall: fixed at 0 */
+            N[ci][ii + n0 * (jj + n1 * kk)] = 0.0;
+            continue;
+          }
           int64_t c[3] = {ii, jj, kk};
           int64_t ei[3] = {0, 0, 0};
           ei[ci] = 1;
-          double u0 = at(P, u[ci], c[0], c[1], c[2]);
+          double u0 = vel(P, ci, u[ci], c[0], c[1], c[2]);
           double dv = 0.0, ad = 0.0;
           for (int32_t cj = 0; cj < d; cj++) {
             int64_t ej[3] = {0, 0, 0};
             ej[cj] = 1;
             if (cj == ci) {
-              double up = at(P, u[ci], c[0] + ei[0], c[1] + ei[1], c[2] + ei[2]);
-              double um = at(P, u[ci], c[0] - ei[0], c[1] - ei[1], c[2] - ei[2]);
+              double up = vel(P, ci, u[ci], c[0] + ei[0], c[1] + ei[1], c[2] + ei[2]);
+              double um = vel(P, ci, u[ci], c[0] - ei[0], c[1] - ei[1], c[2] - ei[2]);
               double ap = 0.5 * (u0 + up); /* centre of cell c */
               double am = 0.5 * (um + u0); /* centre of cell c - e_i */
               dv += (ap * ap - am * am) / h;
@@ -328,14 +409,14 @@ void ibo_advection(const ibo_params *P, const double *const u[3],
               /* transporting velocity u_j averaged along x_i, on the edges at
                * c (lower j side) and c + e_j (upper j side) */
               double Uj0 =
-                  0.5 * (at(P, u[cj], c[0] - ei[0], c[1] - ei[1], c[2] - ei[2]) +
-                         at(P, u[cj], c[0], c[1], c[2]));
+                  0.5 * (vel(P, cj, u[cj], c[0] - ei[0], c[1] - ei[1], c[2] - ei[2]) +
+                         vel(P, cj, u[cj], c[0], c[1], c[2]));
               double Uj1 =
-                  0.5 * (at(P, u[cj], c[0] + ej[0] - ei[0], c[1] + ej[1] - ei[1],
+                  0.5 * (vel(P, cj, u[cj], c[0] + ej[0] - ei[0], c[1] + ej[1] - ei[1],
                             c[2] + ej[2] - ei[2]) +
-                         at(P, u[cj], c[0] + ej[0], c[1] + ej[1], c[2] + ej[2]));
-              double ujp = at(P, u[ci], c[0] + ej[0], c[1] + ej[1], c[2] + ej[2]);
-              double ujm = at(P, u[ci], c[0] - ej[0], c[1] - ej[1], c[2] - ej[2]);
+                         vel(P, cj, u[cj], c[0] + ej[0], c[1] + ej[1], c[2] + ej[2]));
+              double ujp = vel(P, ci, u[ci], c[0] + ej[0], c[1] + ej[1], c[2] + ej[2]);
+              double ujm = vel(P, ci, u[ci], c[0] - ej[0], c[1] - ej[1], c[2] - ej[2]);
               double ui0 = 0.5 * (ujm + u0); /* u_i averaged along x_j, edge c */
               double ui1 = 0.5 * (u0 + ujp); /* same, edge c + e_j */
               dv += (Uj1 * ui1 - Uj0 * ui0) / h;
@@ -366,8 +447,9 @@ void ibo_laplacian(const ibo_params *P, const double *q, double *out) {
       }
 }
 
-/* Second difference along one axis only (D_aa). */
-static void second_diff(const ibo_params *P, const double *q, int32_t axis,
+/* Second difference along one axis only (D_aa) of velocity component c
+ * (walls through vel(); v on a wall face gets 0). */
+static void second_diff(const ibo_params *P, int32_t c, const double *q, int32_t axis,
                         double *out) {
   const double h2 = P->h * P->h;
   const int64_t n0 = P->n[0], n1 = P->n[1], n2 = P->n[2];
@@ -378,9 +460,23 @@ static void second_diff(const ibo_params *P, const double *q, int32_t axis,
     for (int64_t j = 0; j < n1; j++)
       for (int64_t i = 0; i < n0; i++)
         out[i + n0 * (j + n1 * k)] =
-            (at(P, q, i + e[0], j + e[1], k + e[2]) - 2.0 * at(P, q, i, j, k) +
-             at(P, q, i - e[0], j - e[1], k - e[2])) /
-            h2;
+            (P->walls_y && c == 1 && j == 0)
+                ? 0.0
+                : (vel(P, c, q, i + e[0], j + e[1], k + e[2]) - 2.0 * vel(P, c, q, i, j, k) +
+                   vel(P, c, q, i - e[0], j - e[1], k - e[2])) /
+                      h2;
+}
+
+void ibo_vel_laplacian(const ibo_params *P, int32_t c, const double *q, double *out) {
+  const int64_t nc = ncells(P);
+  double *tmp = (double *)malloc(sizeof(double) * (size_t)nc);
+  if (!tmp) return;
+  for (int64_t i = 0; i < nc; i++) out[i] = 0.0;
+  for (int32_t a = 0; a < P->dim; a++) {
+    second_diff(P, c, q, a, tmp);
+    for (int64_t i = 0; i < nc; i++) out[i] += tmp[i];
+  }
+  free(tmp);
 }
 
 /* D^{E->C} . u = sum_a (u_a[c + e_a] - u_a[c]) / h. */
@@ -481,12 +577,16 @@ int ibo_step(ibo_sim *s) {
   }
   ibo_gradient(P, pstar, g);
   for (int32_t c = 0; c < d; c++) {
-    ibo_laplacian(P, un[c], lap);
+    ibo_vel_laplacian(P, c, un[c], lap);
     for (int64_t i = 0; i < nc; i++) {
       double Nh = (n == 0) ? Nn[c][i] : 1.5 * Nn[c][i] - 0.5 * s->nl_prev[c][i];
       us[c][i] = un[c][i] + dt * (-Nh + (mu * lap[i] - g[c][i] + f[c][i]) / rho);
     }
   }
+  /* channel: v stays zero on the wall faces (row j = 0 of every layer) */
+  if (P->walls_y)
+    for (int64_t k = 0; k < P->n[2]; k++)
+      for (int64_t i = 0; i < P->n[0]; i++) us[1][i + (int64_t)P->n[0] * P->n[1] * k] = 0.0;
 
   /* Steps 3c-3d (and the z sweep in 3D), eq:umacstep1/2:
    *   (1 - nu D_aa) u^(a) = u^(a-1) - nu D_aa u^n,  nu = mu dt / (2 rho). */
@@ -497,10 +597,12 @@ int ibo_step(ibo_sim *s) {
   for (int32_t c = 0; c < d && rc == 0; c++) {
     for (int32_t s_ = 0; s_ < d && rc == 0; s_++) {
       int32_t ax = order[s_];
-      second_diff(P, un[c], ax, lap);
+      second_diff(P, c, un[c], ax, lap);
       for (int64_t i = 0; i < nc; i++) us[c][i] = us[c][i] - nu * lap[i];
-      rc = ibo_line_solve(us[c], P->n, ax, 1.0 + 2.0 * nu / (h * h),
-                          -nu / (h * h));
+      const int32_t bc = (P->walls_y && ax == 1)
+                             ? (c == 1 ? IBO_BC_DIRICHLET_FACE : IBO_BC_DIRICHLET_CELL)
+                             : IBO_BC_PERIODIC;
+      rc = ibo_line_solve_bc(us[c], P->n, ax, 1.0 + 2.0 * nu / (h * h), -nu / (h * h), bc);
     }
   }
   /* us now holds u^{n+1}. */
@@ -510,9 +612,11 @@ int ibo_step(ibo_sim *s) {
   if (rc == 0) {
     ibo_divergence(P, (const double *const *)us, rhs);
     for (int64_t i = 0; i < nc; i++) rhs[i] = -(rho / dt) * rhs[i];
+    /* channel: psi takes a homogeneous Neumann condition at the walls */
     for (int32_t s_ = 0; s_ < d && rc == 0; s_++)
-      rc = ibo_line_solve(rhs, P->n, order[s_], 1.0 + 2.0 / (h * h),
-                          -1.0 / (h * h));
+      rc = ibo_line_solve_bc(rhs, P->n, order[s_], 1.0 + 2.0 / (h * h), -1.0 / (h * h),
+                             (P->walls_y && order[s_] == 1) ? IBO_BC_NEUMANN_CELL
+                                                            : IBO_BC_PERIODIC);
   }
 
   if (rc == 0) {

@@ -32,6 +32,8 @@ typedef struct {
   double chi;         /* pressure-correction weight (0.6 in the paper) */
   int32_t rotate;     /* 1: rotate the split order every step */
   int32_t no_advection; /* 1: drop the advection term (Stokes flow) */
+  int32_t walls_y;    /* 1: no-slip walls at y = 0 and y = n1 h (a channel,
+                         periodic in x and z); 0: periodic in y */
 } ibo_params;
 
 typedef struct {
@@ -89,8 +91,25 @@ void ibo_link_force(int32_t dim, int64_t np, const double *X, const double *peri
 void ibo_advection(const ibo_params *prm, const double *const u[3],
                    double *const N[3]);
 
-/* D_xx + D_yy (+ D_zz) of a field at any fixed staggering. */
+/* D_xx + D_yy (+ D_zz) of a field at any fixed staggering (periodic box). */
 void ibo_laplacian(const ibo_params *prm, const double *q, double *out);
+
+/* The same for velocity component c, with the channel's no-slip walls when
+ * prm->walls_y is set (tangential components reflect oddly across a wall,
+ * v is zero on the wall faces). */
+void ibo_vel_laplacian(const ibo_params *prm, int32_t c, const double *q, double *out);
+
+/* Line-solve boundary kinds: periodic; Dirichlet for a cell-centred unknown
+ * (ghost value -x across the wall); Dirichlet for a face unknown whose
+ * element 0 lies on the wall (x_0 = 0, and x_N = 0 on the opposite wall);
+ * Neumann for a cell-centred unknown (ghost value +x). */
+enum { IBO_BC_PERIODIC = 0, IBO_BC_DIRICHLET_CELL = 1, IBO_BC_DIRICHLET_FACE = 2,
+       IBO_BC_NEUMANN_CELL = 3 };
+
+/* eq:TriDiagX along `axis` with the given boundary kind (a plain Thomas
+ * solve of the bounded system for the non-periodic kinds). */
+int ibo_line_solve_bc(double *field, const int32_t n[3], int32_t axis, double diag,
+                      double off, int32_t bc);
 
 /* D^{E->C} . u : forward differences to the cell centres. */
 void ibo_divergence(const ibo_params *prm, const double *const u[3],

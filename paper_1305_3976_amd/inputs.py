@@ -259,6 +259,47 @@ class Workload:
         return 1.0 / self.n[0]
 
 
+def channel_velocity(dim: int, n, seed: int = 1, amp: float = 0.2) -> list:
+    """Smooth, discretely divergence-free velocity for a channel with walls at
+    y = 0 and y = n1 h (v = 0 on the wall faces, rows j = 0): a stream
+    function (2-D) or vector potential (3-D, A_y = 0) built from
+    cos/sin(2 pi (kx x + kz z)) sin(m pi y) modes with N(0,1) coefficients,
+    which vanishes on the wall rows, differenced with one-cell stencils and
+    scaled to max |u| = amp."""
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n[0]
+    ny = n[1]
+    x = np.arange(n[0]) * h
+    yw = np.arange(ny) / ny                         # wall-face rows y = j h
+    z = np.arange(n[2]) * h if dim == 3 else np.zeros(1)
+    Z, Y, Xg = np.meshgrid(z, yw, x, indexing="ij")
+
+    def potential():
+        s = np.zeros(Xg.shape)
+        for kx in range(0, 3):
+            for m in range(1, 4):
+                for kz in (range(0, 2) if dim == 3 else [0]):
+                    a, b = rng.standard_normal(2)
+                    ph = 2 * math.pi * (kx * Xg + kz * Z)
+                    s += (a * np.cos(ph) + b * np.sin(ph)) * np.sin(m * math.pi * Y)
+        return s                                     # zero on the wall rows j = 0
+
+    if dim == 2:
+        s = potential()                               # at corners (i h, j h)
+        u = (np.roll(s, -1, axis=1) - s) / h          # x-faces (i h, (j+1/2) h)
+        v = -(np.roll(s, -1, axis=2) - s) / h         # y-faces (j = 0 rows stay 0)
+        vel = [u, v]
+    else:
+        A0, A2 = potential(), potential()              # A_x on x-edges, A_z on z-edges
+        # u = curl A with A_y = 0: u = dA_z/dy, v = dA_x/dz - dA_z/dx, w = -dA_x/dy
+        u = (np.roll(A2, -1, axis=1) - A2) / h
+        v = (np.roll(A0, -1, axis=0) - A0) / h - (np.roll(A2, -1, axis=2) - A2) / h
+        w = -(np.roll(A0, -1, axis=1) - A0) / h
+        vel = [u, v, w]
+    scale = amp / max(np.abs(c).max() for c in vel)
+    return [c * scale for c in vel]
+
+
 def config_ellipse_64(steps: int = 100) -> Workload:
     """2-D periodic unit square, 64^2, rho=1, mu=0.1, dt=1e-3; closed ellipse
     (semi-axes 0.3/0.2, centred), 256 points, sigma=1, L=0, fluid at rest."""

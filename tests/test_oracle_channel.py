@@ -1,0 +1,137 @@
+"""Pins of the oracle's channel (no-slip walls at y = 0 and y = 1, periodic in
+x and z) against what the mathematics fixes: the bounded line systems against
+the periodic solve of the mirrored (odd or even) extension and against dense
+solves; the exact decay factor of a shear mode between the walls; energy
+neutrality of the skew advection with walls; v stays zero on the wall faces,
+rest stays at rest and the mean pressure stays zero with a membrane between
+the walls.  (The paper notes
+the solver is not tied to periodic boundaries, Sec. "Comparison with Poisson
+Solvers"; the walls here are its periodic channel.)"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1305_3976_amd import inputs
+
+NO_LINKS = (np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0), np.zeros(0))
+
+
+def dense(N, diag, off, bc):
+    A = np.diag(np.full(N, diag)) + np.diag(np.full(N - 1, off), 1) + np.diag(np.full(N - 1, off), -1)
+    if bc == oracle.BC_DIRICHLET_CELL:
+        A[0, 0] -= off
+        A[-1, -1] -= off
+    elif bc == oracle.BC_NEUMANN_CELL:
+        A[0, 0] += off
+        A[-1, -1] += off
+    return A
+
+
+@pytest.mark.parametrize("bc", [oracle.BC_DIRICHLET_CELL, oracle.BC_DIRICHLET_FACE,
+                                oracle.BC_NEUMANN_CELL])
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_bounded_line_solves_are_mirrored_periodic_solves(bc, axis):
+    """Method of images: with the ghost value -x (+x) across a wall between
+    cells, the bounded system is the periodic system of twice the length
+    applied to the odd (even) extension about the wall; a face unknown on the
+    wall extends oddly about that face (x_0 = x_N = 0)."""
+    rng = np.random.default_rng(3 + bc + 7 * axis)
+    shape = [5, 6, 7]
+    N = shape[2 - axis]
+    diag, off = 1.0 + 2.0 * 37.0, -37.0
+    f = rng.standard_normal(shape)
+    if bc == oracle.BC_DIRICHLET_FACE:
+        idx = [slice(None)] * 3
+        idx[2 - axis] = 0
+        f[tuple(idx)] = 0.0
+    got = oracle.line_solve_bc(f, axis, diag, off, bc)
+    g = np.moveaxis(f, 2 - axis, -1)
+    if bc == oracle.BC_DIRICHLET_CELL:
+        ext = np.concatenate([g, -g[..., ::-1]], axis=-1)
+    elif bc == oracle.BC_NEUMANN_CELL:
+        ext = np.concatenate([g, g[..., ::-1]], axis=-1)
+    else:  # face: x_0 = 0, x_{N+m} = -x_{N-m}
+        ext = np.concatenate([g, np.zeros(g.shape[:-1] + (1,)), -g[..., :0:-1]], axis=-1)[..., :2 * N]
+    ext_sol = oracle.line_solve(np.moveaxis(ext, -1, 2 - axis), axis, diag, off)
+    want = np.moveaxis(np.moveaxis(ext_sol, 2 - axis, -1)[..., :N], -1, 2 - axis)
+    assert np.abs(got - want).max() < 1e-12 * np.abs(want).max()
+    # and the written-out bounded matrix, solved densely, line by line
+    gl = np.moveaxis(got, 2 - axis, -1).reshape(-1, N)
+    fl = g.reshape(-1, N)
+    if bc == oracle.BC_DIRICHLET_FACE:
+        A = dense(N - 1, diag, off, bc)
+        assert np.abs(gl[:, 0]).max() == 0.0
+        ref = np.linalg.solve(A, fl[:, 1:].T).T
+        assert np.abs(gl[:, 1:] - ref).max() < 1e-12 * np.abs(ref).max()
+    else:
+        ref = np.linalg.solve(dense(N, diag, off, bc), fl.T).T
+        assert np.abs(gl - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+def channel_sim(dim, n, u, structure=None, mu=0.05, dt=1e-3, no_advection=False, rotate=True):
+    P = oracle.make_params(dim, n, 1.0 / n[0], mu=mu, dt=dt, no_advection=no_advection,
+                           rotate=rotate, walls_y=True)
+    if structure is None:
+        return oracle.Sim(P, u, np.full((dim, 1), 0.5), NO_LINKS, np.ones(1))
+    return oracle.Sim(P, u, structure.X, structure.links, structure.w)
+
+
+@pytest.mark.parametrize("dim,comp,k", [(2, 0, 1), (2, 0, 3), (3, 0, 2), (3, 2, 1)])
+def test_shear_mode_decay_between_walls(dim, comp, k):
+    """u_c(y) = sin(k pi (j + 1/2)/n1), all else 0: divergence-free, its
+    advection vanishes, and it is an eigenvector of the wall second
+    difference with lambda = -(4/h^2) sin^2(k pi/(2 n1)).  The explicit step
+    and the Douglas sweeps then give exactly
+    u^{n+1} = (1 + nu lambda)/(1 - nu lambda) u^n,  nu = mu dt/(2 rho);
+    psi and p stay zero."""
+    n = (8, 16, 6 if dim == 3 else 1)
+    h = 1.0 / n[0]
+    mu, dt, steps = 0.05, 2e-3, 7
+    y = (np.arange(n[1]) + 0.5) / n[1]
+    prof = np.sin(k * math.pi * y)
+    shp = (n[2], n[1], n[0])
+    u = [np.zeros(shp) for _ in range(dim)]
+    u[comp] = np.broadcast_to(prof[None, :, None], shp).copy()
+    s = channel_sim(dim, n, u, mu=mu, dt=dt).advance(steps)
+    lam = -(4 / h ** 2) * math.sin(k * math.pi / (2 * n[1])) ** 2
+    nu = mu * dt / 2
+    g = (1 + nu * lam) / (1 - nu * lam)
+    assert np.abs(s.u[comp] - g ** steps * u[comp]).max() < 1e-13
+    for c in range(dim):
+        if c != comp:
+            assert np.abs(s.u[c]).max() < 1e-13
+    assert np.abs(s.p).max() < 1e-11 and np.abs(s.psi).max() < 1e-11
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_advection_with_walls_is_energy_neutral(dim):
+    n = (8, 12, 6 if dim == 3 else 1)
+    P = oracle.make_params(dim, n, 1.0 / n[0], walls_y=True)
+    rng = np.random.default_rng(5)
+    u = [rng.standard_normal((n[2], n[1], n[0])) for _ in range(dim)]
+    u[1][:, 0, :] = 0.0
+    N = oracle.advection(P, u)
+    e = sum(float(np.sum(u[c] * N[c])) for c in range(dim))
+    scale = sum(float(np.sum(np.abs(u[c] * N[c]))) for c in range(dim))
+    assert abs(e) < 1e-13 * scale
+    assert np.abs(N[1][:, 0, :]).max() == 0.0
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_channel_invariants(dim):
+    n = (16, 16, 8 if dim == 3 else 1)
+    shp = (n[2], n[1], n[0])
+    s = channel_sim(dim, n, [np.zeros(shp)] * dim).advance(3)
+    assert max(np.abs(c).max() for c in s.u[:dim]) == 0.0
+    u0 = inputs.channel_velocity(dim, n, seed=1)
+    P = oracle.make_params(dim, n, 1.0 / n[0], walls_y=True)
+    assert np.abs(oracle.divergence(P, u0)).max() < 1e-12
+    if dim == 2:
+        S = inputs.ellipse(64, 0.2, 0.15, 1.0)
+    else:
+        S = inputs.ellipsoid_shell(300, axes=(0.2, 0.15, 0.1), center=(0.5, 0.5, 0.25))
+    s = channel_sim(dim, n, u0, structure=S, mu=0.05, dt=1e-3).advance(20)
+    assert np.abs(s.u[1][:, 0, :]).max() == 0.0          # v on the walls
+    assert abs(float(np.mean(s.p))) < 1e-10 * max(1.0, np.abs(s.p).max())
