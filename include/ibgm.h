@@ -73,6 +73,17 @@ typedef enum {
 
 /* flags */
 #define IB_FLAG_NO_ADVECTION 1 /* drop the advection term (Stokes flow) */
+/* No-slip walls at y = 0 and y = n[1] h: a channel, periodic in x (and z).
+ * The solver is not tied to periodic boundaries and the channel is the
+ * paper's example (Sec. "Comparison with Poisson Solvers").  u (and w) take
+ * the ghost value -u across a wall, v is zero on the wall faces (y-face row
+ * j = 0, which is both walls periodically; the caller's initial v must be
+ * zero there), psi takes a homogeneous Neumann condition; the y sweeps solve
+ * these bounded systems as periodic ones on the odd / even mirror image of
+ * each line.  Requires 32 <= n[1] <= 512 with n[1] a multiple of 16 (of 32
+ * above 256).  Lagrangian points must stay at least 2h from the walls (the
+ * 4-point stencils then never reach across them); nothing checks this. */
+#define IB_FLAG_WALLS_Y 2
 
 typedef struct {
   int32_t dim;          /* 2 or 3 */

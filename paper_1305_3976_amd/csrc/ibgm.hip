@@ -347,11 +347,34 @@ static const SweepTune *tune_of(const ib_ctx *c, int axis, bool r64) {
 
 // Launch one sweep along `axis`; `id_x` / `id_s` name it for profiling (the
 // strided id is id_x + 1).  R is the recurrence type of the strided kernel.
+// Channel walls: the y systems are bounded (a.bc per field); they are
+// solved as periodic systems on the mirrored line of length 2 n1 (chunks of
+// 16, or 32 above n1 = 256; 32 columns per workgroup row).
+template <typename T, typename R, int M, int MODE, int LB>
+static void go_wall(SweepArgs<T> a, int nf, hipStream_t st) {
+  const int G = 2 * a.g.n1 / M;
+  dim3 grid((unsigned)((a.g.n0 + 31) / 32), (unsigned)a.g.n2, nf);
+  hipLaunchKernelGGL((k_sweep_wall<T, R, M, MODE, LB>), grid, dim3(32, G), 0, st, a);
+}
+
+template <typename T, int MODE, typename R>
+static void dispatch_wall(SweepArgs<T> a, int nf, hipStream_t st) {
+  const int n1 = (int)a.g.n1;  // 32..512, checked at ib_init
+  if (n1 <= 64) go_wall<T, R, 16, MODE, 256>(a, nf, st);
+  else if (n1 <= 128) go_wall<T, R, 16, MODE, 512>(a, nf, st);
+  else if (n1 <= 256) go_wall<T, R, 16, MODE, 1024>(a, nf, st);
+  else go_wall<T, R, 32, MODE, 1024>(a, nf, st);
+}
+
 template <typename T, int MODE, typename R = double>
 static void sweep(ib_ctx *c, int id_x, SweepArgs<T> a, int axis, int nf, hipStream_t st) {
   // the tuner times plain sweeps; the sweeps with epilogue operands (FINAL,
   // PFINAL) hold more registers per element and keep the library's shapes
   const SweepTune *tu = MODE == SW_PLAIN ? tune_of(c, axis, sizeof(R) == 8) : nullptr;
+  if (axis == 1 && c && (c->prm.flags & IB_FLAG_WALLS_Y)) {  // (ib_line_solve: no context)
+    launch(c, id_x + 1, [&] { dispatch_wall<T, MODE, R>(a, nf, st); });
+    return;
+  }
   if (axis == 0)
     launch(c, id_x, [&] { dispatch_x<T, MODE>(a, nf, st, tu); });
   else
@@ -384,7 +407,14 @@ static ib_status check_params(const ib_grid_params *p) {
       p->precision != IB_PREC_MIXED_STATE64)
     return fail(IB_E_INVALID, "unknown precision %d", p->precision);
   if (p->step0 < 0) return fail(IB_E_INVALID, "step0 must be >= 0");
-  if (p->flags & ~IB_FLAG_NO_ADVECTION) return fail(IB_E_INVALID, "unknown flags 0x%x", p->flags);
+  if (p->flags & ~(IB_FLAG_NO_ADVECTION | IB_FLAG_WALLS_Y))
+    return fail(IB_E_INVALID, "unknown flags 0x%x", p->flags);
+  if (p->flags & IB_FLAG_WALLS_Y) {
+    const int n1 = p->n[1];
+    if (n1 < 32 || n1 > 512 || n1 % 16 != 0 || (n1 > 256 && n1 % 32 != 0))
+      return fail(IB_E_INVALID,
+                  "walls need 32 <= n[1] <= 512, a multiple of 16 (of 32 above 256); got %d", n1);
+  }
   return IB_OK;
 }
 
@@ -562,8 +592,10 @@ static void launch_explicit(ib_ctx *c, bool first) {
   a.inv_rho = 1.0 / c->prm.rho;
   a.first = first;
   a.advect = !(c->prm.flags & IB_FLAG_NO_ADVECTION);
+  a.walls = (c->prm.flags & IB_FLAG_WALLS_Y) ? 1 : 0;
   if constexpr (DIM == 3) {
-    if (c->g.n0 % EX == 0 && c->g.n1 % EY == 0 && c->g.ncell < INT32_MAX) {
+    // (the plane-marching kernel has no wall rows: channels take k_explicit)
+    if (!a.walls && c->g.n0 % EX == 0 && c->g.n1 % EY == 0 && c->g.ncell < INT32_MAX) {
       // one round of resident workgroups (c->resident3, from ib_init) split
       // over the (x, y) column tiles
       const int resident = std::max(1, c->resident3);
@@ -643,6 +675,7 @@ static void enqueue_step(ib_ctx *c) {
   for (int i = 0; i < 3; i++) {
     m.f[i] = m.o[i] = (T *)(i < DIM ? c->delta[i] : nullptr);
     m.u[i] = kState64 ? nullptr : (T *)(i < DIM ? c->buf.u[i] : nullptr);
+    m.bc[i] = i == 1 ? SB_DIRICHLET_FACE : SB_DIRICHLET_CELL;  // used by wall sweeps only
   }
   for (int s = 0; s < DIM; s++) {
     if (s < DIM - 1 || kState64) sweep<T, SW_PLAIN, T>(c, KP_MOM_X_PLAIN, m, order[s], DIM, c->stream);
@@ -669,6 +702,7 @@ static void enqueue_step(ib_ctx *c) {
   q.invc_layer = c->l_psi_invc;  // per-layer -(rho/dt)/c in 2-D batches
   q.f[0] = (T *)c->divn;
   q.o[0] = (T *)c->buf.psi;
+  q.bc[0] = SB_NEUMANN_CELL;  // used by wall sweeps only
   sweep<T, SW_PLAIN>(c, KP_PSI_X_FIRST, q, order[0], 1, c->stream);
   q.inv_c = c->psi_invc;
   q.invc_layer = nullptr;

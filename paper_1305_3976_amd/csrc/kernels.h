@@ -702,6 +702,7 @@ struct ExplicitArgs {
   TileGrid tg;
   double inv_h, inv_h2, dt, mu, inv_rho;
   int first, advect;
+  int walls;  // channel: no-slip walls at y = 0 and y = n1 h (k_explicit only)
   int ez;  // planes per workgroup of the 3-D plane-marching kernel
 };
 
@@ -729,14 +730,28 @@ __global__ void __launch_bounds__(256) k_explicit(ExplicitArgs<T, DIM, V> a) {
       i / TS + (int64_t)a.tg.nt[0] * (j / TS + (int64_t)a.tg.nt[1] * (DIM == 3 ? k / TS : k));
   const bool forced = a.flag[tile] != 0;
   const C dt = (C)((DIM == 2 && a.dt_layer) ? a.dt_layer[k] : a.dt);
+  // channel walls: across y = 0 and y = n1 h a tangential component takes
+  // the no-slip ghost value -u; v lives on the y faces, whose row 0 is the
+  // wall (both walls, periodically) and holds 0, so periodic indexing gives
+  // the wall value there and v is not advanced on it
+  const bool wlo = a.walls && j == 0, whi = a.walls && j + 1 == n1;
 #pragma unroll
   for (int ci = 0; ci < DIM; ci++) {
+    if (wlo && ci == 1) {
+      a.delta[1][idx] = T(0);
+      a.nl[1][idx] = T(0);
+      continue;
+    }
     const V *__restrict__ ui = a.u[ci];
     const C u0 = (C)ui[idx];
     C dv = 0, ad = 0, lap = 0;
 #pragma unroll
     for (int cj = 0; cj < DIM; cj++) {
-      const C up = (C)ui[idx + dp[cj]], um = (C)ui[idx + dm[cj]];
+      C up = (C)ui[idx + dp[cj]], um = (C)ui[idx + dm[cj]];
+      if (cj == 1 && ci != 1) {
+        if (whi) up = -u0;
+        if (wlo) um = -u0;
+      }
       lap += up - C(2) * u0 + um;
       if (!a.advect) continue;
       if (cj == ci) {
@@ -990,6 +1005,10 @@ __global__ void __launch_bounds__(256) k_add_increment(double *u0, double *u1, d
 // the P x P interface system replaced by the scan of the factored form.
 
 enum { SW_PLAIN = 0, SW_FINAL = 1, SW_PFINAL = 3 };
+// Boundary kinds of a channel's y lines: Dirichlet for a cell-centred unknown
+// (ghost -x across the wall), for a face unknown on the wall (element 0, and
+// element N on the opposite wall, are zero), Neumann for a cell-centred one.
+enum { SB_DIRICHLET_CELL = 1, SB_DIRICHLET_FACE = 2, SB_NEUMANN_CELL = 3 };
 
 template <typename T>
 struct SweepArgs {
@@ -1003,6 +1022,7 @@ struct SweepArgs {
   const double *alpha_layer, *invc_layer;  // 2-D batches: per-layer coefficients
   double half_chi_mu;  // PFINAL
   const double *gauge; // PFINAL: per-layer mean of psi removed before use (or null)
+  int32_t bc[3];       // channel y sweeps: boundary kind per field (SB_*)
   Grid g;
   int32_t G;           // threads per line (x kernel: power of two <= 64)
   int32_t dim;
@@ -1362,39 +1382,14 @@ struct Col {
   }
 };
 
-// R: recurrence type (double, or float for the benign momentum systems under
-// the mixed policy).  EVEN: the line length is G * M, so every chunk is full
-// and the per-element guards drop out.
-template <typename T, typename R, int M, int MODE, int LB, int TX, bool EVEN>
-__global__ void __launch_bounds__(LB) k_sweep_sb(SweepArgs<T> a, int axis) {
-  __shared__ R sA[LB], sB[LB];
-  const int tx = threadIdx.x, g = threadIdx.y, G = blockDim.y;
-  const int64_t n0 = a.g.n0, n1 = a.g.n1, ncell = a.g.ncell;
-  const int64_t x0 = (int64_t)blockIdx.x * TX;
-  const int64_t other = blockIdx.y;
-  const int fld = blockIdx.z;
-  const int N = axis == 1 ? (int)n1 : (int)a.g.n2;
-  const int64_t stride = axis == 1 ? n0 : n0 * n1;
-  const int64_t tb = axis == 1 ? x0 + other * n0 * n1 : x0 + other * n0;  // first column
-  const int64_t rem = ncell - tb;                                          // elements to the end
-  const bool live = x0 + tx < n0;
-  const int s = g * M;
-  const int cnt = EVEN ? M : (s >= N ? 0 : (N - s < M ? N - s : M));
-  // 2-D batches sweep y only, so the remaining index is the layer
-  const R al = (R)(a.alpha_layer ? a.alpha_layer[other] : a.alpha);
-  const R ic = (R)(a.invc_layer ? a.invc_layer[other] : a.inv_c);
+// The column solve of one chunk row: forward recurrence over the chunk from
+// zero, the chunk maps of the rows above combined through LDS (sA, sB) and
+// the periodic fixed point closed, then the same backward.  r holds the
+// chunk's right-hand side in and its solution out.
+template <typename R, int M, bool EVEN>
+__device__ __forceinline__ void sb_solve(R (&r)[M], int cnt, R al, R ic, R *sA, R *sB, int g,
+                                         int G, int TX, int tx) {
   const int slot = g * TX + tx;
-  auto col = [&](const auto *base) {
-    using E = std::remove_cv_t<std::remove_pointer_t<decltype(base)>>;
-    return Col<E>(base + tb, rem * (int64_t)sizeof(E), tx, stride, s);
-  };
-
-  R r[M];
-  {
-    const auto cf = col(a.f[fld]);
-#pragma unroll
-    for (int q = 0; q < M; q++) r[q] = (EVEN || q < cnt) ? (R)cf.ld(q) : R(0);
-  }
   R z = 0, A = 1;
 #pragma unroll
   for (int q = 0; q < M; q++)
@@ -1459,6 +1454,41 @@ __global__ void __launch_bounds__(LB) k_sweep_sb(SweepArgs<T> a, int axis) {
         r[q] += cx;
       }
   }
+}
+
+// R: recurrence type (double, or float for the benign momentum systems under
+// the mixed policy).  EVEN: the line length is G * M, so every chunk is full
+// and the per-element guards drop out.
+template <typename T, typename R, int M, int MODE, int LB, int TX, bool EVEN>
+__global__ void __launch_bounds__(LB) k_sweep_sb(SweepArgs<T> a, int axis) {
+  __shared__ R sA[LB], sB[LB];
+  const int tx = threadIdx.x, g = threadIdx.y, G = blockDim.y;
+  const int64_t n0 = a.g.n0, n1 = a.g.n1, ncell = a.g.ncell;
+  const int64_t x0 = (int64_t)blockIdx.x * TX;
+  const int64_t other = blockIdx.y;
+  const int fld = blockIdx.z;
+  const int N = axis == 1 ? (int)n1 : (int)a.g.n2;
+  const int64_t stride = axis == 1 ? n0 : n0 * n1;
+  const int64_t tb = axis == 1 ? x0 + other * n0 * n1 : x0 + other * n0;  // first column
+  const int64_t rem = ncell - tb;                                          // elements to the end
+  const bool live = x0 + tx < n0;
+  const int s = g * M;
+  const int cnt = EVEN ? M : (s >= N ? 0 : (N - s < M ? N - s : M));
+  // 2-D batches sweep y only, so the remaining index is the layer
+  const R al = (R)(a.alpha_layer ? a.alpha_layer[other] : a.alpha);
+  const R ic = (R)(a.invc_layer ? a.invc_layer[other] : a.inv_c);
+  auto col = [&](const auto *base) {
+    using E = std::remove_cv_t<std::remove_pointer_t<decltype(base)>>;
+    return Col<E>(base + tb, rem * (int64_t)sizeof(E), tx, stride, s);
+  };
+
+  R r[M];
+  {
+    const auto cf = col(a.f[fld]);
+#pragma unroll
+    for (int q = 0; q < M; q++) r[q] = (EVEN || q < cnt) ? (R)cf.ld(q) : R(0);
+  }
+  sb_solve<R, M, EVEN>(r, cnt, al, ic, sA, sB, g, G, TX, tx);
   if (!live) return;
   if (MODE == SW_PLAIN) {
     const auto co = col(a.o[fld]);
@@ -1502,6 +1532,99 @@ __global__ void __launch_bounds__(LB) k_sweep_sb(SweepArgs<T> a, int axis) {
         cp.st(q, pp[q] + (double)r[q] - a.half_chi_mu * ((double)pdn[q] + (double)pdp[q]));
         cdp.st(q, pdn[q]);
       }
+  }
+}
+
+// Channel y lines.  A bounded line of n1 elements is solved as the periodic
+// line of 2 n1 that mirrors it (method of images): Dirichlet for a
+// cell-centred unknown is the odd extension about the wall between cells,
+// Neumann the even one, and Dirichlet for a face unknown on the wall the odd
+// extension about that face (element 0 and element n1 then vanish).  The
+// workgroup holds the virtual line: chunk rows 0 .. G/2-1 read the line,
+// rows G/2 .. G-1 read it backwards with the sign of the extension, and only
+// the first half stores.  32 columns per row; n1 is a multiple of M, so no
+// chunk straddles the mirror.  blockIdx.y = z index (3-D) or layer (2-D).
+template <typename T, typename R, int M, int MODE, int LB>
+__global__ void __launch_bounds__(LB) k_sweep_wall(SweepArgs<T> a) {
+  constexpr int TX = 32;
+  __shared__ R sA[LB], sB[LB];
+  const int tx = threadIdx.x, g = threadIdx.y, G = blockDim.y;
+  const int64_t n0 = a.g.n0, n1 = a.g.n1, ncell = a.g.ncell;
+  const int64_t x0 = (int64_t)blockIdx.x * TX;
+  const int64_t other = blockIdx.y;
+  const int fld = blockIdx.z;
+  const int N = (int)n1;
+  const int64_t tb = x0 + other * n0 * n1;  // first column of the block
+  const int64_t rem = ncell - tb;
+  const bool live = x0 + tx < n0;
+  const int s = g * M;  // chunk start on the virtual line of 2N
+  const bool mirror = s >= N;
+  const int bc = a.bc[fld];
+  const R al = (R)(a.alpha_layer ? a.alpha_layer[other] : a.alpha);
+  const R ic = (R)(a.invc_layer ? a.invc_layer[other] : a.inv_c);
+  // first real element of the chunk's span (backwards for mirrored chunks):
+  // a mirrored cell chunk covers 2N-1-s .. 2N-s-M, a mirrored face chunk
+  // 2N-s .. 2N-s-M+1 (its element at s = N is the far wall, zero)
+  const int face = bc == SB_DIRICHLET_FACE;
+  const int r0 = !mirror ? s : (face ? 2 * N - s - M + 1 : 2 * N - s - M);
+  auto col = [&](const auto *base) {
+    using E = std::remove_cv_t<std::remove_pointer_t<decltype(base)>>;
+    return Col<E>(base + tb, rem * (int64_t)sizeof(E), tx, n0, r0);
+  };
+  R r[M];
+  {
+    const auto cf = col(a.f[fld]);
+    if (!mirror) {
+#pragma unroll
+      for (int q = 0; q < M; q++) r[q] = (R)cf.ld(q);
+    } else {
+      const R sg = bc == SB_NEUMANN_CELL ? R(1) : R(-1);
+#pragma unroll
+      for (int q = 0; q < M; q++) {
+        const R v = (R)cf.ld(M - 1 - q);
+        r[q] = (face && q == 0 && s == N) ? R(0) : sg * v;
+      }
+    }
+  }
+  sb_solve<R, M, true>(r, M, al, ic, sA, sB, g, G, TX, tx);
+  if (!live || mirror) return;
+  const bool wall0 = face && s == 0;  // element 0 is the wall face
+  if (MODE == SW_PLAIN) {
+    const auto co = col(a.o[fld]);
+#pragma unroll
+    for (int q = 0; q < M; q++) co.st(q, (q == 0 && wall0) ? T(0) : (T)r[q]);
+  } else if constexpr (MODE == SW_FINAL) {
+    const auto cu = col(a.u[fld]);
+    T pu[M];
+#pragma unroll
+    for (int q = 0; q < M; q++) pu[q] = cu.ld(q);
+#pragma unroll
+    for (int q = 0; q < M; q++)
+      if (!(q == 0 && wall0)) cu.st(q, (T)((R)pu[q] + r[q]));
+  } else if constexpr (MODE == SW_PFINAL) {
+    if (a.gauge) {
+      const R gz = (R)a.gauge[a.dim == 2 ? other : 0];
+#pragma unroll
+      for (int q = 0; q < M; q++) r[q] -= gz;
+    }
+    const auto cf = col(a.f[fld]);
+    const auto cdn = col(a.divn);
+    const auto cdp = col(a.divp);
+    const auto cp = col(a.p);
+    T pdn[M], pdp[M];
+    double pp[M];
+#pragma unroll
+    for (int q = 0; q < M; q++) {
+      pdn[q] = cdn.ld(q);
+      pdp[q] = cdp.ld(q);
+      pp[q] = cp.ld(q);
+    }
+#pragma unroll
+    for (int q = 0; q < M; q++) {
+      cf.st(q, (T)r[q]);
+      cp.st(q, pp[q] + (double)r[q] - a.half_chi_mu * ((double)pdn[q] + (double)pdp[q]));
+      cdp.st(q, pdn[q]);
+    }
   }
 }
 

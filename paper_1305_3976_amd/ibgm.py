@@ -22,6 +22,7 @@ IB_OK, IB_E_INVALID, IB_E_UNSUPPORTED, IB_E_DEVICE, IB_E_NONFINITE, IB_E_STATE =
 IB_F64, IB_F32 = 0, 1
 IB_PREC_FP64, IB_PREC_MIXED, IB_PREC_MIXED_STATE64 = 0, 1, 2
 IB_FLAG_NO_ADVECTION = 1
+IB_FLAG_WALLS_Y = 2
 IB_GRAPH_BRANCHES = 1
 
 _vp = ctypes.c_void_p
@@ -170,6 +171,7 @@ class Config:
     rotate_split: bool = True
     no_advection: bool = False
     layer_dt: tuple = None  # 2-D batches: time step of each layer
+    walls_y: bool = False   # channel: no-slip walls at y = 0 and y = n[1] h
 
     def params(self, step0: int = 0) -> GridParams:
         P = GridParams()
@@ -182,7 +184,8 @@ class Config:
         P.h, P.rho, P.mu, P.dt, P.chi = self.h, self.rho, self.mu, self.dt, self.chi
         P.precision = self.precision
         P.rotate_split = 1 if self.rotate_split else 0
-        P.flags = IB_FLAG_NO_ADVECTION if self.no_advection else 0
+        P.flags = ((IB_FLAG_NO_ADVECTION if self.no_advection else 0)
+                   | (IB_FLAG_WALLS_Y if self.walls_y else 0))
         P.step0 = step0
         if self.layer_dt is not None:
             self._ldt = np.ascontiguousarray(self.layer_dt, dtype=np.float64)

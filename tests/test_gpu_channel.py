@@ -1,0 +1,129 @@
+"""The periodic channel (no-slip walls at y = 0 and y = n1 h) on the GPU
+stepper, through the C ABI, against the oracle: a membrane in a 2-D channel
+and a shell in a 3-D channel, per field (FP64 1e-12, with the conditioning
+bar for p; mixed policies 1e-5); the exact decay of a shear mode between the
+walls; v stays zero on the wall faces; invalid wall grids are rejected."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1305_3976_amd import inputs
+from helpers import field_errors, gpu_sim, oracle_sim, psi_vs_p
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+MIXED_TOL = 1e-5
+
+
+def p_bar(n):
+    return max(FP64_TOL, (1 + 4 * n * n) * 2.0 ** -52)
+
+
+def channel_2d(steps):
+    n = (64, 48, 1)
+    S = inputs.ellipse(160, 0.15, 0.1, 1.0, center=(0.5, 0.375))
+    w = inputs.Workload("channel2d", 2, n, 1.0, 0.05, 1e-3, steps, S,
+                        inputs.channel_velocity(2, n, seed=7, amp=0.2))
+    return w
+
+
+def channel_3d(steps):
+    n = (64, 32, 48)
+    S = inputs.ellipsoid_shell(800, axes=(0.15, 0.1, 0.12), center=(0.5, 0.25, 0.375))
+    return inputs.Workload("channel3d", 3, n, 1.0, 0.05, 1e-3, steps, S,
+                           inputs.channel_velocity(3, n, seed=8, amp=0.2))
+
+
+def check(errs, precision, n):
+    for k, e in errs.items():
+        if precision == 0:
+            lim = p_bar(n) if k in ("p", "psi") else FP64_TOL
+        else:
+            lim = MIXED_TOL
+        assert e <= lim, (k, e, lim)
+
+
+@pytest.fixture(scope="module")
+def oracle_2d():
+    w = channel_2d(100)
+    return w, oracle_sim(w, walls_y=True).advance(w.steps)
+
+
+@pytest.mark.parametrize("precision", [0, 1, 2])
+def test_channel_2d_parity(oracle_2d, precision):
+    w, o = oracle_2d
+    g = gpu_sim(w, precision, walls_y=True)
+    g.step(w.steps)
+    assert g.sync() == w.steps
+    st = g.state()
+    errs = field_errors(st, o, 2)
+    errs["psi"] = psi_vs_p(st["psi"], o.psi, o.p)
+    print("channel 2d precision", precision, errs)
+    check(errs, precision, max(w.n))
+    assert np.abs(st["u"][1][:, 0, :]).max() == 0.0      # v on the walls
+    g.close()
+
+
+@pytest.fixture(scope="module")
+def oracle_3d():
+    w = channel_3d(20)
+    return w, oracle_sim(w, walls_y=True).advance(w.steps)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_channel_3d_parity(oracle_3d, precision):
+    w, o = oracle_3d
+    g = gpu_sim(w, precision, walls_y=True)
+    g.step(w.steps)
+    assert g.sync() == w.steps
+    st = g.state()
+    errs = field_errors(st, o, 3)
+    errs["psi"] = psi_vs_p(st["psi"], o.psi, o.p)
+    print("channel 3d precision", precision, errs)
+    check(errs, precision, max(w.n))
+    assert np.abs(st["u"][1][:, 0, :]).max() == 0.0
+    g.close()
+
+
+@pytest.mark.parametrize("dim,comp,k", [(2, 0, 1), (2, 0, 5), (3, 2, 2)])
+def test_shear_mode_decay(dim, comp, k):
+    """u_c(y) = sin(k pi (j + 1/2)/n1): the discrete step multiplies it by
+    exactly (1 + nu lambda)/(1 - nu lambda), lambda = -(4/h^2) sin^2(k pi/(2 n1))."""
+    n = (64, 32, 32 if dim == 3 else 1)
+    h = 1.0 / n[0]
+    mu, dt, steps = 0.05, 2e-3, 10
+    y = (np.arange(n[1]) + 0.5) / n[1]
+    shp = (n[2], n[1], n[0])
+    u = [np.zeros(shp) for _ in range(dim)]
+    u[comp] = np.broadcast_to(np.sin(k * math.pi * y)[None, :, None], shp).copy()
+    X = np.full((dim, 1), 0.5)
+    S = inputs.Structure(X, (np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0), np.zeros(0)),
+                         np.ones(1))
+    w = inputs.Workload("shear", dim, n, 1.0, mu, dt, steps, S, u)
+    g = gpu_sim(w, 0, walls_y=True)
+    g.step(steps)
+    g.sync()
+    st = g.state()
+    lam = -(4 / h ** 2) * math.sin(k * math.pi / (2 * n[1])) ** 2
+    nu = mu * dt / 2
+    fac = ((1 + nu * lam) / (1 - nu * lam)) ** steps
+    assert np.abs(st["u"][comp] - fac * u[comp]).max() < 1e-12
+    for c in range(dim):
+        if c != comp:
+            assert np.abs(st["u"][c]).max() < 1e-12
+    g.close()
+
+
+def test_wall_grids_are_checked():
+    from paper_1305_3976_amd import ibgm
+    X = np.array([[0.5], [0.5]])
+    S = inputs.Structure(X, (np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0), np.zeros(0)),
+                         np.ones(1))
+    for n1 in (16, 40, 528):
+        n = (64, n1, 1)
+        cfg = ibgm.Config(2, n, 1.0 / 64, mu=0.05, walls_y=True)
+        with pytest.raises(ibgm.IBError):
+            ibgm.Simulation(cfg, inputs.zero_velocity(2, n), S)
