@@ -108,6 +108,10 @@ typedef struct {
   const double *layer_dt; /* HOST, 2-D batches: time step of each of the n[2]
                            layers (each > 0), or NULL for dt everywhere;
                            copied at ib_init */
+  double body_force[3]; /* uniform force density g added to the fluid force f
+                           of the momentum equation (Sec. "Governing
+                           Equations"), e.g. the mean pressure gradient that
+                           drives a channel; zeros for none; finite */
 } ib_grid_params;
 
 /* Device state, caller-owned, borrowed by the context until ib_destroy.
@@ -141,6 +145,13 @@ typedef struct {
   const int32_t *layer;      /* host [n_points], 2-D batches: the layer (in
                                 [0, n[2])) each point lives in, or NULL for 0;
                                 links must not join points of different layers */
+  /* Tether points (Sec. "Introduction to the GM method": complex solid
+   * boundaries as immersed points attached to fixed tether points): point k
+   * feels kappa_t[k] (Y_k - X_k) towards its fixed target Y_k (nearest
+   * periodic image), added to its link force in Step 2a.  Both NULL: no
+   * tethers. */
+  const double *tether_kappa;  /* host [n_points], >= 0 (0: point not tethered) */
+  const double *tether_target; /* host FP64 [dim][n_points], finite */
 } ib_structure;
 
 /* Bytes of device workspace a context with these parameters needs. */
@@ -196,8 +207,9 @@ ib_status ib_step_force(ib_ctx *ctx, void *const f_out[3]);
 ib_status ib_interp(ib_ctx *ctx, const double *X, int64_t npts,
                     void *const u_in[3], double *U);
 
-/* Step 2a on given buffers: F = link force of the context's structure at
- * positions X (FP64 device [dim][n_points] -> [dim][n_points]). */
+/* Step 2a on given buffers: F = link force of the context's structure (plus
+ * its tether pulls) at positions X (FP64 device [dim][n_points] ->
+ * [dim][n_points]). */
 ib_status ib_force(ib_ctx *ctx, const double *X, double *F);
 
 /* eq:TriDiagX, batched and in place: every line along `axis` (0 = x) of the

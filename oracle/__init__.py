@@ -43,7 +43,8 @@ class Params(ctypes.Structure):
                 ("h", ctypes.c_double), ("rho", ctypes.c_double),
                 ("mu", ctypes.c_double), ("dt", ctypes.c_double),
                 ("chi", ctypes.c_double), ("rotate", ctypes.c_int32),
-                ("no_advection", ctypes.c_int32), ("walls_y", ctypes.c_int32)]
+                ("no_advection", ctypes.c_int32), ("walls_y", ctypes.c_int32),
+                ("body_force", ctypes.c_double * 3)]
 
 
 class _Sim(ctypes.Structure):
@@ -52,7 +53,7 @@ class _Sim(ctypes.Structure):
                 ("psi", _dp), ("np", ctypes.c_int64), ("X", _dp),
                 ("U_prev", _dp), ("nlinks", ctypes.c_int64),
                 ("link_a", _ip), ("link_b", _ip), ("link_k", _dp),
-                ("link_l0", _dp), ("w", _dp)]
+                ("link_l0", _dp), ("w", _dp), ("tether_k", _dp), ("tether_Y", _dp)]
 
 
 _lib = None
@@ -75,6 +76,7 @@ def lib():
         L.ibo_link_force.argtypes = [ctypes.c_int32, ctypes.c_int64, _dp, _dp,
                                      ctypes.c_int64, _ip, _ip, _dp, _dp, _dp]
         L.ibo_advection.argtypes = [ctypes.POINTER(Params), _dp * 3, _dp * 3]
+        L.ibo_tether_force.argtypes = [ctypes.c_int32, ctypes.c_int64, _dp, _dp, _dp, _dp, _dp]
         L.ibo_vel_laplacian.argtypes = [ctypes.POINTER(Params), ctypes.c_int32, _dp, _dp]
         L.ibo_line_solve_bc.argtypes = [_dp, _ip, ctypes.c_int32, ctypes.c_double,
                                         ctypes.c_double, ctypes.c_int32]
@@ -100,7 +102,7 @@ def _pi(a: np.ndarray):
 
 
 def make_params(dim, n, h, rho=1.0, mu=0.0, dt=1e-3, chi=0.6, rotate=True,
-                no_advection=False, walls_y=False) -> Params:
+                no_advection=False, walls_y=False, body_force=(0.0, 0.0, 0.0)) -> Params:
     nn = list(n) + [1] * (3 - len(n))
     P = Params()
     P.dim = dim
@@ -110,6 +112,8 @@ def make_params(dim, n, h, rho=1.0, mu=0.0, dt=1e-3, chi=0.6, rotate=True,
     P.rotate = 1 if rotate else 0
     P.no_advection = 1 if no_advection else 0
     P.walls_y = 1 if walls_y else 0
+    for a in range(3):
+        P.body_force[a] = float(body_force[a]) if a < len(body_force) else 0.0
     return P
 
 
@@ -206,6 +210,18 @@ def link_force(X, links, period=None):
     return F
 
 
+def tether_force(X, kappa, Y, period=None):
+    """Tether pulls kappa_k (Y_k - X_k) alone (nearest image if period)."""
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    kappa = np.ascontiguousarray(kappa, dtype=np.float64)
+    Y = np.ascontiguousarray(Y, dtype=np.float64)
+    per = None if period is None else np.ascontiguousarray(period, dtype=np.float64)
+    F = np.zeros_like(X)
+    lib().ibo_tether_force(X.shape[0], X.shape[1], _p(X), None if per is None else _p(per),
+                           _p(kappa), _p(Y), _p(F))
+    return F
+
+
 def advection(P: Params, u):
     u = [np.ascontiguousarray(c, dtype=np.float64) for c in u]
     N = [np.zeros(grid_shape(P)) for _ in range(P.dim)]
@@ -261,6 +277,7 @@ class Sim:
     nl_prev: list = None
     U_prev: np.ndarray = None
     step: int = 0
+    tether: tuple = None  # (kappa [np], target [dim][np]) or None
     _keep: list = field(default_factory=list, repr=False)
 
     def __post_init__(self):
@@ -289,6 +306,9 @@ class Sim:
                       np.ascontiguousarray(k, dtype=np.float64),
                       np.ascontiguousarray(l0, dtype=np.float64))
         self.w = np.ascontiguousarray(self.w, dtype=np.float64)
+        if self.tether is not None:
+            self.tether = (np.ascontiguousarray(self.tether[0], dtype=np.float64),
+                           np.ascontiguousarray(self.tether[1], dtype=np.float64))
 
     def _struct(self) -> _Sim:
         s = _Sim()
@@ -306,6 +326,8 @@ class Sim:
         s.link_a, s.link_b = _pi(a), _pi(b)
         s.link_k, s.link_l0 = _p(k), _p(l0)
         s.w = _p(self.w)
+        if self.tether is not None:
+            s.tether_k, s.tether_Y = _p(self.tether[0]), _p(self.tether[1])
         return s
 
     def advance(self, nsteps: int = 1):

@@ -366,6 +366,19 @@ void ibo_link_force(int32_t dim, int64_t np, const double *X, const double *peri
   }
 }
 
+/* Tether points (the paper's route to complex solid boundaries, Sec.
+ * "Introduction to the GM method"): a point tied to a fixed target Y by a
+ * spring of stiffness kappa feels kappa (Y - X).  Added to F. */
+void ibo_tether_force(int32_t dim, int64_t np, const double *X, const double *period,
+                      const double *kappa, const double *Y, double *F) {
+  for (int64_t k = 0; k < np; k++)
+    for (int32_t c = 0; c < dim; c++) {
+      double d = Y[c * np + k] - X[c * np + k];
+      if (period) d -= period[c] * round(d / period[c]);
+      F[c * np + k] += kappa[k] * d;
+    }
+}
+
 /* ------------------------------------------------ difference operators -- */
 
 /* Skew-symmetric advection, Sec. "IB-GM Algorithm" (Morinishi et al. 1998,
@@ -562,6 +575,7 @@ int ibo_step(ibo_sim *s) {
   const double box[3] = {P->n[0] * P->h, P->n[1] * P->h, P->n[2] * P->h};
   ibo_link_force(d, np, Xh, box, s->nlinks, s->link_a, s->link_b, s->link_k,
                  s->link_l0, F);
+  if (s->tether_k) ibo_tether_force(d, np, Xh, box, s->tether_k, s->tether_Y, F);
   /* Step 2b: spread it to the grid. */
   ibo_spread(P, Xh, F, s->w, np, f);
 
@@ -580,7 +594,7 @@ int ibo_step(ibo_sim *s) {
     ibo_vel_laplacian(P, c, un[c], lap);
     for (int64_t i = 0; i < nc; i++) {
       double Nh = (n == 0) ? Nn[c][i] : 1.5 * Nn[c][i] - 0.5 * s->nl_prev[c][i];
-      us[c][i] = un[c][i] + dt * (-Nh + (mu * lap[i] - g[c][i] + f[c][i]) / rho);
+      us[c][i] = un[c][i] + dt * (-Nh + (mu * lap[i] - g[c][i] + f[c][i] + P->body_force[c]) / rho);
     }
   }
   /* channel: v stays zero on the wall faces (row j = 0 of every layer) */

@@ -34,6 +34,7 @@ typedef struct {
   int32_t no_advection; /* 1: drop the advection term (Stokes flow) */
   int32_t walls_y;    /* 1: no-slip walls at y = 0 and y = n1 h (a channel,
                          periodic in x and z); 0: periodic in y */
+  double body_force[3]; /* uniform force density added to f (0: none) */
 } ibo_params;
 
 typedef struct {
@@ -50,6 +51,8 @@ typedef struct {
   const int32_t *link_a, *link_b;
   const double *link_k, *link_l0;
   const double *w;            /* per-point quadrature weight for spreading */
+  const double *tether_k;     /* [np] tether stiffness (0: free), or NULL */
+  const double *tether_Y;     /* [dim][np] fixed tether targets, or NULL */
 } ibo_sim;
 
 /* eq:discretedelta, the 4-point kernel phi(r), written with its two
@@ -85,6 +88,11 @@ void ibo_spread(const ibo_params *prm, const double *X, const double *F,
 void ibo_link_force(int32_t dim, int64_t np, const double *X, const double *period,
                     int64_t nlinks, const int32_t *la, const int32_t *lb,
                     const double *lk, const double *ll0, double *F);
+
+/* Tether points: F_k += kappa_k (Y_k - X_k) towards the fixed target Y_k,
+ * nearest periodic image in a box of lengths period[] (NULL: no images). */
+void ibo_tether_force(int32_t dim, int64_t np, const double *X, const double *period,
+                      const double *kappa, const double *Y, double *F);
 
 /* Skew-symmetric advection N(u) = 1/2 u.grad u + 1/2 div(uu) on the MAC
  * grid with the second-order staggered stencils of Morinishi et al. */

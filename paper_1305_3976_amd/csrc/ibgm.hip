@@ -99,6 +99,7 @@ struct ib_ctx {
   // structure (library allocation)
   int32_t *ptr, *nbr;
   double *kap, *l0, *w;
+  double *tk, *ty;  // tethers: stiffness [np] and target [dim][np] (null: none)
   int64_t nlinks;
   // factored coefficients
   double mom_alpha, mom_invc, psi_alpha, psi_invc;
@@ -407,6 +408,8 @@ static ib_status check_params(const ib_grid_params *p) {
       p->precision != IB_PREC_MIXED_STATE64)
     return fail(IB_E_INVALID, "unknown precision %d", p->precision);
   if (p->step0 < 0) return fail(IB_E_INVALID, "step0 must be >= 0");
+  for (int a = 0; a < 3; a++)
+    if (!std::isfinite(p->body_force[a])) return fail(IB_E_INVALID, "body_force must be finite");
   if (p->flags & ~(IB_FLAG_NO_ADVECTION | IB_FLAG_WALLS_Y))
     return fail(IB_E_INVALID, "unknown flags 0x%x", p->flags);
   if (p->flags & IB_FLAG_WALLS_Y) {
@@ -503,6 +506,8 @@ static void launch_force(ib_ctx *c, const double *Xh, double *F, bool commit) {
   a.Xn1 = commit ? c->Xn1 : nullptr;
   a.X = c->buf.X;
   a.np = c->np;
+  a.tk = c->tk;
+  a.ty = c->ty;
   for (int i = 0; i < DIM; i++) a.box[i] = c->prm.n[i] * c->prm.h;
   launch(c, KP_FORCE, [&] {
     hipLaunchKernelGGL((k_force<DIM>), dim3((unsigned)((c->np + 255) / 256)), dim3(256), 0,
@@ -593,6 +598,7 @@ static void launch_explicit(ib_ctx *c, bool first) {
   a.first = first;
   a.advect = !(c->prm.flags & IB_FLAG_NO_ADVECTION);
   a.walls = (c->prm.flags & IB_FLAG_WALLS_Y) ? 1 : 0;
+  for (int i = 0; i < 3; i++) a.g_body[i] = i < DIM ? c->prm.body_force[i] : 0.0;
   if constexpr (DIM == 3) {
     // (the plane-marching kernel has no wall rows: channels take k_explicit)
     if (!a.walls && c->g.n0 % EX == 0 && c->g.n1 % EY == 0 && c->g.ncell < INT32_MAX) {
@@ -759,6 +765,16 @@ extern "C" ib_status ib_init(ib_ctx **out, const ib_grid_params *prm, const ib_b
   if (!st->w) return fail(IB_E_INVALID, "null spreading weights");
   for (int64_t i = 0; i < np; i++)
     if (!std::isfinite(st->w[i])) return fail(IB_E_INVALID, "non-finite weight at point %lld", (long long)i);
+  if (!st->tether_kappa != !st->tether_target)
+    return fail(IB_E_INVALID, "tether stiffness and targets come together (both or neither)");
+  if (st->tether_kappa) {
+    for (int64_t i = 0; i < np; i++)
+      if (!(std::isfinite(st->tether_kappa[i]) && st->tether_kappa[i] >= 0))
+        return fail(IB_E_INVALID, "tether stiffness at point %lld must be finite and >= 0", (long long)i);
+    for (int64_t i = 0; i < (int64_t)d * np; i++)
+      if (!std::isfinite(st->tether_target[i]))
+        return fail(IB_E_INVALID, "non-finite tether target (entry %lld)", (long long)i);
+  }
   if (st->layer) {
     if (d != 2) return fail(IB_E_INVALID, "point layers are for 2-D batches only");
     for (int64_t i = 0; i < np; i++)
@@ -882,6 +898,14 @@ extern "C" ib_status ib_init(ib_ctx **out, const ib_grid_params *prm, const ib_b
       hipMalloc(&c->l0, sizeof(double) * l0.size()) != hipSuccess ||
       hipMalloc(&c->w, sizeof(double) * np) != hipSuccess)
     return bail(fail(IB_E_DEVICE, "hipMalloc of the link table failed"));
+  if (st->tether_kappa) {
+    if (hipMalloc(&c->tk, sizeof(double) * np) != hipSuccess ||
+        hipMalloc(&c->ty, sizeof(double) * d * np) != hipSuccess)
+      return bail(fail(IB_E_DEVICE, "hipMalloc of the tether table failed"));
+    if (hipMemcpy(c->tk, st->tether_kappa, sizeof(double) * np, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c->ty, st->tether_target, sizeof(double) * d * np, hipMemcpyHostToDevice) != hipSuccess)
+      return bail(fail(IB_E_DEVICE, "upload of the tether table failed"));
+  }
   if (layered) {
     const size_t nl = (size_t)prm->n[2];
     std::vector<int> lay(np, 0);
@@ -1087,6 +1111,8 @@ extern "C" ib_status ib_destroy(ib_ctx *c) {
   if (c->kap) (void)hipFree(c->kap);
   if (c->l0) (void)hipFree(c->l0);
   if (c->w) (void)hipFree(c->w);
+  if (c->tk) (void)hipFree(c->tk);
+  if (c->ty) (void)hipFree(c->ty);
   for (void *q : {(void *)c->p_layer, (void *)c->l_dt, (void *)c->l_mom_alpha,
                   (void *)c->l_mom_invc, (void *)c->l_psi_invc})
     if (q) (void)hipFree(q);

@@ -237,7 +237,8 @@ __global__ void __launch_bounds__(256) k_interp(InterpArgs<T, DIM> a) {
 // ----------------------------------------------------- Lagrangian: Step 2a --
 
 // One thread per point: gather the link forces at X^{n+1/2} over the point's
-// incident links (CSR by point), F_k = sum kappa (X_l - X_k)(1 - l0/|X_l - X_k|).
+// incident links (CSR by point), F_k = sum kappa (X_l - X_k)(1 - l0/|X_l - X_k|),
+// plus a tethered point's pull kappa_t (Y_k - X_k) towards its fixed target.
 // X_l - X_k is the nearest periodic image (the box is periodic and a fiber
 // may close through its periodic copy, as the axial fibers of the cylinder
 // of Sec. "Cylindrical Shell in 3D" do).  When Xn1 != null also commit
@@ -252,6 +253,7 @@ struct ForceArgs {
   double *X;
   int64_t np;
   double box[DIM];  // periodic box length per axis
+  const double *tk, *ty;  // tethers: stiffness [np], target [DIM][np] (null: none)
 };
 
 template <int DIM>
@@ -276,6 +278,14 @@ __global__ void __launch_bounds__(256) k_force(ForceArgs<DIM> a) {
     const double r0 = a.l0[e];
     if (r0 != 0.0) t *= 1.0 - r0 / sqrt(len2);
     for (int c = 0; c < DIM; c++) f[c] += t * d[c];
+  }
+  if (a.tk) {  // tether: kappa_t (Y_k - X_k), nearest image
+    const double t = a.tk[k];
+    for (int c = 0; c < DIM; c++) {
+      double d = a.ty[c * a.np + k] - xk[c];
+      d -= a.box[c] * round(d / a.box[c]);
+      f[c] += t * d;
+    }
   }
   for (int c = 0; c < DIM; c++) a.F[c * a.np + k] = f[c];
   if (a.Xn1)
@@ -703,6 +713,7 @@ struct ExplicitArgs {
   double inv_h, inv_h2, dt, mu, inv_rho;
   int first, advect;
   int walls;  // channel: no-slip walls at y = 0 and y = n1 h (k_explicit only)
+  double g_body[3];  // uniform body force density added to f
   int ez;  // planes per workgroup of the 3-D plane-marching kernel
 };
 
@@ -770,7 +781,7 @@ __global__ void __launch_bounds__(256) k_explicit(ExplicitArgs<T, DIM, V> a) {
     const double psm = a.p[idx + dm[ci]] + (double)a.psi[idx + dm[ci]];
     const C gp = (C)((ps0 - psm) * a.inv_h);
     const C Nh = a.first ? N : C(1.5) * N - C(0.5) * (C)a.nl[ci][idx];
-    const C fc = forced ? (C)a.f[ci][idx] : C(0);
+    const C fc = (forced ? (C)a.f[ci][idx] : C(0)) + (C)a.g_body[ci];
     const C d = dt * (-Nh + ((C)a.mu * lap * (C)a.inv_h2 - gp + fc) * (C)a.inv_rho);
     a.delta[ci][idx] = (T)d;
     a.nl[ci][idx] = (T)N;
@@ -862,7 +873,7 @@ __global__ void __launch_bounds__(ENT) k_explicit3(ExplicitArgs<T, 3, V> a) {
 #pragma unroll
     for (int ci = 0; ci < 3; ci++) {
       nl_out[ci] = a.first ? C(0) : (C)(a.nl[ci] + kp)[cell];
-      f_out[ci] = forced ? (C)(a.f[ci] + kp)[cell] : C(0);
+      f_out[ci] = (forced ? (C)(a.f[ci] + kp)[cell] : C(0)) + (C)a.g_body[ci];
     }
   };
   cell_terms(k0, nlp, fc);

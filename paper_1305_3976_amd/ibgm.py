@@ -34,7 +34,8 @@ class GridParams(ctypes.Structure):
                 ("rho", ctypes.c_double), ("mu", ctypes.c_double), ("dt", ctypes.c_double),
                 ("chi", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("rotate_split", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("step0", ctypes.c_int64), ("layer_dt", _dp)]
+                ("step0", ctypes.c_int64), ("layer_dt", _dp),
+                ("body_force", ctypes.c_double * 3)]
 
 
 class Buffers(ctypes.Structure):
@@ -46,7 +47,8 @@ class Buffers(ctypes.Structure):
 class Structure(ctypes.Structure):
     _fields_ = [("n_links", ctypes.c_int64), ("a", ctypes.POINTER(ctypes.c_int32)),
                 ("b", ctypes.POINTER(ctypes.c_int32)), ("kappa", _dp), ("l0", _dp),
-                ("w", _dp), ("layer", ctypes.POINTER(ctypes.c_int32))]
+                ("w", _dp), ("layer", ctypes.POINTER(ctypes.c_int32)),
+                ("tether_kappa", _dp), ("tether_target", _dp)]
 
 
 class IBError(RuntimeError):
@@ -172,6 +174,7 @@ class Config:
     no_advection: bool = False
     layer_dt: tuple = None  # 2-D batches: time step of each layer
     walls_y: bool = False   # channel: no-slip walls at y = 0 and y = n[1] h
+    body_force: tuple = (0.0, 0.0, 0.0)  # uniform force density added to f
 
     def params(self, step0: int = 0) -> GridParams:
         P = GridParams()
@@ -187,6 +190,8 @@ class Config:
         P.flags = ((IB_FLAG_NO_ADVECTION if self.no_advection else 0)
                    | (IB_FLAG_WALLS_Y if self.walls_y else 0))
         P.step0 = step0
+        for a in range(3):
+            P.body_force[a] = float(self.body_force[a]) if a < len(self.body_force) else 0.0
         if self.layer_dt is not None:
             self._ldt = np.ascontiguousarray(self.layer_dt, dtype=np.float64)
             P.layer_dt = self._ldt.ctypes.data_as(_dp)
@@ -267,6 +272,12 @@ class Simulation:
         S.w = self._host[4].ctypes.data_as(_dp)
         if len(self._host) > 5:
             S.layer = self._host[5].ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        tether = getattr(structure, "tether", None)
+        if tether is not None:
+            self._tether = (np.ascontiguousarray(tether[0], dtype=np.float64),
+                            np.ascontiguousarray(tether[1], dtype=np.float64))
+            S.tether_kappa = self._tether[0].ctypes.data_as(_dp)
+            S.tether_target = self._tether[1].ctypes.data_as(_dp)
         self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
         ctx = _vp()
         check(lib.ib_init(ctypes.byref(ctx), ctypes.byref(P), ctypes.byref(B), ctypes.byref(S),

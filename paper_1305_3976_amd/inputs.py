@@ -26,10 +26,13 @@ class Structure:
             pulls a and b together with kappa (X_b - X_a)(1 - l0/|X_b - X_a|)
     w       (np,) float64 spreading weight of each point (h_s for a fiber
             force density, 1 for a total nodal force)
+    tether  optional (kappa, Y): point k is pulled by kappa[k] (Y[:, k] - X_k)
+            towards a fixed target (tether points)
     """
     X: np.ndarray
     links: tuple
     w: np.ndarray
+    tether: tuple = None  # (kappa [np], fixed target [dim][np]) or None
 
     @property
     def np(self) -> int:
@@ -62,6 +65,15 @@ def ellipse(npts: int, r1: float, r2: float, sigma: float, L: float = 0.0,
                   center[1] + r2 * np.sin(2 * np.pi * s)])
     w = np.full(npts, 1.0 / npts)
     return Structure(X, closed_fiber_links(npts, sigma, L), w)
+
+
+def tethered_ring(npts: int, radius: float, center, sigma: float, kappa_t: float) -> Structure:
+    """A rigid-ish obstacle: a closed circular fiber (stiffness sigma, w = h_s)
+    whose points are tied to their initial positions by tethers of stiffness
+    kappa_t (force density per unit displacement)."""
+    S = ellipse(npts, radius, radius, sigma, center=center)
+    S.tether = (np.full(npts, float(kappa_t)), S.X.copy())
+    return S
 
 
 def thick_ellipse(ns: int, nr: int, r1: float, r2: float, gamma: float,

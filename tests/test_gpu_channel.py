@@ -127,3 +127,76 @@ def test_wall_grids_are_checked():
         cfg = ibgm.Config(2, n, 1.0 / 64, mu=0.05, walls_y=True)
         with pytest.raises(ibgm.IBError):
             ibgm.Simulation(cfg, inputs.zero_velocity(2, n), S)
+
+
+@pytest.mark.parametrize("dim,precision", [(2, 0), (2, 1), (3, 0)])
+def test_poiseuille_steady_state(dim, precision):
+    """Body force g along x between the walls from rest: the discrete steady
+    state u_j = g/(2 mu) (y_j (L - y_j) + h^2/4) (exact for the scheme)."""
+    n = (64, 32, 16 if dim == 3 else 1)
+    h = 1.0 / 64
+    mu, g, dt = 1.0, 2.0, 1e-3
+    X = np.full((dim, 1), 0.5)
+    S = inputs.Structure(X, (np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0), np.zeros(0)),
+                         np.zeros(1))
+    w = inputs.Workload("poiseuille", dim, n, 1.0, mu, dt, 2500, S, inputs.zero_velocity(dim, n))
+    sim = gpu_sim(w, precision, walls_y=True, body_force=(g, 0.0, 0.0))
+    sim.step(w.steps)
+    sim.sync()
+    st = sim.state()
+    y = (np.arange(n[1]) + 0.5) * h
+    L = n[1] * h
+    want = g / (2 * mu) * (y * (L - y) + h * h / 4)
+    tol = 1e-11 if precision == 0 else 2e-6
+    err = np.abs(st["u"][0] - want[None, :, None]).max() / want.max()
+    print("poiseuille", dim, precision, err)
+    assert err < tol
+    for c in range(1, dim):
+        assert np.abs(st["u"][c]).max() < tol * want.max()
+    sim.close()
+
+
+def tethered_channel(steps):
+    n = (64, 48, 1)
+    S = inputs.tethered_ring(96, 0.1, (0.4, 0.375), 1.0, 2e4)
+    return inputs.Workload("tethered_channel", 2, n, 1.0, 0.05, 5e-4, steps, S,
+                           inputs.channel_velocity(2, n, seed=11, amp=0.1))
+
+
+@pytest.fixture(scope="module")
+def oracle_tethered():
+    w = tethered_channel(100)
+    return w, oracle_sim(w, walls_y=True, body_force=(2.0, 0.0, 0.0)).advance(w.steps)
+
+
+@pytest.mark.parametrize("precision", [0, 1, 2])
+def test_tethered_obstacle_in_driven_channel(oracle_tethered, precision):
+    """Flow past a tethered ring in a channel driven by a body force: walls,
+    body force and tether points together, against the oracle."""
+    w, o = oracle_tethered
+    g = gpu_sim(w, precision, walls_y=True, body_force=(2.0, 0.0, 0.0))
+    g.step(w.steps)
+    assert g.sync() == w.steps
+    st = g.state()
+    errs = field_errors(st, o, 2)
+    errs["psi"] = psi_vs_p(st["psi"], o.psi, o.p)
+    print("tethered channel precision", precision, errs)
+    check(errs, precision, max(w.n))
+    g.close()
+
+
+def test_force_entry_includes_tethers():
+    """ib_force = link force + tether pull, at positions where some points
+    and targets are stored as other periodic copies."""
+    import oracle
+    w = tethered_channel(1)
+    rng = np.random.default_rng(12)
+    box = np.array([w.n[0] * w.h, w.n[1] * w.h])
+    X = w.structure.X + 0.01 * rng.standard_normal(w.structure.X.shape)
+    X[0, :7] += box[0]
+    ref = (oracle.link_force(X, w.structure.links, period=box)
+           + oracle.tether_force(X, w.structure.tether[0], w.structure.tether[1], period=box))
+    g = gpu_sim(w, 0, walls_y=True)
+    F = g.force(torch.tensor(X, device="cuda")).cpu().numpy()
+    assert np.abs(F - ref).max() <= 1e-12 * np.abs(ref).max()
+    g.close()

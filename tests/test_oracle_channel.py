@@ -135,3 +135,62 @@ def test_channel_invariants(dim):
     s = channel_sim(dim, n, u0, structure=S, mu=0.05, dt=1e-3).advance(20)
     assert np.abs(s.u[1][:, 0, :]).max() == 0.0          # v on the walls
     assert abs(float(np.mean(s.p))) < 1e-10 * max(1.0, np.abs(s.p).max())
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_body_force_drives_discrete_poiseuille_flow(dim):
+    """A uniform body force g along x between the walls, from rest: the
+    steady state of the discrete scheme solves mu D_yy u = -g with the
+    no-slip ghosts, whose exact solution is the parabola shifted by the
+    ghost condition: u_j = g/(2 mu) (y_j (L - y_j) + h^2/4), y_j = (j + 1/2) h,
+    L = n1 h; v, w, psi vanish and p stays zero."""
+    n = (8, 16, 4 if dim == 3 else 1)
+    h = 1.0 / 16
+    mu, g, dt, steps = 1.0, 2.0, 0.01, 400
+    P = oracle.make_params(dim, n, h, mu=mu, dt=dt, walls_y=True, body_force=(g, 0.0, 0.0))
+    shp = (n[2], n[1], n[0])
+    s = oracle.Sim(P, [np.zeros(shp) for _ in range(dim)], np.full((dim, 1), 0.5), NO_LINKS,
+                   np.zeros(1)).advance(steps)
+    y = (np.arange(n[1]) + 0.5) * h
+    L = n[1] * h
+    want = g / (2 * mu) * (y * (L - y) + h * h / 4)
+    assert np.abs(s.u[0] - want[None, :, None]).max() < 1e-12 * want.max()
+    for c in range(1, dim):
+        assert np.abs(s.u[c]).max() < 1e-13
+    assert np.abs(s.p).max() < 1e-11 and np.abs(s.psi).max() < 1e-11
+
+
+def test_tether_is_a_link_to_a_fixed_point():
+    """kappa (Y - X) on a tethered point is the pull of a zero-rest-length
+    link of stiffness kappa to a point held at Y (link force brute force),
+    also across the periodic box."""
+    rng = np.random.default_rng(9)
+    n = 40
+    X = rng.uniform(0, 1, size=(2, n))
+    Y = X + 0.02 * rng.standard_normal((2, n))
+    Y[:, :5] += np.array([[1.0], [-1.0]])              # targets stored as other copies
+    kap = rng.uniform(0, 50, size=n)
+    F = oracle.tether_force(X, kap, Y, period=(1.0, 1.0))
+    XX = np.concatenate([X, Y], axis=1)
+    links = (np.arange(n, dtype=np.int32), np.arange(n, 2 * n, dtype=np.int32), kap, np.zeros(n))
+    ref = oracle.link_force(XX, links, period=(1.0, 1.0))[:, :n]
+    assert np.abs(F - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+def test_tethered_ring_holds_in_driven_channel():
+    """A tethered ring in a channel driven by a body force: the fluid goes
+    round it and the ring stays within a small fraction of a cell of its
+    targets, while a free ring in the same flow is carried downstream."""
+    n = (32, 32, 1)
+    h = 1.0 / 32
+    P = oracle.make_params(2, n, h, mu=0.1, dt=1e-3, walls_y=True, body_force=(5.0, 0.0, 0.0))
+    shp = (1, 32, 32)
+    moved = {}
+    for kt in (0.0, 2e4):
+        S = inputs.tethered_ring(48, 0.1, (0.5, 0.5), 1.0, kt)
+        s = oracle.Sim(P, [np.zeros(shp)] * 2, S.X, S.links, S.w, tether=S.tether).advance(150)
+        moved[kt] = float(np.abs(s.X - S.X).max())
+        if kt:
+            assert np.abs(s.u[1][:, 0, :]).max() == 0.0
+    assert moved[2e4] < 0.05 * h
+    assert moved[0.0] > 20 * moved[2e4]
