@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--cylinder", type=int, nargs="*", default=[256, 128], metavar="N",
                     help="grid sizes of the 3-D cylinder row (100 steps each, mixed and "
                          "FP64); none to skip")
+    ap.add_argument("--no-channel", action="store_true",
+                    help="skip the channel row (the 256^3 shell between no-slip walls)")
     ap.add_argument("--cylinder-only", action="store_true",
                     help="run only the cylinder row (for profiling it alone) and print it")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -92,11 +94,12 @@ def step_bytes(b: int, ncell: int, dim: int) -> float:
     return ((4 * dim + 1) * b + 8 + mom + psi) * ncell
 
 
-def run_gpu(w, precision, steps, warmup, tune=False):
+def run_gpu(w, precision, steps, warmup, tune=False, walls=False):
     import torch
     from paper_1305_3976_amd import ibgm
     cfg = ibgm.Config(w.dim, w.n, w.h, rho=w.rho, mu=w.mu, dt=w.dt, chi=w.chi,
-                      precision=precision)
+                      precision=precision, walls_y=walls,
+                      body_force=(1.0, 0.0, 0.0) if walls else (0.0, 0.0, 0.0))
     sim = ibgm.Simulation(cfg, w.u0, w.structure)
     stream = sim.stream
     picks = sim.tune(3) if tune else None
@@ -165,6 +168,24 @@ def run_cylinder(sizes, steps=100, warmup=5, fp64=True):
                         "r1=5/28, r2=7/20",
             "note": "paper times are FP64 (assumed) on a CPU cluster: context, not a target",
             "runs": out}
+
+
+def run_channel(w, steps, warmup, fp64=True, plain_ms=None):
+    """The same shell workload between no-slip walls at y = 0 and y = 1 (a
+    channel driven by a body force along x): the y sweeps then solve the
+    mirrored lines of twice the length."""
+    out = {"workload": w.name + " between walls at y = 0, 1 (body force 1 along x)", "runs": []}
+    for prec, tag in ((1, "mixed"), (0, "fp64")):
+        if prec == 0 and not fp64:
+            continue
+        ms, ms_plain, _, kern, _ = run_gpu(w, prec, steps, warmup, walls=True)
+        row = {"precision": tag, "ms_per_step": round(ms_plain / steps, 4),
+               "kernels_avg_us": {k: round(t / c * 1e3, 2) for k, (t, c) in kern.items()}}
+        if plain_ms and tag in plain_ms:
+            row["vs_periodic"] = round(plain_ms[tag] / (ms_plain / steps), 3)
+        out["runs"].append(row)
+        print("# channel %s: %.3f ms/step" % (tag, ms_plain / steps), file=sys.stderr, flush=True)
+    return out
 
 
 def run_ensemble(steps, spl_choices=(2, 10), seed=4):
@@ -387,6 +408,12 @@ def main():
                         "step_GB_s": round(step_bytes(8, ncell, w.dim) / (ms64_plain / args.steps * 1e-3) / 1e9, 1),
                         "kernels_avg_us": {k: round(t / c * 1e3, 2) for k, (t, c) in kern64.items()}}
         line["mixed_vs_fp64_speedup"] = round(steps_s / s64, 3)
+    if not args.no_channel:
+        plain = {"mixed": ms_plain / args.steps}
+        if "fp64" in res:
+            plain["fp64"] = res["fp64"][1] / args.steps
+        line["channel"] = run_channel(w, args.steps, args.warmup, fp64=not args.no_fp64,
+                                      plain_ms=plain)
     if args.cylinder:
         line["cylinder"] = run_cylinder(args.cylinder, fp64=not args.no_fp64)
     if args.ensemble_steps:

@@ -600,8 +600,7 @@ static void launch_explicit(ib_ctx *c, bool first) {
   a.walls = (c->prm.flags & IB_FLAG_WALLS_Y) ? 1 : 0;
   for (int i = 0; i < 3; i++) a.g_body[i] = i < DIM ? c->prm.body_force[i] : 0.0;
   if constexpr (DIM == 3) {
-    // (the plane-marching kernel has no wall rows: channels take k_explicit)
-    if (!a.walls && c->g.n0 % EX == 0 && c->g.n1 % EY == 0 && c->g.ncell < INT32_MAX) {
+    if (c->g.n0 % EX == 0 && c->g.n1 % EY == 0 && c->g.ncell < INT32_MAX) {
       // one round of resident workgroups (c->resident3, from ib_init) split
       // over the (x, y) column tiles
       const int resident = std::max(1, c->resident3);

@@ -712,7 +712,7 @@ struct ExplicitArgs {
   TileGrid tg;
   double inv_h, inv_h2, dt, mu, inv_rho;
   int first, advect;
-  int walls;  // channel: no-slip walls at y = 0 and y = n1 h (k_explicit only)
+  int walls;  // channel: no-slip walls at y = 0 and y = n1 h
   double g_body[3];  // uniform body force density added to f
   int ez;  // planes per workgroup of the 3-D plane-marching kernel
 };
@@ -837,6 +837,8 @@ __global__ void __launch_bounds__(ENT) k_explicit3(ExplicitArgs<T, 3, V> a) {
     poff[q] = wrap(j0 - 1 + e / PW, n1) * n0 + wrap(i0 - 1 + e % PW, n0);
   }
   const int cell = (j0 + ty) * n0 + (i0 + tx);
+  // channel walls (as in k_explicit): this thread's row may border one
+  const bool wlo = a.walls && j0 + ty == 0, whi = a.walls && j0 + ty == n1 - 1;
   const int tflag_row = (i0 + tx) / TS + a.tg.nt[0] * ((j0 + ty) / TS);
   const int tplane = a.tg.nt[0] * a.tg.nt[1];
   auto pbase = [&](int kk) { return (int64_t)wrap(kk, n2) * plane; };
@@ -909,12 +911,21 @@ __global__ void __launch_bounds__(ENT) k_explicit3(ExplicitArgs<T, 3, V> a) {
     const int dpl[3] = {1, EW, 0}, sl_m[3] = {s0, s0, sm}, sl_p[3] = {s0, s0, sp};
 #pragma unroll
     for (int ci = 0; ci < 3; ci++) {
+      if (wlo && ci == 1) {  // v on the wall face: not advanced
+        (a.delta[1] + kp)[cell] = T(0);
+        (a.nl[1] + kp)[cell] = T(0);
+        continue;
+      }
       const C u0 = U[ci][s0][c];
       C dv = 0, ad = 0, lap = 0;
 #pragma unroll
       for (int cj = 0; cj < 3; cj++) {
-        const C up = U[ci][sl_p[cj]][c + dpl[cj]];
-        const C um = U[ci][sl_m[cj]][c - dpl[cj]];
+        C up = U[ci][sl_p[cj]][c + dpl[cj]];
+        C um = U[ci][sl_m[cj]][c - dpl[cj]];
+        if (cj == 1 && ci != 1) {  // no-slip ghosts across a channel wall
+          if (whi) up = -u0;
+          if (wlo) um = -u0;
+        }
         lap += up - C(2) * u0 + um;
         if (!a.advect) continue;
         if (cj == ci) {
