@@ -233,3 +233,43 @@ def test_ellipse512_100_steps(ellipse512_oracle, precision):
             lim = MIXED_TOL
         assert e <= lim, (k, e, lim)
     g.close()
+
+
+@pytest.mark.parametrize("long_axis", [0, 1, 2])
+@pytest.mark.parametrize("precision", [0, 1])
+def test_longest_lines(long_axis, precision):
+    """The longest lines the library takes (1024 cells) along each axis in
+    turn, 16 cells across, h = 1/16: a shell in a 64 x 1 x 1 box (rotated to
+    the long axis) with a seeded random flow, 10 steps against the oracle.
+    The 1024-element x, y and z lines take the largest chunk shapes and the
+    widest workgroups of every sweep kernel."""
+    n = [16, 16, 16]
+    n[long_axis] = 1024
+    n = tuple(n)
+    h = 1.0 / 16
+    center = [0.5, 0.5, 0.5]
+    center[long_axis] = 20.0
+    axes = [0.3, 0.25, 0.2]
+    S = inputs.ellipsoid_shell(400, axes=tuple(axes), center=tuple(center))
+    rng = np.random.default_rng(40 + long_axis)
+    shp = (n[2], n[1], n[0])
+    u0 = [0.02 * rng.standard_normal(shp) for _ in range(3)]
+    w = inputs.Workload("longest_lines", 3, n, 1.0, 0.05, 1e-3, 10, S, u0)
+    o = oracle_sim_h(w, h).advance(w.steps)
+    from paper_1305_3976_amd import ibgm
+    cfg = ibgm.Config(3, n, h, rho=1.0, mu=0.05, dt=1e-3, precision=precision)
+    g = ibgm.Simulation(cfg, u0, S)
+    g.step(w.steps)
+    assert g.sync() == w.steps
+    errs = field_errors(g.state(), o, 3)
+    print("longest lines axis", long_axis, "precision", precision, errs)
+    # (h = 1/16: the psi systems' condition number 1 + 4/h^2 keeps p within
+    # the plain FP64 bar)
+    check(errs, FP64_TOL if precision == 0 else MIXED_TOL)
+    g.close()
+
+
+def oracle_sim_h(w, h):
+    P = oracle.make_params(w.dim, w.n, h, rho=w.rho, mu=w.mu, dt=w.dt, chi=w.chi)
+    S = w.structure
+    return oracle.Sim(P, [np.asarray(c, dtype=np.float64) for c in w.u0], S.X, S.links, S.w)
