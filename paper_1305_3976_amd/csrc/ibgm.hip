@@ -575,6 +575,12 @@ static void launch_spread(ib_ctx *c, const double *X, const double *F, const dou
   });
 }
 
+// Grid of the per-cell kernels: blocks of 64 x 4 cells over (x, y), one
+// z-plane (or 2-D layer) per blockIdx.z.
+static dim3 cell_grid(const Grid &g) {
+  return dim3((unsigned)((g.n0 + 63) / 64), (unsigned)((g.n1 + 3) / 4), (unsigned)g.n2);
+}
+
 template <typename T, int DIM, typename V = T>
 static void launch_explicit(ib_ctx *c, bool first) {
   ExplicitArgs<T, DIM, V> a{};
@@ -615,8 +621,7 @@ static void launch_explicit(ib_ctx *c, bool first) {
     }
   }
   launch(c, KP_EXPLICIT, [&] {
-    hipLaunchKernelGGL((k_explicit<T, DIM, V>), dim3((unsigned)((c->g.ncell + 255) / 256)),
-                       dim3(256), 0, c->stream, a);
+    hipLaunchKernelGGL((k_explicit<T, DIM, V>), cell_grid(c->g), dim3(64, 4), 0, c->stream, a);
   });
 }
 
@@ -624,8 +629,8 @@ static void launch_explicit(ib_ctx *c, bool first) {
 template <typename T, int DIM, typename V = T>
 static void launch_divergence(ib_ctx *c, void *out) {
   launch(c, KP_DIVERGENCE, [&] {
-    hipLaunchKernelGGL((k_divergence<V, DIM, T>), dim3((unsigned)((c->g.ncell + 255) / 256)),
-                       dim3(256), 0, c->stream, (const V *)c->buf.u[0],
+    hipLaunchKernelGGL((k_divergence<V, DIM, T>), cell_grid(c->g),
+                       dim3(64, 4), 0, c->stream, (const V *)c->buf.u[0],
                        (const V *)c->buf.u[1], (const V *)(DIM == 3 ? c->buf.u[2] : nullptr),
                        (T *)out, c->g, 1.0 / c->prm.h);
   });

@@ -720,10 +720,14 @@ struct ExplicitArgs {
 template <typename T, int DIM, typename V = T>
 __global__ void __launch_bounds__(256) k_explicit(ExplicitArgs<T, DIM, V> a) {
   using C = V;  // arithmetic in the precision of the velocity state
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= a.g.ncell) return;
+  // blockDim (64, 4): x from blockIdx.x, y from blockIdx.y, the slowest
+  // index (z, or the layer of a 2-D batch) from blockIdx.z -- no divisions
   const int64_t n0 = a.g.n0, n1 = a.g.n1, n2 = a.g.n2;
-  const int64_t i = idx % n0, j = (idx / n0) % n1, k = idx / (n0 * n1);
+  const int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  const int64_t j = (int64_t)blockIdx.y * 4 + threadIdx.y;
+  const int64_t k = blockIdx.z;
+  if (i >= n0 || j >= n1) return;
+  const int64_t idx = i + n0 * (j + n1 * k);
   // linear offsets to the +/- neighbour along each axis, periodic
   int64_t dp[3], dm[3];
   dp[0] = (i + 1 == n0) ? -(n0 - 1) : 1;
@@ -984,10 +988,13 @@ template <typename T, int DIM, typename TD = T>
 __global__ void __launch_bounds__(256) k_divergence(const T *u0, const T *u1,
                                                      const T *u2, TD *out, Grid g,
                                                      double inv_h) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= g.ncell) return;
+  // blockDim (64, 4) over (x, y), blockIdx.z the slowest index, as k_explicit
   const int64_t n0 = g.n0, n1 = g.n1, n2 = g.n2;
-  const int64_t i = idx % n0, j = (idx / n0) % n1, k = idx / (n0 * n1);
+  const int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  const int64_t j = (int64_t)blockIdx.y * 4 + threadIdx.y;
+  const int64_t k = blockIdx.z;
+  if (i >= n0 || j >= n1) return;
+  const int64_t idx = i + n0 * (j + n1 * k);
   double s = (double)u0[idx + ((i + 1 == n0) ? -(n0 - 1) : 1)] - (double)u0[idx];
   s += (double)u1[idx + ((j + 1 == n1) ? -(n1 - 1) * n0 : n0)] - (double)u1[idx];
   if (DIM == 3)

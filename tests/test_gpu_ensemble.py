@@ -107,9 +107,9 @@ def test_graph_replays_match_eager(branches):
             errs = state_errors(sb["u"], sb["p"], sb["psi"], sb["X"],
                                 sa["u"], sa["p"], sa["psi"], sa["X"])
             # equal up to the order of the atomic additions of spreading (which
-            # p sees through the conditioning of the psi solves)
+            # psi and p see through the conditioning of the psi solves)
             for k, e in errs.items():
-                lim = fp64_p_tolerance(sim.cfg.n[0]) if k == "p" else 1e-13
+                lim = fp64_p_tolerance(sim.cfg.n[0]) if k in ("p", "psi") else 1e-13
                 assert e <= lim, (r, k, e, lim)
         # the program's own eager work between replays
         eager.step(2)
