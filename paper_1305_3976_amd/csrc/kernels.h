@@ -147,7 +147,7 @@ struct Grid {
 
 // ------------------------------------------------- Lagrangian: Step 1a-1c --
 
-// One thread per (point, component): interpolate component c of u at X^n
+// Four lanes per (point, component): interpolate component c of u at X^n
 // (Step 1a) and, if `evolve`, advance that coordinate with AB2 (forward
 // Euler when `first`) to X^{n+1} and the midpoint X^{n+1/2} (Steps 1b-1c).
 template <typename T, int DIM>
@@ -165,12 +165,20 @@ struct InterpArgs {
   int evolve, first;
 };
 
-template <typename T, int DIM>
+template <typename T, int DIM, int L>
 __global__ void __launch_bounds__(256) k_interp(InterpArgs<T, DIM> a) {
   using C = T;
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // L = 4 lanes per (point, component): lane q gathers stencil plane t2 = q
+  // (3-D) or row t1 = q (2-D), 16 or 4 loads, and the four partial sums meet
+  // through two lane exchanges -- four times the loads in flight per point.
+  // L = 1: one lane loops over the four planes / rows (dense FP64
+  // structures, where the fourfold weight arithmetic costs more than it
+  // hides).
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t k = L == 4 ? gid >> 2 : gid;
+  const int q0 = L == 4 ? (int)(gid & 3) : 0;
   const int c = blockIdx.y;
-  if (k >= a.np) return;
+  if (k >= a.np) return;  // all four lanes of a point leave together
   const int64_t lay = (DIM == 2 && a.layer) ? a.layer[k] : 0;
   const int32_t nn[3] = {a.g.n0, a.g.n1, a.g.n2};
   C w[3][4];
@@ -180,13 +188,11 @@ __global__ void __launch_bounds__(256) k_interp(InterpArgs<T, DIM> a) {
                             nn[ax], w[ax]);
   const T *__restrict__ uc = a.u[c];
   C acc = 0;
-  // fully unrolled: all 64 loads of the stencil are issued before the first
-  // use (left to itself the compiler keeps the outer loop for FP32 and waits
-  // on memory four times per point)
-  if (DIM == 3) {
 #pragma unroll
-    for (int t2 = 0; t2 < 4; t2++) {
-      int64_t kk = b[2] + t2;
+  for (int r = 0; r < 4 / L; r++) {
+    const int q = q0 + r;
+    if (DIM == 3) {
+      int64_t kk = b[2] + q;
       kk -= kk >= nn[2] ? nn[2] : 0;
       C acc1 = 0;
 #pragma unroll
@@ -203,21 +209,25 @@ __global__ void __launch_bounds__(256) k_interp(InterpArgs<T, DIM> a) {
         }
         acc1 += acc0 * w[1][t1];
       }
-      acc += acc1 * w[2][t2];
-    }
-  } else {
-    for (int t1 = 0; t1 < 4; t1++) {
-      int64_t jj = b[1] + t1;
+      acc += acc1 * (q == 0 ? w[2][0] : q == 1 ? w[2][1] : q == 2 ? w[2][2] : w[2][3]);
+    } else {
+      int64_t jj = b[1] + q;
       jj -= jj >= nn[1] ? nn[1] : 0;
       const T *row = uc + (lay * nn[1] + jj) * nn[0];
       C acc0 = 0;
+#pragma unroll
       for (int t0 = 0; t0 < 4; t0++) {
         int64_t ii = b[0] + t0;
         ii -= ii >= nn[0] ? nn[0] : 0;
         acc0 += (C)row[ii] * w[0][t0];
       }
-      acc += acc0 * w[1][t1];
+      acc += acc0 * (q == 0 ? w[1][0] : q == 1 ? w[1][1] : q == 2 ? w[1][2] : w[1][3]);
     }
+  }
+  if (L == 4) {
+    acc += __shfl_xor(acc, 1);
+    acc += __shfl_xor(acc, 2);
+    if (q0 != 0) return;
   }
   const double U = (double)acc;
   const int64_t o = c * a.np + k;
