@@ -591,10 +591,12 @@ __global__ void __launch_bounds__(NT) k_spread_tiles(SpreadArgs<T, DIM> a) {
     // fall inside the tile are visited
     const int npts = c_pref[ncomb];
     const int64_t np = a.np;
-    // one thread per (candidate point, component) in 2-D, where tiles hold
-    // few candidates; per candidate point (all components) in 3-D, where the
-    // points' shared stencil rows keep one thread busy (measured faster)
-    constexpr int PER = DIM == 2 ? DIM : 1;
+    // one thread per (candidate point, component) in 2-D and for dense 3-D
+    // structures (the 1024-thread tiles: the threefold parallelism hides
+    // more of the atomics' latency, 754 -> 614 us for the 933,888-point
+    // cylinder); per candidate point (all components) for sparse 3-D ones,
+    // where the points' shared stencil rows keep one thread busy
+    constexpr int PER = (DIM == 2 || NT == 1024) ? DIM : 1;
     for (int it = threadIdx.x; it < npts * PER; it += blockDim.x) {
       const int pi = it / PER;
       int slot = 0;
