@@ -591,12 +591,11 @@ __global__ void __launch_bounds__(NT) k_spread_tiles(SpreadArgs<T, DIM> a) {
     // fall inside the tile are visited
     const int npts = c_pref[ncomb];
     const int64_t np = a.np;
-    // one thread per (candidate point, component) in 2-D and for dense 3-D
-    // structures (the 1024-thread tiles: the threefold parallelism hides
-    // more of the atomics' latency, 754 -> 614 us for the 933,888-point
-    // cylinder); per candidate point (all components) for sparse 3-D ones,
-    // where the points' shared stencil rows keep one thread busy
-    constexpr int PER = (DIM == 2 || NT == 1024) ? DIM : 1;
+    // one thread per (candidate point, component): the DIM-fold parallelism
+    // hides more of the atomics' latency than one thread walking all
+    // components (3-D: 754 -> 614 us for the 933,888-point cylinder, 73 ->
+    // 66 us for the 65,536-point shell)
+    constexpr int PER = DIM;
     for (int it = threadIdx.x; it < npts * PER; it += blockDim.x) {
       const int pi = it / PER;
       int slot = 0;
