@@ -86,6 +86,12 @@ struct ib_ctx {
   bool f32;    // work arrays (N, psi, div, workspace) in FP32
   bool u64;    // velocity state in FP64 while the work arrays are FP32
   int resident3;  // workgroups of the 3-D explicit kernel resident on the device at once
+  // Lagrangian work of the next step (Steps 1a-2b) overlapped with this
+  // step's psi sweeps on a second stream: ev_u marks u^{n+1} final, ev_lag
+  // the end of the overlapped work, lag_pending that it was enqueued
+  hipStream_t stream2;
+  hipEvent_t ev_u, ev_lag;
+  bool lag_pending;
   size_t tsz;  // bytes per work-array value
   // workspace
   void *delta[3], *f[3], *divn;
@@ -656,21 +662,38 @@ static void seed_divergence(ib_ctx *c) {
   }
 }
 
-// One full IB-GM step (Steps 1a-3f) at step index n.  T: work arrays; V:
-// velocity state (V = double with T = float is the FP64-state policy: the
-// last momentum sweep then leaves its increment in the work array and
-// u += d runs in FP64).
+// Steps 1a-2b of the step at hand: interpolation and position update, link
+// force (committing X^{n+1}), spreading.  T: work arrays; V: velocity state.
 template <typename T, int DIM, typename V = T>
-static void enqueue_step(ib_ctx *c) {
-  constexpr bool kState64 = !std::is_same<T, V>::value;
-  const int64_t n = c->step;
-  const bool first = n == 0;
+static void enqueue_lagrangian(ib_ctx *c, bool first) {
   // Steps 1a-1c
   launch_interp<V, DIM>(c, KP_INTERP_EVOLVE, c->buf.X, c->np, c->buf.u, c->buf.U_prev,
                         true, first);
   // Step 2a (+ commit X^{n+1}) and Step 2b
   launch_force<DIM>(c, c->Xh, c->F, true);
   launch_spread<T, DIM, false>(c, c->Xh, c->F, c->w, c->np, c->f);
+}
+
+// One full IB-GM step (Steps 1a-3f) at step index n.  T: work arrays; V:
+// velocity state (V = double with T = float is the FP64-state policy: the
+// last momentum sweep then leaves its increment in the work array and
+// u += d runs in FP64).  With `overlap` (another step follows in the same
+// enqueue), the next step's Steps 1a-2b -- which need only u^{n+1} and
+// X^{n+1}, and touch none of the fields of Steps 3e-3f -- are enqueued on
+// the second stream as soon as u^{n+1} is final and run beside this step's
+// divergence and psi sweeps; the next step joins them before its explicit
+// step.
+template <typename T, int DIM, typename V>
+static void enqueue_step(ib_ctx *c, bool overlap) {
+  constexpr bool kState64 = !std::is_same<T, V>::value;
+  const int64_t n = c->step;
+  const bool first = n == 0;
+  if (c->lag_pending) {
+    (void)hipStreamWaitEvent(c->stream, c->ev_lag, 0);
+    c->lag_pending = false;
+  } else {
+    enqueue_lagrangian<T, DIM, V>(c, first);
+  }
   // Steps 3a-3b
   launch_explicit<T, DIM, V>(c, first);
   // split order of this step
@@ -704,6 +727,17 @@ static void enqueue_step(ib_ctx *c) {
                          (const T *)c->delta[1], (const T *)(DIM == 3 ? c->delta[2] : c->delta[0]),
                          c->g.ncell);
     });
+  }
+  if (overlap) {
+    // fork: the next step's Lagrangian work on the second stream
+    hipStream_t main = c->stream;
+    (void)hipEventRecord(c->ev_u, main);
+    (void)hipStreamWaitEvent(c->stream2, c->ev_u, 0);
+    c->stream = c->stream2;
+    enqueue_lagrangian<T, DIM, V>(c, false);
+    c->stream = main;
+    (void)hipEventRecord(c->ev_lag, c->stream2);
+    c->lag_pending = true;
   }
   // Steps 3e-3f: D.u^{n+1} into div_new, then the psi sweeps: the first
   // solves for -(rho/dt) div_new (the scale rides on 1/c) into psi, the last
@@ -746,7 +780,7 @@ static void enqueue_step(ib_ctx *c) {
   c->have_force = true;
 }
 
-static void enqueue_any(ib_ctx *c);
+static void enqueue_any(ib_ctx *c, bool overlap);
 
 // ---------------------------------------------------------------- API --
 
@@ -901,6 +935,11 @@ extern "C" ib_status ib_init(ib_ctx **out, const ib_grid_params *prm, const ib_b
   c->gauge_part = c->gauge + gauge_layers(prm);
   // upload the structure
   auto bail = [&](ib_status e) { ib_destroy(c); return e; };
+  // the second stream of the overlapped Lagrangian work (default priority)
+  if (hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_u, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_lag, hipEventDisableTiming) != hipSuccess)
+    return bail(fail(IB_E_DEVICE, "creating the overlap stream and events failed"));
   if (hipMalloc(&c->ptr, sizeof(int32_t) * (np + 1)) != hipSuccess ||
       hipMalloc(&c->nbr, sizeof(int32_t) * nbr.size()) != hipSuccess ||
       hipMalloc(&c->kap, sizeof(double) * kap.size()) != hipSuccess ||
@@ -970,7 +1009,7 @@ extern "C" ib_status ib_restart(ib_ctx *c, int64_t step0) {
 extern "C" ib_status ib_step(ib_ctx *c, int32_t nsteps) {
   if (!c) return fail(IB_E_STATE, "null context");
   if (nsteps < 0) return fail(IB_E_INVALID, "nsteps < 0");
-  for (int32_t i = 0; i < nsteps; i++) enqueue_any(c);
+  for (int32_t i = 0; i < nsteps; i++) enqueue_any(c, i + 1 < nsteps);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(IB_E_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
   return IB_OK;
@@ -1122,6 +1161,12 @@ extern "C" ib_status ib_destroy(ib_ctx *c) {
   if (c->w) (void)hipFree(c->w);
   if (c->tk) (void)hipFree(c->tk);
   if (c->ty) (void)hipFree(c->ty);
+  if (c->stream2) {
+    (void)hipStreamSynchronize(c->stream2);
+    (void)hipStreamDestroy(c->stream2);
+  }
+  if (c->ev_u) (void)hipEventDestroy(c->ev_u);
+  if (c->ev_lag) (void)hipEventDestroy(c->ev_lag);
   for (void *q : {(void *)c->p_layer, (void *)c->l_dt, (void *)c->l_mom_alpha,
                   (void *)c->l_mom_invc, (void *)c->l_psi_invc})
     if (q) (void)hipFree(q);
@@ -1159,16 +1204,16 @@ extern "C" ib_status ib_profile_read(ib_ctx *c, int32_t id, double *total_ms,
 
 // ----------------------------------------------------------- autotuner --
 
-static void enqueue_any(ib_ctx *c) {
+static void enqueue_any(ib_ctx *c, bool overlap) {
   if (c->u64) {
-    if (c->dim == 2) enqueue_step<float, 2, double>(c);
-    else enqueue_step<float, 3, double>(c);
+    if (c->dim == 2) enqueue_step<float, 2, double>(c, overlap);
+    else enqueue_step<float, 3, double>(c, overlap);
   } else if (c->f32) {
-    if (c->dim == 2) enqueue_step<float, 2>(c);
-    else enqueue_step<float, 3>(c);
+    if (c->dim == 2) enqueue_step<float, 2, float>(c, overlap);
+    else enqueue_step<float, 3, float>(c, overlap);
   } else {
-    if (c->dim == 2) enqueue_step<double, 2>(c);
-    else enqueue_step<double, 3>(c);
+    if (c->dim == 2) enqueue_step<double, 2, double>(c, overlap);
+    else enqueue_step<double, 3, double>(c, overlap);
   }
 }
 
@@ -1289,6 +1334,10 @@ struct ib_graph {
 // context is recorded on a stream of its own forked from `st` and joined back,
 // so the graph holds one independent branch per context, which the runtime may
 // run concurrently (the problems share no data).
+// (Captured steps do not overlap the next step's Lagrangian work on the
+// context's second stream: a capture holding that fork and join ended in a
+// crash inside the runtime.  Graphs of several contexts overlap through their
+// branches instead.)
 static ib_status capture_steps(ib_ctx *const *ctxs, int32_t nctx, int32_t spl, hipStream_t st,
                                int32_t flags, hipGraph_t *graph) {
   const bool branches = (flags & IB_GRAPH_BRANCHES) && nctx > 1;
@@ -1326,13 +1375,13 @@ static ib_status capture_steps(ib_ctx *const *ctxs, int32_t nctx, int32_t spl, h
     for (int i = 0; i < nctx && ef == hipSuccess; i++) {
       ef = hipStreamWaitEvent(br[i], ev[nctx], 0);
       ctxs[i]->stream = br[i];
-      for (int k = 0; k < spl && ef == hipSuccess; k++) enqueue_any(ctxs[i]);
+      for (int k = 0; k < spl && ef == hipSuccess; k++) enqueue_any(ctxs[i], false);
       if (ef == hipSuccess) ef = hipEventRecord(ev[i], br[i]);
       if (ef == hipSuccess) ef = hipStreamWaitEvent(st, ev[i], 0);
     }
   } else {
     for (int k = 0; k < spl; k++)
-      for (int i = 0; i < nctx; i++) enqueue_any(ctxs[i]);
+      for (int i = 0; i < nctx; i++) enqueue_any(ctxs[i], false);
   }
   hipError_t el = hipGetLastError();
   e = hipStreamEndCapture(st, graph);
