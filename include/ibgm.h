@@ -158,10 +158,11 @@ typedef struct {
 ib_status ib_workspace_size(const ib_grid_params *prm, int64_t n_points,
                             size_t *bytes);
 
-/* Validate, upload the structure (the library allocates only its link table),
- * precompute the line-solve factors in FP64 on the host and, for step0 == 0,
- * compute div_prev = D.u^0 and clear the workspace (on `hip_stream`, a
- * hipStream_t; NULL = default stream). */
+/* Validate, upload the structure (the library allocates only its link,
+ * layer and tether tables, plus one internal stream of default priority
+ * and two events per context), precompute the line-solve factors in FP64 on
+ * the host and, for step0 == 0, compute div_prev = D.u^0 and clear the
+ * workspace (on `hip_stream`, a hipStream_t; NULL = default stream). */
 ib_status ib_init(ib_ctx **out, const ib_grid_params *prm,
                   const ib_buffers *buf, const ib_structure *st,
                   void *hip_stream);
@@ -170,7 +171,12 @@ ib_status ib_init(ib_ctx **out, const ib_grid_params *prm,
  * interpolate u to the points, evolve X (AB2; forward Euler at n = 0),
  * link force at X^{n+1/2}, spread, explicit momentum with AB2 skew advection
  * (eq:nonlinear), one implicit sweep per axis (eq:umacstep1/2), the psi
- * sweeps (eq:PenaltyStepPart1/2) and the pressure update.  Asynchronous. */
+ * sweeps (eq:PenaltyStepPart1/2) and the pressure update.  Asynchronous.
+ * Within one call, Steps 1a-2b of each following step run on the context's
+ * internal stream beside the previous step's psi sweeps (they need only
+ * u^{n+1} and X^{n+1}); everything is joined back into `hip_stream` before
+ * the call's last step, so the state seen between calls is that of plain
+ * sequential steps. */
 ib_status ib_step(ib_ctx *ctx, int32_t nsteps);
 
 /* Continue from state the caller has written into the context's buffers

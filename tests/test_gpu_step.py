@@ -273,3 +273,33 @@ def oracle_sim_h(w, h):
     P = oracle.make_params(w.dim, w.n, h, rho=w.rho, mu=w.mu, dt=w.dt, chi=w.chi)
     S = w.structure
     return oracle.Sim(P, [np.asarray(c, dtype=np.float64) for c in w.u0], S.X, S.links, S.w)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_one_call_equals_single_steps(precision):
+    """ib_step(ctx, k) overlaps each next step's Lagrangian work with the psi
+    sweeps of the step before on the context's second stream; the result
+    equals k calls of ib_step(ctx, 1) (plain order) up to the order of the
+    spreading's atomic additions (psi and p through the conditioning of the
+    psi solves)."""
+    n = (64, 48, 40)
+    S = inputs.ellipsoid_shell(2000, axes=(0.3, 0.25 * 48 / 64, 0.2 * 40 / 64),
+                               center=(0.5, 0.5 * 48 / 64, 0.5 * 40 / 64))
+    rng = np.random.default_rng(21)
+    u0 = [0.05 * rng.standard_normal((n[2], n[1], n[0])) for _ in range(3)]
+    w = inputs.Workload("overlap", 3, n, 1.0, 0.05, 1e-3, 30, S, u0)
+    a, b = gpu_sim(w, precision), gpu_sim(w, precision)
+    a.step(w.steps)
+    for _ in range(w.steps):
+        b.step(1)
+    assert a.sync() == b.sync() == w.steps
+    sa, sb = a.state(), b.state()
+    for k in ("p", "psi", "X"):
+        e = rel_l2(sa[k], sb[k])
+        lim = (1e-12 if k == "X" else max(FP64_TOL, (1 + 4 * 64 ** 2) * 2.0 ** -52)) \
+            if precision == 0 else MIXED_TOL
+        assert e <= lim, (k, e)
+    for c in range(3):
+        assert rel_l2(sa["u"][c], sb["u"][c]) <= (1e-12 if precision == 0 else MIXED_TOL)
+    a.close()
+    b.close()
