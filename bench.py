@@ -21,6 +21,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -130,6 +131,56 @@ def run_gpu(w, precision, steps, warmup, tune=False, walls=False):
     del sim
     torch.cuda.empty_cache()
     return ms, ms_plain, wall, kern, picks
+
+
+# The paper's directional-split solve alone (Table StrongScaling:PoissonProblem3d):
+# wall time in seconds on one core and on its fastest partition.
+PAPER_POISSON_3D = {128: {"P=1": 0.205, "P=128": 1.88e-3}, 256: {"P=1": 1.71, "P=256": 7.46e-3}}
+
+
+def run_poisson(sizes=(256, 128), reps=20):
+    """(1 - D_xx)(1 - D_yy)(1 - D_zz) psi = sin 2 pi x cos 2 pi y cos 2 pi z
+    (Sec. "Comparison with Poisson Solvers") through ib_line_solve, one sweep
+    per axis, FP64 and FP32 storage (FP64 recurrences), timed with HIP events;
+    checked against the closed-form solution f / (1 + (4/h^2) sin^2(pi h))^3."""
+    import torch
+    from paper_1305_3976_amd import ibgm
+    out = []
+    for N in sizes:
+        h = 1.0 / N
+        c = (torch.arange(N, dtype=torch.float64, device="cuda") + 0.5) * h
+        f = (torch.sin(2 * math.pi * c)[None, None, :] * torch.cos(2 * math.pi * c)[None, :, None]
+             * torch.cos(2 * math.pi * c)[:, None, None])
+        lam = 1 + (4 / h ** 2) * math.sin(math.pi * h) ** 2
+        for dt_ in (torch.float64, torch.float32):
+            t = f.to(dt_).contiguous()
+            work = t.clone()
+            for axis in (0, 1, 2):
+                ibgm.line_solve(work, axis, 1 + 2 / h ** 2, -1 / h ** 2)
+            err = ((work.double() - f / lam ** 3).abs().max() / (f / lam ** 3).abs().max()).item()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(reps):
+                for axis in (0, 1, 2):
+                    ibgm.line_solve(work, axis, 1 + 2 / h ** 2, -1 / h ** 2)
+            e1.record()
+            torch.cuda.synchronize()
+            sec = e0.elapsed_time(e1) * 1e-3 / reps
+            paper = PAPER_POISSON_3D.get(N, {})
+            row = {"n": N, "dtype": "f64" if dt_ == torch.float64 else "f32",
+                   "s_per_solve": round(sec, 7), "gcell_per_s": round(N ** 3 / sec / 1e9, 2),
+                   "max_rel_err_vs_closed_form": float("%.3g" % err),
+                   "paper_s_per_solve": paper}
+            for key, v in paper.items():
+                row["ratio_vs_paper_" + key] = round(v / sec, 1)
+            out.append(row)
+            del t, work
+        del f, c
+        torch.cuda.empty_cache()
+    return {"workload": "directional-split Poisson solve, 3 sweeps on N^3 cell centres",
+            "note": "paper times are a CPU cluster (FP64 assumed): context, not a target",
+            "runs": out}
 
 
 # Wall time in seconds of the paper's first 100 steps of the cylinder on its
@@ -408,6 +459,7 @@ def main():
                         "step_GB_s": round(step_bytes(8, ncell, w.dim) / (ms64_plain / args.steps * 1e-3) / 1e9, 1),
                         "kernels_avg_us": {k: round(t / c * 1e3, 2) for k, (t, c) in kern64.items()}}
         line["mixed_vs_fp64_speedup"] = round(steps_s / s64, 3)
+    line["poisson"] = run_poisson()
     if not args.no_channel:
         plain = {"mixed": ms_plain / args.steps}
         if "fp64" in res:
