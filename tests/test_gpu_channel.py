@@ -200,3 +200,27 @@ def test_force_entry_includes_tethers():
     F = g.force(torch.tensor(X, device="cuda")).cpu().numpy()
     assert np.abs(F - ref).max() <= 1e-12 * np.abs(ref).max()
     g.close()
+
+
+@pytest.fixture(scope="module")
+def channel256_oracle():
+    w = inputs.config_shell_256(steps=2)
+    return w, oracle_sim(w, walls_y=True, body_force=(1.0, 0.0, 0.0)).advance(w.steps)
+
+
+@pytest.mark.parametrize("precision", [1, 0])
+def test_channel_256_full_size(channel256_oracle, precision):
+    """The timed channel workload itself: the 256^3 shell (65,536 points)
+    between walls at y = 0, 1, driven by a unit body force along x, through
+    the same multi-step call, against the oracle after two steps."""
+    w, o = channel256_oracle
+    g = gpu_sim(w, precision, walls_y=True, body_force=(1.0, 0.0, 0.0))
+    g.step(w.steps)
+    assert g.sync() == w.steps
+    st = g.state()
+    errs = field_errors(st, o, 3)
+    errs["psi"] = psi_vs_p(st["psi"], o.psi, o.p)
+    print("channel 256 precision", precision, errs)
+    check(errs, precision, 256)
+    assert np.abs(st["u"][1][:, 0, :]).max() == 0.0
+    g.close()
