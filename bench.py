@@ -61,6 +61,8 @@ def parse():
                          "FP64); none to skip")
     ap.add_argument("--no-channel", action="store_true",
                     help="skip the channel row (the 256^3 shell between no-slip walls)")
+    ap.add_argument("--no-poisson", action="store_true",
+                    help="skip the directional-split Poisson row (three line-solve sweeps)")
     ap.add_argument("--cylinder-only", action="store_true",
                     help="run only the cylinder row (for profiling it alone) and print it")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -459,7 +461,8 @@ def main():
                         "step_GB_s": round(step_bytes(8, ncell, w.dim) / (ms64_plain / args.steps * 1e-3) / 1e9, 1),
                         "kernels_avg_us": {k: round(t / c * 1e3, 2) for k, (t, c) in kern64.items()}}
         line["mixed_vs_fp64_speedup"] = round(steps_s / s64, 3)
-    line["poisson"] = run_poisson()
+    if not args.no_poisson:
+        line["poisson"] = run_poisson()
     if not args.no_channel:
         plain = {"mixed": ms_plain / args.steps}
         if "fp64" in res:

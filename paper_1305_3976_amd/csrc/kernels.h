@@ -812,6 +812,9 @@ __global__ void __launch_bounds__(256) k_explicit(ExplicitArgs<T, DIM, V> a) {
 // once instead of once per stencil use.  The loads are software-pipelined:
 // while plane k is computed from LDS, plane k+2 of the velocities, plane k+1
 // of p* and this cell's N^{n-1} and f are already in flight into registers.
+// N^{n-1} is read and N^n written with streaming (non-temporal) hints: neither
+// is touched again within the step, so they should not displace delta, which
+// the first momentum sweep reads next, from the last-level cache.
 // Same arithmetic as k_explicit.
 constexpr int EX = 64, EY = 4;
 constexpr int EW = EX + 2, EH = EY + 2;  // velocity plane with halo
@@ -889,7 +892,7 @@ __global__ void __launch_bounds__(ENT) k_explicit3(ExplicitArgs<T, 3, V> a) {
     const bool forced = a.flag[tflag_row + tplane * (kk / TS)] != 0;
 #pragma unroll
     for (int ci = 0; ci < 3; ci++) {
-      nl_out[ci] = a.first ? C(0) : (C)(a.nl[ci] + kp)[cell];
+      nl_out[ci] = a.first ? C(0) : (C)__builtin_nontemporal_load(&(a.nl[ci] + kp)[cell]);
       f_out[ci] = (forced ? (C)(a.f[ci] + kp)[cell] : C(0)) + (C)a.g_body[ci];
     }
   };
@@ -964,7 +967,7 @@ __global__ void __launch_bounds__(ENT) k_explicit3(ExplicitArgs<T, 3, V> a) {
       const C Nh = a.first ? N : C(1.5) * N - C(0.5) * nlp[ci];
       const C d = (C)a.dt * (-Nh + ((C)a.mu * lap * (C)a.inv_h2 - gp + fc[ci]) * (C)a.inv_rho);
       (a.delta[ci] + kp)[cell] = (T)d;
-      (a.nl[ci] + kp)[cell] = (T)N;
+      __builtin_nontemporal_store((T)N, &(a.nl[ci] + kp)[cell]);
     }
     ps_below = ps0;
     // 3. rotate: plane k+2 replaces plane k-1, plane k+1 of p* replaces k
