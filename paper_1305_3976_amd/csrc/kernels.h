@@ -603,29 +603,30 @@ __global__ void __launch_bounds__(NT) k_spread_tiles(SpreadArgs<T, DIM> a) {
       const int64_t k = c_start[slot] + (pi - c_pref[slot]);
       const int c_lo = PER == 1 ? 0 : it - pi * PER, c_hi = PER == 1 ? DIM : c_lo + 1;
       for (int c = c_lo; c < c_hi; c++) {
-        int b[3], tlo[3], thi[3];
+        // in-tile coordinate of each stencil offset t = 0..3 per axis, -1
+        // where (b + t) mod n falls outside the tile.  The in-tile offsets
+        // need not be contiguous: on an axis of at most 10 cells tile 0 can
+        // hold cells from both sides of the periodic wrap (n = 9, b = 7:
+        // cells 7, 8, 0, 1, of which 7, 0, 1 lie in tile 0).
+        int loc[3][4];
         bool any = true;
+#pragma unroll
         for (int ax = 0; ax < 3; ax++) {
-          if (ax >= DIM) {
-            b[ax] = lo[ax];  // 2-D: the tile's layer
-            tlo[ax] = 0;
-            thi[ax] = 1;
-            continue;
-          }
-          b[ax] = a.st.base[(c * 3 + ax) * np + k];
-          // stencil offsets t in 0..3 with (b + t) mod n inside [lo, hi)
-          int t0 = 4, t1 = -1;
+          bool hit = false;
+          const int b0 = ax < DIM ? a.st.base[(c * 3 + ax) * np + k] : 0;
+#pragma unroll
           for (int t = 0; t < 4; t++) {
-            int cell = b[ax] + t;
-            cell -= cell >= nn[ax] ? nn[ax] : 0;
-            if (cell >= lo[ax] && cell < hi[ax]) {
-              t0 = t < t0 ? t : t0;
-              t1 = t;
+            if (ax >= DIM) {  // 2-D: the tile's own layer, one offset
+              loc[ax][t] = t == 0 ? 0 : -1;
+              continue;
             }
+            int cell = b0 + t;  // b0 < n and n >= 4: one wrap at most
+            cell -= cell >= nn[ax] ? nn[ax] : 0;
+            const bool in = cell >= lo[ax] && cell < hi[ax];
+            loc[ax][t] = in ? cell - lo[ax] : -1;
+            hit |= in;
           }
-          tlo[ax] = t0;
-          thi[ax] = t1 + 1;
-          any &= t0 <= t1;
+          any &= ax >= DIM || hit;
         }
         if (!any) continue;
         // the 4 weights per axis in registers (loaded together), then the
@@ -638,28 +639,19 @@ __global__ void __launch_bounds__(NT) k_spread_tiles(SpreadArgs<T, DIM> a) {
           wy[t] = a.st.wt[((c * 3 + 1) * 4 + t) * np + k];
           wz[t] = DIM == 3 ? a.st.wt[((c * 3 + 2) * 4 + t) * np + k] : C(1);
         }
-        // in-tile coordinate of the first in-tile stencil cell per axis (the
-        // in-tile cells of a stencil are contiguous: a wrap leaves one side
-        // of it outside the tile)
-        int l0[3];
-#pragma unroll
-        for (int ax = 0; ax < 3; ax++) {
-          int cell = b[ax] + tlo[ax];
-          cell -= (ax < DIM && cell >= nn[ax]) ? nn[ax] : 0;
-          l0[ax] = ax < DIM ? cell - lo[ax] - tlo[ax] : 0;
-        }
 #pragma unroll
         for (int t2 = 0; t2 < (DIM == 3 ? 4 : 1); t2++) {
-          if (DIM == 3 && (t2 < tlo[2] || t2 >= thi[2])) continue;
-          const int lz = DIM == 3 ? l0[2] + t2 : 0;
+          const int lz = loc[2][t2];
+          if (lz < 0) continue;
 #pragma unroll
           for (int t1 = 0; t1 < 4; t1++) {
-            if (t1 < tlo[1] || t1 >= thi[1]) continue;
+            const int ly = loc[1][t1];
+            if (ly < 0) continue;
             const C rw = val * wz[t2] * wy[t1];
-            const int lrow = (lz * TS + l0[1] + t1) * TS + l0[0];
+            const int lrow = (lz * TS + ly) * TS;
 #pragma unroll
             for (int t0 = 0; t0 < 4; t0++)
-              if (t0 >= tlo[0] && t0 < thi[0]) atomicAdd(&acc[c][lrow + t0], (A)(rw * wx[t0]));
+              if (loc[0][t0] >= 0) atomicAdd(&acc[c][lrow + loc[0][t0]], (A)(rw * wx[t0]));
           }
         }
       }
