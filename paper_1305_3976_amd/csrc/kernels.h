@@ -490,33 +490,46 @@ __device__ __forceinline__ int source_tiles(int lo, int hi, int n, int list[3]) 
 
 // One thread per tile: does any point's stencil reach the tile?  Touched
 // tiles are appended to `list` (order arbitrary) and, in store mode, every
-// tile's flag records whether f holds force there.
+// tile's flag records whether f holds force there.  A wave reserves the
+// list slots of all its touched tiles with one atomic (consecutive slots in
+// lane order) instead of one atomic per tile on the shared counter.
 template <int DIM>
 __global__ void __launch_bounds__(256) k_touch(const int *start, int *flag, int *list,
                                                 int *nlist, Grid g, TileGrid tg) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= tg.ntiles) return;
-  const int32_t nn[3] = {g.n0, g.n1, g.n2};
-  const int tc[3] = {(int)(t % tg.nt[0]), (int)((t / tg.nt[0]) % tg.nt[1]),
-                     (int)(t / ((int64_t)tg.nt[0] * tg.nt[1]))};
-  int lst[3][3], len[3];
-  for (int ax = 0; ax < 3; ax++) {
-    if (ax >= DIM) {
-      lst[ax][0] = tc[ax];  // 2-D: the tile's own layer
-      len[ax] = 1;
-    } else {
-      len[ax] = source_tiles(tc[ax] * TS, min(nn[ax], tc[ax] * TS + TS), nn[ax], lst[ax]);
-    }
-  }
-  int total = 0;
-  for (int i2 = 0; i2 < len[2]; i2++)
-    for (int i1 = 0; i1 < len[1]; i1++)
-      for (int i0 = 0; i0 < len[0]; i0++) {
-        const int64_t tt = lst[0][i0] + (int64_t)tg.nt[0] * (lst[1][i1] + (int64_t)tg.nt[1] * lst[2][i2]);
-        total += start[tt + 1] - start[tt];
+  bool hit = false;
+  if (t < tg.ntiles) {  // every lane stays for the ballot below
+    const int32_t nn[3] = {g.n0, g.n1, g.n2};
+    const int tc[3] = {(int)(t % tg.nt[0]), (int)((t / tg.nt[0]) % tg.nt[1]),
+                       (int)(t / ((int64_t)tg.nt[0] * tg.nt[1]))};
+    int lst[3][3], len[3];
+    for (int ax = 0; ax < 3; ax++) {
+      if (ax >= DIM) {
+        lst[ax][0] = tc[ax];  // 2-D: the tile's own layer
+        len[ax] = 1;
+      } else {
+        len[ax] = source_tiles(tc[ax] * TS, min(nn[ax], tc[ax] * TS + TS), nn[ax], lst[ax]);
       }
-  if (flag) flag[t] = total > 0;
-  if (total > 0) list[atomicAdd(nlist, 1)] = (int)t;
+    }
+    int total = 0;
+    for (int i2 = 0; i2 < len[2]; i2++)
+      for (int i1 = 0; i1 < len[1]; i1++)
+        for (int i0 = 0; i0 < len[0]; i0++) {
+          const int64_t tt =
+              lst[0][i0] + (int64_t)tg.nt[0] * (lst[1][i1] + (int64_t)tg.nt[1] * lst[2][i2]);
+          total += start[tt + 1] - start[tt];
+        }
+    if (flag) flag[t] = total > 0;
+    hit = total > 0;
+  }
+  const uint64_t m = __ballot(hit);
+  if (m == 0) return;
+  const int lane = (int)__lane_id();
+  const int leader = __builtin_ctzll(m);
+  int base = 0;
+  if (lane == leader) base = atomicAdd(nlist, __popcll(m));
+  base = __shfl(base, leader);
+  if (hit) list[base + __popcll(m & ((1ull << lane) - 1ull))] = (int)t;
 }
 
 template <typename T, int DIM>
