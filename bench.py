@@ -246,43 +246,53 @@ def run_ensemble(steps, spl_choices=(2, 10), seed=4):
     {128,...,512}, 4N-point ellipses, stiffness log-uniform in [0.1, 100], time
     step per member), FP32 grid.  Step 0 runs eagerly (start-up rules); then
     every variant (steps per graph launch x one chain / one branch per size
-    class) is timed over the same number of steps after tuning, and the
-    fastest is reported, beside eager launches of the same steps."""
+    class, and one branch per context with the largest class split in two) is
+    timed over the same number of steps after tuning, and the fastest is
+    reported, beside eager launches of the same steps."""
     import torch
     from paper_1305_3976_amd import ensemble, ibgm, inputs
     members, shared = inputs.config_ensemble(nsims=64, seed=seed, steps=steps)
-    ens = ensemble.Ensemble(members, rho=shared["rho"], mu=shared["mu"],
-                            precision=ibgm.IB_PREC_MIXED)
-    st = ens.stream
-    t0 = time.perf_counter()
-    picks = ens.tune(reps=10)
-    tune_s = time.perf_counter() - t0
-    ens.step(1)
-    ens.sync()
+    per_size = {}
+    for m in members:
+        per_size[m.n] = per_size.get(m.n, 0) + 1
+    split = (max(n * n * c for n, c in per_size.items()) + 1) // 2
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     timed = steps - 1 - (steps - 1) % (2 * max(spl_choices))
-    # eager launches of the same steps
-    e0.record(st)
-    ens.step(timed)
-    e1.record(st)
-    ens.sync()
-    eager_ms = e0.elapsed_time(e1)
     variants = {}
-    for spl in spl_choices:
-        for br in (False, True):
-            ens.capture(spl, branches=br)
-            ens.launch(1)                      # warm the instantiated graph
-            ens.sync()
+    for split_cells in (0, split):
+        ens = ensemble.Ensemble(members, rho=shared["rho"], mu=shared["mu"],
+                                precision=ibgm.IB_PREC_MIXED, split_cells=split_cells)
+        st = ens.stream
+        t0 = time.perf_counter()
+        pk = ens.tune(reps=10)
+        if split_cells == 0:
+            picks, tune_s = pk, time.perf_counter() - t0
+        ens.step(1)
+        ens.sync()
+        if split_cells == 0:
+            # eager launches of the same steps
             e0.record(st)
-            ens.launch(timed // spl)
+            ens.step(timed)
             e1.record(st)
             ens.sync()
-            variants["spl%d_%s" % (spl, "branches" if br else "chain")] = e0.elapsed_time(e1)
+            eager_ms = e0.elapsed_time(e1)
+        for spl in spl_choices:
+            for br in ((False, True) if split_cells == 0 else (True,)):
+                ens.capture(spl, branches=br)
+                ens.launch(1)                      # warm the instantiated graph
+                ens.sync()
+                e0.record(st)
+                ens.launch(timed // spl)
+                e1.record(st)
+                ens.sync()
+                key = "spl%d_%s%s" % (spl, "branches" if br else "chain",
+                                      "_split" if split_cells else "")
+                variants[key] = e0.elapsed_time(e1)
+        ens.close()
+        del ens
+        torch.cuda.empty_cache()
     best = min(variants, key=variants.get)
     ms = variants[best]
-    ens.close()
-    del ens
-    torch.cuda.empty_cache()
     cells = sum(m.n ** 2 for m in members)
     sizes = {}
     for m in members:
@@ -292,6 +302,7 @@ def run_ensemble(steps, spl_choices=(2, 10), seed=4):
                     "(seed %d), 4N-point 0.3x0.2 ellipses, stiffness log-uniform [0.1,100], "
                     "mu=0.01, per-member dt from the stiffness table, FP32 grid" % seed,
         "members": len(members), "members_per_size": sizes, "cells": cells,
+        "split_cells": split,
         "timed_steps": timed,
         "member_steps_per_s": round(len(members) * timed / (ms * 1e-3), 1),
         "ensemble_steps_per_s": round(timed / (ms * 1e-3), 2),

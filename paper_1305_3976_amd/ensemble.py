@@ -3,11 +3,14 @@
 Problems of equal grid size N form one size class; a class is one library
 context whose 2-D grid has n = (N, N, m): m layers that never exchange data
 (each with its own time step and line-solve factors, and its points tagged
-with their layer).  All classes share one stream; after the first step (which
-uses the start-up rules of the method) the steps of every class are replayed
-from one captured hipGraph (ib_graph_create / ib_graph_launch), optionally
-with one independent graph branch per class.  The line-solve tile shapes of
-each class can be picked by the library's autotuner (ib_tune).
+with their layer).  A class of more than `split_cells` cells is dealt out to
+several contexts of near-equal layer counts, so that with one graph branch
+per context no single branch carries most of the work.  All contexts share
+one stream; after the first step (which uses the start-up rules of the
+method) the steps of every context are replayed from one captured hipGraph
+(ib_graph_create / ib_graph_launch), optionally with one independent graph
+branch per context.  The line-solve tile shapes of each context can be
+picked by the library's autotuner (ib_tune).
 """
 from __future__ import annotations
 
@@ -29,17 +32,27 @@ class _Batch:
 
 class Ensemble:
     """members: objects with n (grid cells per side, the box is the unit
-    square), dt, and structure (X (2, np), links (a, b, kappa, l0), w)."""
+    square), dt, and structure (X (2, np), links (a, b, kappa, l0), w).
+    split_cells: 0 keeps one context per size class; otherwise a class of
+    more cells is split over ceil(cells / split_cells) contexts."""
 
     def __init__(self, members, rho: float = 1.0, mu: float = 0.01, chi: float = 0.6,
-                 precision: int = ibgm.IB_PREC_MIXED, device="cuda", stream=None):
+                 precision: int = ibgm.IB_PREC_MIXED, device="cuda", stream=None,
+                 split_cells: int = 0):
         self.members = list(members)
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
         sizes = sorted({int(m.n) for m in self.members})
-        self.sims, self.classes, self.where = [], [], {}
+        groups = []
         for n in sizes:
-            group = [m for m in self.members if int(m.n) == n]
+            cls = [m for m in self.members if int(m.n) == n]
+            parts = 1
+            if split_cells > 0:
+                parts = min(len(cls), -(-len(cls) * n * n // int(split_cells)))
+            for q in range(parts):  # members q, q + parts, ... (near-equal counts)
+                groups.append((n, cls[q::parts]))
+        self.sims, self.classes, self.where = [], [], {}
+        for n, group in groups:
             Xs, a, b, k, l0, w, lay = [], [], [], [], [], [], []
             off = 0
             for layer, m in enumerate(group):

@@ -87,6 +87,25 @@ def test_members_match_oracle(small_oracle, precision, tol, branches):
     ens.close()
 
 
+@pytest.mark.parametrize("precision,tol", [(0, FP64_TOL), (1, MIXED_TOL)])
+def test_split_classes_match_oracle(small_oracle, precision, tol):
+    """A size class dealt out to several contexts (split_cells below the
+    class size), one graph branch each: every member still matches the
+    oracle."""
+    members, shared, steps, refs = small_oracle
+    ens = ensemble.Ensemble(members, rho=shared["rho"], mu=shared["mu"], precision=precision,
+                            split_cells=64 * 64)
+    assert len(ens.sims) > len(SMALL_SIZES)
+    ens.run(steps, steps_per_launch=4, branches=True)
+    assert ens.sync() == [steps] * len(ens.sims)
+    for m, o in zip(members, refs):
+        errs = member_errors(ens, m, o)
+        for k, e in errs.items():
+            lim = fp64_p_tolerance(m.n) if (precision == 0 and k == "p") else tol
+            assert e <= lim, (m.index, k, e, lim)
+    ens.close()
+
+
 def all_states(ens):
     return [s.state() for s in ens.sims]
 
