@@ -63,6 +63,8 @@ def parse():
                     help="skip the channel row (the 256^3 shell between no-slip walls)")
     ap.add_argument("--no-poisson", action="store_true",
                     help="skip the directional-split Poisson row (three line-solve sweeps)")
+    ap.add_argument("--poisson-only", action="store_true",
+                    help="run only the directional-split Poisson row and print it")
     ap.add_argument("--cylinder-only", action="store_true",
                     help="run only the cylinder row (for profiling it alone) and print it")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -393,6 +395,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.poisson_only:
+        print(json.dumps({"poisson": run_poisson()}), flush=True)
+        return
     if args.cylinder_only:
         print(json.dumps({"cylinder": run_cylinder(args.cylinder or [256],
                                                    steps=args.steps, warmup=args.warmup,
