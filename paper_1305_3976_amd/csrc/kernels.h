@@ -496,12 +496,14 @@ __device__ __forceinline__ int source_tiles(int lo, int hi, int n, int list[3]) 
 template <int DIM>
 __global__ void __launch_bounds__(256) k_touch(const int *start, int *flag, int *list,
                                                 int *nlist, Grid g, TileGrid tg) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // tile counts stay below 2^31 (at most (1024/8)^3 tiles, or 128^2 tiles
+  // times 65535 layers in 2-D), so the index arithmetic is 32-bit
+  const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
   bool hit = false;
   if (t < tg.ntiles) {  // every lane stays for the ballot below
     const int32_t nn[3] = {g.n0, g.n1, g.n2};
-    const int tc[3] = {(int)(t % tg.nt[0]), (int)((t / tg.nt[0]) % tg.nt[1]),
-                       (int)(t / ((int64_t)tg.nt[0] * tg.nt[1]))};
+    const int nt0 = tg.nt[0], nt1 = tg.nt[1];
+    const int tc[3] = {t % nt0, (t / nt0) % nt1, t / (nt0 * nt1)};
     int lst[3][3], len[3];
     for (int ax = 0; ax < 3; ax++) {
       if (ax >= DIM) {
@@ -510,14 +512,21 @@ __global__ void __launch_bounds__(256) k_touch(const int *start, int *flag, int 
       } else {
         len[ax] = source_tiles(tc[ax] * TS, min(nn[ax], tc[ax] * TS + TS), nn[ax], lst[ax]);
       }
+      for (int q = len[ax]; q < 3; q++) lst[ax][q] = lst[ax][0];  // valid fillers
     }
+    // fixed trip counts, every count read issued up front (the fillers read
+    // real entries and are masked out), so the reads overlap instead of
+    // waiting one after another
     int total = 0;
-    for (int i2 = 0; i2 < len[2]; i2++)
-      for (int i1 = 0; i1 < len[1]; i1++)
-        for (int i0 = 0; i0 < len[0]; i0++) {
-          const int64_t tt =
-              lst[0][i0] + (int64_t)tg.nt[0] * (lst[1][i1] + (int64_t)tg.nt[1] * lst[2][i2]);
-          total += start[tt + 1] - start[tt];
+#pragma unroll
+    for (int i2 = 0; i2 < (DIM == 3 ? 3 : 1); i2++)
+#pragma unroll
+      for (int i1 = 0; i1 < 3; i1++)
+#pragma unroll
+        for (int i0 = 0; i0 < 3; i0++) {
+          const int tt = lst[0][i0] + nt0 * (lst[1][i1] + nt1 * lst[2][i2]);
+          const int cnt = start[tt + 1] - start[tt];
+          total += (i0 < len[0] && i1 < len[1] && i2 < len[2]) ? cnt : 0;
         }
     if (flag) flag[t] = total > 0;
     hit = total > 0;
