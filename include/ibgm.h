@@ -85,6 +85,10 @@ typedef enum {
  * 4-point stencils then never reach across them); nothing checks this. */
 #define IB_FLAG_WALLS_Y 2
 
+/* Largest number of immersed points per context: points are sorted by tile
+ * with 32-bit counts and ranks. */
+#define IB_MAX_POINTS 2147483647LL
+
 typedef struct {
   int32_t dim;          /* 2 or 3 */
   int32_t n[3];         /* cells per axis, each >= 4 and <= 1024.  In 2D, n[2]
@@ -124,7 +128,7 @@ typedef struct {
   double *p;        /* p^{n-1/2}, FP64, cell centred */
   double *X;        /* X^n, FP64 [dim][n_points] */
   double *U_prev;   /* U^{n-1}, FP64 [dim][n_points] */
-  int64_t n_points;
+  int64_t n_points; /* 1 .. IB_MAX_POINTS (larger: IB_E_UNSUPPORTED) */
   void *workspace;  /* device scratch of ib_workspace_size() bytes, 256-B aligned */
   size_t workspace_bytes;
 } ib_buffers;

@@ -471,6 +471,7 @@ extern "C" ib_status ib_workspace_size(const ib_grid_params *prm, int64_t n_poin
   ib_status st = check_params(prm);
   if (st != IB_OK) return st;
   if (n_points < 0) return fail(IB_E_INVALID, "n_points < 0");
+  if (n_points > IB_MAX_POINTS) return fail(IB_E_UNSUPPORTED, "n_points above IB_MAX_POINTS");
   if (!bytes) return fail(IB_E_INVALID, "null output");
   *bytes = workspace_bytes(prm, n_points);
   return IB_OK;
@@ -797,6 +798,9 @@ extern "C" ib_status ib_init(ib_ctx **out, const ib_grid_params *prm, const ib_b
   if (!buf->psi || !buf->div_prev || !buf->p) return fail(IB_E_INVALID, "null p / psi / div_prev");
   const int64_t np = buf->n_points;
   if (np < 1) return fail(IB_E_INVALID, "n_points must be >= 1");
+  if (np > IB_MAX_POINTS)
+    return fail(IB_E_UNSUPPORTED, "n_points = %lld above %lld (32-bit sort ranks)", (long long)np,
+                (long long)IB_MAX_POINTS);
   if (!buf->X || !buf->U_prev) return fail(IB_E_INVALID, "null X / U_prev");
   if (!buf->workspace || ((uintptr_t)buf->workspace & 255))
     return fail(IB_E_INVALID, "workspace must be non-null and 256-byte aligned");

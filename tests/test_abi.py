@@ -77,3 +77,25 @@ def test_init_argument_errors(ib):
     assert not ctx.value
     assert ib.lib.ib_step(None, 1) == ib.IB_E_STATE
     assert ib.lib.ib_sync(None, None) == ib.IB_E_STATE
+
+
+def test_point_count_limit(ib):
+    """More points than the 32-bit sort ranks hold is refused up front (no
+    array is read: the device pointers below are never dereferenced)."""
+    P = ib.Config(3, (16, 16, 16), 1 / 16).params()
+    n = ctypes.c_size_t()
+    big = 2 ** 31
+    assert ib.lib.ib_workspace_size(ctypes.byref(P), big, ctypes.byref(n)) == ib.IB_E_UNSUPPORTED
+    assert ib.lib.ib_workspace_size(ctypes.byref(P), big - 1, ctypes.byref(n)) == ib.IB_OK
+    B = ib.Buffers()
+    fake = ctypes.c_void_p(4096)
+    for c in range(3):
+        B.u[c] = fake
+        B.nl_prev[c] = fake
+    B.psi = B.div_prev = B.p = B.X = B.U_prev = fake
+    B.n_points = big
+    ctx = ctypes.c_void_p()
+    st = ib.lib.ib_init(ctypes.byref(ctx), ctypes.byref(P), ctypes.byref(B),
+                        ctypes.byref(ib.Structure()), None)
+    assert st == ib.IB_E_UNSUPPORTED and not ctx.value
+    assert b"n_points" in ib.lib.ib_last_error(None)
