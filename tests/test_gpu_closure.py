@@ -255,3 +255,38 @@ def test_closure_gain_on_held_out_trajectories():
     assert np.all(np.isfinite(losses))
     assert losses[-20:].mean() < 0.5 * losses[:20].mean()
     assert e1 < 0.7 * e0
+
+
+def test_network_forward_full_size_sampled():
+    """The network as the closure applies it at full size (one 128^3
+    periodic field, 9 -> 32 -> 32 -> 3) against the oracle at sampled voxels:
+    an output depends only on the 7^3 periodic neighbourhood of its voxel, on
+    which the oracle runs the three layers in 'valid' mode with the stored
+    activations rounded to BF16 as on the GPU.  Box corners and faces are
+    among the samples (their neighbourhoods wrap)."""
+    rng = np.random.default_rng(71)
+    net = cl.ConvNet(seed=5)
+    for i in range(3):
+        net.b[i].copy_(torch.as_tensor(rng.standard_normal(net.b[i].shape[0]).astype(np.float32) * 0.05))
+    net.pack()
+    n = 128
+    _, xh = bf16_pair((1, n, n, n, 16), rng)
+    xh[..., cl.CIN:] = 0.0
+    x = torch.as_tensor(xh.astype(np.float32)).to(torch.bfloat16).to(DEV)
+    y = net.forward(x, 1, (n, n, n), cl.PERIODIC)
+    torch.cuda.synchronize()
+    got = y.double().cpu().numpy().reshape(n, n, n, 3)
+    (W1, b1), (W2, b2), (W3, b3) = [(bf16_round(W), b) for W, b in net.params_numpy()]
+    pts = [(0, 0, 0), (n - 1, n - 1, n - 1), (0, n - 1, n // 2), (n // 2, 0, n - 1)]
+    pts += [tuple(int(v) for v in rng.integers(0, n, 3)) for _ in range(60)]
+    mine, ref = [], []
+    for pz, py, px in pts:
+        w = np.arange(-3, 4)
+        brick = xh[0][np.ix_((pz + w) % n, (py + w) % n, (px + w) % n)][None, ..., :cl.CIN]
+        a1 = bf16_round(oc.relu(oc.conv3d(brick, W1, b1, "valid")))
+        a2 = bf16_round(oc.relu(oc.conv3d(a1, W2, b2, "valid")))
+        ref.append(oc.conv3d(a2, W3, b3, "valid")[0, 0, 0, 0])
+        mine.append(got[pz, py, px])
+    # FP32 sums of exact BF16 products; an activation whose FP32 and FP64
+    # sums round to neighbouring BF16 values differs by 2^-8 of itself
+    assert rel(np.array(mine), np.array(ref)) <= 1e-3

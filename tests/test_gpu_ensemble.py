@@ -229,3 +229,30 @@ def test_layer_tables_rejected():
                         u0, batch(ok_layer))
     with pytest.raises(ibgm.IBError):                      # a batch without a layer table
         ibgm.Simulation(cfg, u0, batch(None))
+
+
+def test_full_size_ensemble_sampled_members():
+    """The timed batch itself: 64 members of N in {128 ... 512} (seed 4),
+    mixed policy, the largest class split in two, one graph branch per
+    context, 1 eager + 10 replayed steps; one member of every size against
+    the oracle, per field."""
+    members, shared = inputs.config_ensemble(nsims=64, seed=4, steps=11)
+    per = {}
+    for m in members:
+        per[m.n] = per.get(m.n, 0) + 1
+    split = (max(n * n * c for n, c in per.items()) + 1) // 2
+    ens = ensemble.Ensemble(members, rho=shared["rho"], mu=shared["mu"],
+                            precision=ibgm.IB_PREC_MIXED, split_cells=split)
+    assert len(ens.sims) == len(per) + 1
+    ens.run(11, steps_per_launch=10, branches=True)
+    assert ens.sync() == [11] * len(ens.sims)
+    sample = {}
+    for m in members:
+        sample.setdefault(m.n, m)
+    for n, m in sorted(sample.items()):
+        o = oracle_member(m, shared, 11)
+        errs = member_errors(ens, m, o)
+        print("member n", n, "sigma %.3g" % m.sigma, errs)
+        for k, e in errs.items():
+            assert e <= MIXED_TOL, (n, k, e)
+    ens.close()
