@@ -325,6 +325,25 @@ def ens_classes_sizes(members):
     return [(n, None) for n in sorted({m.n for m in members})]
 
 
+def lagrangian_traffic(rows, npts, dim, b):
+    """Per-point stencil traffic of the Lagrangian kernels, reported apart
+    from the grid roofline (it is mostly served from L2, not HBM):
+    interp + evolve reads the 4^dim stencil of every velocity component
+    (dim 4^dim b) and X^n, U^{n-1} (2 dim 8), and writes U^n, X^{n+1},
+    X^{n+1/2} (3 dim 8); spreading adds every point's 4^dim stencil values
+    into f, counted as a read-modify-write (2 dim 4^dim b)."""
+    st = 4 ** dim
+    per = {"interp_evolve": dim * st * b + 5 * dim * 8, "spread": 2 * dim * st * b}
+    out = {"points": npts, "note": "per-point stencil bytes, mostly L2-resident (not an HBM bound)"}
+    for k, bpp in per.items():
+        if k in rows:
+            mb = npts * bpp / 1e6
+            out[k] = {"bytes_per_point": bpp, "alg_MB_per_launch": round(mb, 2),
+                      "avg_us": rows[k]["avg_us"],
+                      "GB_s": round(mb * 1e6 / (rows[k]["avg_us"] * 1e-6) / 1e9, 1)}
+    return out
+
+
 def device_copy_rate(mib: int = 1024, reps: int = 5) -> float:
     """Achievable HBM rate: a 1 GiB device-to-device copy (read + write bytes
     per second), timed with HIP events."""
@@ -465,6 +484,7 @@ def main():
                      "achievable_copy_GB_s": round(copy_gbs, 1),
                      "frac_of_copy": round(ach / copy_gbs, 4)},
         "kernels": rows,
+        "lagrangian": lagrangian_traffic(rows, w.structure.np, w.dim, b),
         "tuned_tiles": None if picks is None else {
             "%d/%s" % (a, "f64" if r else "f32"): list(v) for (a, r), v in picks.items()},
     }
