@@ -303,3 +303,53 @@ def test_one_call_equals_single_steps(precision):
         assert rel_l2(sa["u"][c], sb["u"][c]) <= (1e-12 if precision == 0 else MIXED_TOL)
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-10), (1, MIXED_TOL)])
+def test_two_by_two_tiling_at_1024(precision, tol):
+    """A property that holds at any size: four copies of a membrane in a
+    2 x 2 box of 1024^2 cells (h = 1/512) reproduce the single 512^2 problem
+    in every quadrant (translation invariance and periodicity), 20 steps.
+    FP64 bar: the two runs round the psi solves differently (lines of 1024
+    against 512), so p may differ by (1 + 4/h^2) eps64 = 2.3e-10 of itself,
+    which each explicit step passes to u as (dt/(rho h)) G dp: about 0.02 of
+    it per step, 1e-10 over the 20 steps (measured: 3e-11)."""
+    from paper_1305_3976_amd import ibgm
+    N = 512
+    h = 1.0 / N
+    S = inputs.ellipse(2048, 0.3, 0.2, 1.0)
+    u1 = inputs.random_streamfunction_velocity_2d(N, seed=9)   # period 1 in x and y
+
+    def run(n, u0, X, links, w):
+        cfg = ibgm.Config(2, n, h, rho=1.0, mu=0.01, dt=0.01 / 512, precision=precision)
+        sim = ibgm.Simulation(cfg, u0, inputs.Structure(X, links, w))
+        sim.step(20)
+        assert sim.sync() == 20
+        st = sim.state()
+        sim.close()
+        return st
+
+    s1 = run((N, N, 1), u1, S.X, S.links, S.w)
+    shifts = [(0, 0), (1, 0), (0, 1), (1, 1)]
+    npts = S.X.shape[1]
+    X4 = np.concatenate([S.X + np.array([[dx], [dy]]) for dx, dy in shifts], axis=1)
+    a, b, kap, l0 = S.links
+    links4 = (np.concatenate([a + q * npts for q in range(4)]).astype(np.int32),
+              np.concatenate([b + q * npts for q in range(4)]).astype(np.int32),
+              np.tile(kap, 4), np.tile(l0, 4))
+    s4 = run((2 * N, 2 * N, 1), [np.tile(c, (1, 2, 2)) for c in u1], X4, links4, np.tile(S.w, 4))
+    for qx, qy in shifts:
+        sl = (slice(qy * N, (qy + 1) * N), slice(qx * N, (qx + 1) * N))
+        for c in range(2):
+            ref = np.asarray(s1["u"][c]).reshape(N, N)
+            got = np.asarray(s4["u"][c]).reshape(2 * N, 2 * N)[sl]
+            assert np.abs(got - ref).max() <= tol * np.abs(ref).max(), (qx, qy, c)
+        ref = np.asarray(s1["p"]).reshape(N, N)
+        got = np.asarray(s4["p"]).reshape(2 * N, 2 * N)[sl]
+        # p: the psi solves (condition number 1 + 4/h^2 in both runs) round
+        # differently on lines of 1024 than of 512
+        ptol = max(tol, (1 + 4 * N * N) * 2.0 ** -52) if precision == 0 else tol
+        assert np.abs(got - ref).max() <= ptol * np.abs(ref).max(), (qx, qy, "p")
+    for q, (dx, dy) in enumerate(shifts):
+        Xq = s4["X"][:, q * npts:(q + 1) * npts] - np.array([[dx], [dy]])
+        assert np.abs(Xq - s1["X"]).max() <= (1e-12 if precision == 0 else 1e-9)
