@@ -1,4 +1,4 @@
-"""Train and judge the learned closure on method-generated pairs.
+"""Train and evaluate the learned closure on method-generated pairs.
 
     python -m paper_1305_3976_amd.closure_run [--n-fine 256] [--traj 11] ...
 
@@ -7,7 +7,7 @@ with random smooth flow; each snapshot restarts a coarse run (n_fine/2, 2 dt)
 from the restricted fine state, takes one coarse step and pairs its fields
 with the restricted fine velocity two fine steps later.  The network trains on
 crops (valid convolutions with a 3-voxel margin) from the training
-trajectories; the held-out trajectories (about 10% of the seeds) judge it,
+trajectories; the held-out trajectories (about 10% of the seeds) evaluate it,
 once per interval and in a rollout where the correction is applied after
 every coarse step.  Prints one JSON line with the errors against the
 restricted fine solve and the per-step times of the fine solve, the plain

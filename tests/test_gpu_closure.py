@@ -236,7 +236,7 @@ def test_network_gradient_matches_oracle(mode):
 
 
 def test_closure_gain_on_held_out_trajectories():
-    """Small family (fine 64^3, coarse 32^3): train on 16 trajectories, judge
+    """Small family (fine 64^3, coarse 32^3): train on 16 trajectories, evaluate
     on 4 held-out ones; the corrected coarse velocity must be markedly closer
     to the restricted fine velocity than the plain coarse one."""
     ntr, nho, per = 16, 4, 12
