@@ -640,6 +640,19 @@ static void launch_explicit(ib_ctx *c, bool first) {
 // D.u of the velocity state (type V) into `out` (work type T).
 template <typename T, int DIM, typename V = T>
 static void launch_divergence(ib_ctx *c, void *out) {
+  const bool vec = c->g.n0 % 4 == 0 && aligned16(out) && aligned16(c->buf.u[0]) &&
+                   aligned16(c->buf.u[1]) && (DIM == 2 || aligned16(c->buf.u[2]));
+  if (vec) {
+    const dim3 grid((unsigned)((c->g.n0 / 4 + 63) / 64), (unsigned)((c->g.n1 + 3) / 4),
+                    (unsigned)c->g.n2);
+    launch(c, KP_DIVERGENCE, [&] {
+      hipLaunchKernelGGL((k_divergence4<V, DIM, T>), grid, dim3(64, 4), 0, c->stream,
+                         (const V *)c->buf.u[0], (const V *)c->buf.u[1],
+                         (const V *)(DIM == 3 ? c->buf.u[2] : nullptr), (T *)out, c->g,
+                         1.0 / c->prm.h);
+    });
+    return;
+  }
   launch(c, KP_DIVERGENCE, [&] {
     hipLaunchKernelGGL((k_divergence<V, DIM, T>), cell_grid(c->g),
                        dim3(64, 4), 0, c->stream, (const V *)c->buf.u[0],
