@@ -1,8 +1,29 @@
 """Shared test helpers: build oracle and GPU simulations from one seeded
 workload and compare fields with the paper's discrete l2 norms."""
+import importlib
+
 import numpy as np
 
 import oracle
+
+
+class LazyModule:
+    """A module imported on first attribute access.  GPU test modules bind
+    the HIP library through this, so that collecting them (on a machine
+    where the library is not built, with -m "not gpu") imports nothing;
+    on a GPU run the first use imports it and fails loudly if it is
+    missing."""
+
+    def __init__(self, name):
+        self._name = name
+        self._mod = None
+
+    def __getattr__(self, attr):
+        if attr.startswith("_"):
+            raise AttributeError(attr)
+        if self._mod is None:
+            self._mod = importlib.import_module(self._name)
+        return getattr(self._mod, attr)
 
 
 def rel_l2(a, b):

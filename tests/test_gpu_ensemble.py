@@ -7,8 +7,11 @@ import pytest
 import torch
 
 import oracle
-from paper_1305_3976_amd import ensemble, ibgm, inputs
-from helpers import rel_l2
+from paper_1305_3976_amd import inputs
+from helpers import LazyModule, rel_l2
+
+ensemble = LazyModule("paper_1305_3976_amd.ensemble")
+ibgm = LazyModule("paper_1305_3976_amd.ibgm")
 
 pytestmark = pytest.mark.gpu
 

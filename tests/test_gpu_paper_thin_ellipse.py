@@ -19,7 +19,10 @@ import os
 import numpy as np
 import pytest
 
-from paper_1305_3976_amd import ensemble, inputs
+from paper_1305_3976_amd import inputs
+from helpers import LazyModule
+
+ensemble = LazyModule("paper_1305_3976_amd.ensemble")
 
 pytestmark = pytest.mark.gpu
 
