@@ -19,7 +19,9 @@ class LazyModule:
         self._mod = None
 
     def __getattr__(self, attr):
-        if attr.startswith("_"):
+        # dunder lookups (pickling, introspection by pytest) must not import;
+        # the module's own private names (e.g. closure._p) are forwarded
+        if attr.startswith("__"):
             raise AttributeError(attr)
         if self._mod is None:
             self._mod = importlib.import_module(self._name)
@@ -65,3 +67,20 @@ def psi_vs_p(psi, psi_ref, p_ref):
     increment, often orders of magnitude smaller)."""
     scale = max(np.linalg.norm(psi_ref), np.linalg.norm(p_ref), 1e-30)
     return float(np.linalg.norm(np.asarray(psi) - np.asarray(psi_ref)) / scale)
+
+
+def field_maxabs(gpu_state, orc, dim):
+    """max |a - b| / max |b| per field: the point-wise companion of rel_l2,
+    which dilutes a fault in one cell by the square root of the cell count."""
+    def one(a, b):
+        a = np.asarray(a, dtype=np.float64)
+        b = np.asarray(b, dtype=np.float64)
+        return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-30))
+    errs = {}
+    for c in range(dim):
+        errs["u%d" % c] = one(gpu_state["u"][c], orc.u[c])
+    errs["p"] = one(gpu_state["p"], orc.p)
+    errs["X"] = one(gpu_state["X"], orc.X)
+    scale = max(np.abs(np.asarray(orc.psi)).max(), np.abs(np.asarray(orc.p)).max(), 1e-30)
+    errs["psi_vs_p"] = float(np.abs(np.asarray(gpu_state["psi"]) - np.asarray(orc.psi)).max() / scale)
+    return errs
