@@ -205,6 +205,33 @@ ib_status ib_spread(ib_ctx *ctx, const double *X, const double *F,
                     const double *w, int64_t npts, void *const f_out[3],
                     int32_t accumulate);
 
+/* Allocation-free spreading, for callers that cannot allocate device memory:
+ * code under stream capture, tight serving loops, hosts that forbid
+ * hipMalloc.  The same computation as ib_spread (the kernels are shared),
+ * without a context: the grid is given by `prm` (validated as for ib_init;
+ * dim, n, h and precision are used, precision choosing the grid dtype of
+ * f_out), and the point sort and tile tables live in a fixed device array of
+ * IB_SPREAD_STATIC_MAX_BYTES inside the library instead of a workspace.  That
+ * array is one per GPU, reserved when the library's code is loaded on the GPU
+ * and held until the process ends; its device address is looked up on the
+ * first call on each device.
+ *   X, F, w, npts, f_out, accumulate: as ib_spread (device pointers, FP64
+ *   points [dim][npts], weights [npts], f_out[c] [n2][n1][n0] grid dtype).
+ *   One problem only: 2-D needs n[2] = 1 (no batch layers).
+ *   hip_stream: hipStream_t to enqueue on (NULL = default stream).
+ * The tables take about (39 b + 44) npts + 12 ntiles bytes (b = 8 for
+ * IB_PREC_FP64, 4 otherwise; ntiles = prod ceil(n[a] / 8)), e.g. 24 MB for
+ * 65,536 points on a 256^3 FP64 grid; larger calls return IB_E_UNSUPPORTED
+ * and enqueue nothing.  The call allocates nothing and clears what must
+ * start at zero (the tile counts, and f_out unless accumulate) with kernels,
+ * not memset nodes.  Every call on one GPU shares that GPU's array: calls
+ * that overlap on one GPU (two streams, two host threads, two captured
+ * graphs in flight) race and must be serialised by the caller. */
+#define IB_SPREAD_STATIC_MAX_BYTES (32u << 20)
+ib_status ib_spread_static(const ib_grid_params *prm, const double *X, const double *F,
+                           const double *w, int64_t npts, void *const f_out[3],
+                           int32_t accumulate, void *hip_stream);
+
 /* The Eulerian force density f of Step 2b as spread in the last step taken
  * (at X^{n+1/2}), written densely into f_out[c] (grid dtype, zero where no
  * point reached).  Enqueued on the context's stream; IB_E_STATE before the

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -1063,6 +1064,136 @@ extern "C" ib_status ib_spread(ib_ctx *c, const double *X, const double *F, cons
   } else {
     if (c->dim == 2) launch_spread<double, 2, true>(c, X, F, w, npts, f_out);
     else launch_spread<double, 3, true>(c, X, F, w, npts, f_out);
+  }
+  HIP_TRY(hipGetLastError());
+  return IB_OK;
+}
+
+// ------------------------------------------- spreading without allocation --
+
+// The scratch of ib_spread_static: one fixed device array, a copy per GPU
+// that the library runs on, held until the process ends.  In host code the
+// name `scratch` is only a stand-in for the symbol (passing it to a kernel
+// would hand the device a host address): its device address is looked up
+// once per device, with that device current, and kept in g_scratch_dev.
+static __device__ __align__(256) unsigned char scratch[IB_SPREAD_STATIC_MAX_BYTES];
+constexpr int kScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_dev[kScratchDevices];
+
+static ib_status scratch_of_current_device(void **out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kScratchDevices)
+    return fail(IB_E_UNSUPPORTED, "device %d: the static spreading scratch tracks devices 0..%d",
+                dev, kScratchDevices - 1);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(IB_E_DEVICE, "hipGetSymbolAddress of the spreading scratch failed: %s",
+                  hipGetErrorString(e));
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return IB_OK;
+}
+
+// Spreading tables of `np` points on the grid of `p`, carved from `base`
+// (or counted, with base = nullptr): the sorted stencils (start cells,
+// weights, values), the tile counts, list and starts, the block sums of the
+// scan, the point sort (tile, rank) and the list length.
+static size_t carve_spread_tables(ib_ctx *c, const ib_grid_params *p, int64_t np, char *base) {
+  const size_t t = p->precision == IB_PREC_FP64 ? 8 : 4;
+  const size_t npp = (size_t)(np > 0 ? np : 1);
+  const TileGrid tg = tile_grid(p);
+  const size_t tb = align256(sizeof(int) * (size_t)tg.ntiles);
+  const size_t pb = align256(sizeof(int) * npp);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    void *q = base ? (void *)(base + off) : nullptr;
+    off += bytes;
+    return q;
+  };
+  void *st_base = take(align256(sizeof(int) * 9 * npp));
+  void *st_wt = take(align256(t * 36 * npp));
+  void *st_val = take(align256(t * 3 * npp));
+  void *t_count = take(tb);
+  void *t_list = take(tb);
+  void *t_start = take(align256(sizeof(int) * (size_t)(tg.ntiles + 1)));
+  void *t_bsum = take(align256(sizeof(int) * (size_t)((tg.ntiles + SCAN_TILE - 1) / SCAN_TILE)));
+  void *tile_of = take(pb);
+  void *rank_of = take(pb);
+  void *t_nlist = take(256);
+  if (c) {
+    c->tg = tg;
+    c->st_base = (int *)st_base;
+    c->st_wt = st_wt;
+    c->st_val = st_val;
+    c->t_count = (int *)t_count;
+    c->t_list = (int *)t_list;
+    c->t_start = (int *)t_start;
+    c->t_bsum = (int *)t_bsum;
+    c->tile_of = (int *)tile_of;
+    c->rank_of = (int *)rank_of;
+    c->t_nlist = (int *)t_nlist;
+  }
+  return off;
+}
+
+static void launch_zero_words(void *p, size_t bytes, hipStream_t st) {
+  const int64_t n = (int64_t)(bytes / 4);
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096));
+  hipLaunchKernelGGL(k_zero_words, dim3(grid), dim3(256), 0, st, (uint32_t *)p, n);
+}
+
+extern "C" ib_status ib_spread_static(const ib_grid_params *prm, const double *X, const double *F,
+                                      const double *w, int64_t npts, void *const f_out[3],
+                                      int32_t accumulate, void *hip_stream) {
+  ib_status s = check_params(prm);
+  if (s != IB_OK) return s;
+  if (prm->dim == 2 && prm->n[2] != 1)
+    return fail(IB_E_INVALID, "ib_spread_static takes one 2-D problem (n[2] = 1), not a batch");
+  if (npts < 0 || (npts > 0 && (!X || !F || !w)) || !f_out)
+    return fail(IB_E_INVALID, "bad spread arguments");
+  for (int i = 0; i < prm->dim; i++)
+    if (!f_out[i]) return fail(IB_E_INVALID, "null output component %d", i);
+  if (npts > IB_MAX_POINTS)
+    return fail(IB_E_UNSUPPORTED, "npts above IB_MAX_POINTS (32-bit sort ranks)");
+  const size_t need = carve_spread_tables(nullptr, prm, npts, nullptr);
+  if (need > (size_t)IB_SPREAD_STATIC_MAX_BYTES)
+    return fail(IB_E_UNSUPPORTED,
+                "%lld points on this grid need %zu bytes of spreading scratch, above the %zu "
+                "bytes of the static array (use ib_spread with a workspace)",
+                (long long)npts, need, (size_t)IB_SPREAD_STATIC_MAX_BYTES);
+  void *base = nullptr;
+  if ((s = scratch_of_current_device(&base)) != IB_OK) return s;
+  // a host-side description of the grid and the tables (no allocation)
+  ib_ctx c{};
+  c.prm = *prm;
+  c.stream = (hipStream_t)hip_stream;
+  c.dim = prm->dim;
+  c.g.n0 = prm->n[0];
+  c.g.n1 = prm->n[1];
+  c.g.n2 = prm->n[2];
+  c.g.ncell = (int64_t)c.g.n0 * c.g.n1 * c.g.n2;
+  c.f32 = prm->precision != IB_PREC_FP64;
+  c.tsz = c.f32 ? 4 : 8;
+  carve_spread_tables(&c, prm, npts, (char *)base);
+  // the array keeps the last call's contents: clear the tile counts (the
+  // binning counts with atomics) and, unless accumulating, the output
+  launch_zero_words(c.t_count, sizeof(int) * (size_t)c.tg.ntiles, c.stream);
+  if (!accumulate)
+    for (int i = 0; i < c.dim; i++) launch_zero_words(f_out[i], (size_t)c.g.ncell * c.tsz, c.stream);
+  if (npts > 0) {
+    if (c.f32) {
+      if (c.dim == 2) launch_spread<float, 2, true>(&c, X, F, w, npts, f_out);
+      else launch_spread<float, 3, true>(&c, X, F, w, npts, f_out);
+    } else {
+      if (c.dim == 2) launch_spread<double, 2, true>(&c, X, F, w, npts, f_out);
+      else launch_spread<double, 3, true>(&c, X, F, w, npts, f_out);
+    }
   }
   HIP_TRY(hipGetLastError());
   return IB_OK;

@@ -1797,4 +1797,12 @@ __global__ void __launch_bounds__(256) k_layer_mean(const double *partial, int n
   if (threadIdx.x == 0) mean[blockIdx.x] = red[0] / (double)per_layer;
 }
 
+// Clear n 32-bit words (grid-stride): the fill kernel that clears counters
+// and outputs in code a caller may capture into a graph, where memset nodes
+// are avoided.
+__global__ void __launch_bounds__(256) k_zero_words(uint32_t *p, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0u;
+}
+
 }  // namespace ibgm

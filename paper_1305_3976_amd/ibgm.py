@@ -71,6 +71,8 @@ def _load():
     L.ib_restart.argtypes = [_vp, ctypes.c_int64]
     L.ib_sync.argtypes = [_vp, ctypes.POINTER(ctypes.c_int64)]
     L.ib_spread.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int64, _vp * 3, ctypes.c_int32]
+    L.ib_spread_static.argtypes = [ctypes.POINTER(GridParams), _vp, _vp, _vp, ctypes.c_int64,
+                                   _vp * 3, ctypes.c_int32, _vp]
     L.ib_interp.argtypes = [_vp, _vp, ctypes.c_int64, _vp * 3, _vp]
     L.ib_force.argtypes = [_vp, _vp, _vp]
     L.ib_step_force.argtypes = [_vp, _vp * 3]
@@ -103,7 +105,8 @@ def _load():
     L.ib_closure_gather.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(f32), _ip, i32, _ip, _vp,
                                     i32, _ip, i32, i32, _vp, _vp]
     L.ib_closure_apply.argtypes = [ctypes.POINTER(_vp), _ip, _vp, f32, _vp]
-    for f in ("ib_workspace_size", "ib_init", "ib_step", "ib_restart", "ib_sync", "ib_spread", "ib_interp",
+    for f in ("ib_workspace_size", "ib_init", "ib_step", "ib_restart", "ib_sync", "ib_spread",
+              "ib_spread_static", "ib_interp",
               "ib_force", "ib_step_force", "ib_line_solve", "ib_destroy", "ib_profile_enable",
               "ib_profile_read", "ib_tune", "ib_tune_read", "ib_graph_create", "ib_graph_launch",
               "ib_graph_destroy") + CLOSURE_EXPORTED:
@@ -118,7 +121,8 @@ CLOSURE_EXPORTED = ("ib_conv3d_pack", "ib_conv3d_fwd", "ib_conv3d_bwd_data",
 
 lib = _load()
 
-EXPORTED = ("ib_workspace_size", "ib_init", "ib_step", "ib_restart", "ib_sync", "ib_spread", "ib_interp",
+EXPORTED = ("ib_workspace_size", "ib_init", "ib_step", "ib_restart", "ib_sync", "ib_spread",
+            "ib_spread_static", "ib_interp",
             "ib_force", "ib_step_force", "ib_line_solve", "ib_destroy", "ib_last_error",
             "ib_profile_enable",
             "ib_profile_count", "ib_profile_name", "ib_profile_read", "ib_tune", "ib_tune_read",
@@ -139,6 +143,23 @@ def _stream_handle(stream=None):
 def _ptr(t: torch.Tensor):
     assert t.is_cuda and t.is_contiguous()
     return _vp(t.data_ptr())
+
+
+def spread_static(cfg, X: torch.Tensor, F: torch.Tensor, w: torch.Tensor, out=None,
+                  accumulate=False, stream=None):
+    """Step 2b without a context or workspace (ib_spread_static): the force F
+    at points X (FP64 [dim][npts]) with weights w spread onto the grid of
+    `cfg` (one problem), the tables in the library's static device array."""
+    d = cfg.dim
+    if out is None:
+        out = [torch.empty(cfg.shape, dtype=cfg.grid_dtype, device=X.device) for _ in range(d)]
+    P = cfg.params()
+    ptrs = (_vp * 3)(*[out[c].data_ptr() if c < d else None for c in range(3)])
+    npts = X.shape[1]
+    args = [_ptr(X), _ptr(F), _ptr(w)] if npts > 0 else [None, None, None]
+    check(lib.ib_spread_static(ctypes.byref(P), *args, npts, ptrs, 1 if accumulate else 0,
+                               _stream_handle(stream)))
+    return out
 
 
 def line_solve(t: torch.Tensor, axis: int, diag: float, off: float, stream=None):
