@@ -191,6 +191,15 @@ ib_status ib_step(ib_ctx *ctx, int32_t nsteps);
  * captured from this context before the restart must be created again. */
 ib_status ib_restart(ib_ctx *ctx, int64_t step0);
 
+/* The caller changed u between steps (a learned correction added to the
+ * velocity, a rescale, a projection): recompute div_prev = D.u from the
+ * current u, the D.u^n term that the next step's pressure update (Step 3f,
+ * p += psi - chi mu (D.u^{n+1} + D.u^n)/2) averages with D.u^{n+1}.  Without
+ * it div_prev keeps D.u of the velocity the last step produced.  The step
+ * index and the rest of the state are kept.  Asynchronous, on the context's
+ * stream. */
+ib_status ib_refresh_divergence(ib_ctx *ctx);
+
 /* Wait for the stream; report the step index and IB_E_NONFINITE if any
  * position became non-finite since init. */
 ib_status ib_sync(ib_ctx *ctx, int64_t *step_index);

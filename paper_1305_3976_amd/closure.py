@@ -280,6 +280,9 @@ class CoarseFine:
             x = self.inputs_full(scales)
             y = net.forward(x, 1, (nc, nc, nc), PERIODIC)
             apply_correction(self.coarse.u, y, 1.0 / scales.target)
+            # the next step's pressure update averages D.u^{n+1} with D.u^n:
+            # recompute the latter from the corrected velocity
+            self.coarse.refresh_divergence()
 
     def spread_force(self):
         """The force density the coarse step spread (FP32 grid arrays)."""
@@ -488,3 +491,59 @@ def rollout(case, n_fine: int, steps: int, net: ConvNet, scales: Scales, warmup:
     plain.coarse.close()
     cf.close()
     return errs, t_plain / steps, t_corr / steps
+
+
+# ------------------------------------------------- guarded rollout (judge) --
+
+def guarded_rollout(case, n_fine: int, steps: int, net: ConvNet, scales: Scales,
+                    check_every: int = 4, warmup: int = 6):
+    """The closure in service, with the plain fine solve as its judge and its
+    fallback.  Three coarse runs start from the restricted fine state after
+    `warmup` fine steps: plain, corrected after every step, and guarded
+    (corrected too, but audited).  Every `check_every` coarse intervals the
+    judge compares the guarded and the plain coarse velocities with the
+    restricted fine one; where the correction has stopped winning (guarded
+    error above plain), the guarded run falls back on the fine solve: it
+    restarts from the restricted fine state, with the correction kept on.
+    Returns per interval (plain, corrected, guarded) relative l2 errors
+    against the restricted fine velocity, and the intervals where the
+    fallback fired."""
+    runs = [CoarseFine(case, n_fine)]
+    nc = runs[0].nc
+    cc = runs[0].coarse.cfg
+    for _ in range(2):
+        r = CoarseFine.__new__(CoarseFine)
+        r.__dict__.update(runs[0].__dict__)
+        r.coarse = ibgm.Simulation(cc, [np.zeros((nc, nc, nc))] * 3, case.structure,
+                                   device=runs[0].w.device)
+        r.ub = [torch.empty_like(t) for t in runs[0].ub]
+        r.f = None
+        runs.append(r)
+    judge, plain, corr = runs[0], runs[1], runs[2]
+    guard = judge  # the guarded run is the judge's own coarse companion
+    judge.fine_steps(warmup)
+    for r in (guard, plain, corr):
+        r.sync_coarse_to_fine()
+    host = lambda ts: [t.double().cpu().numpy() for t in ts]
+
+    def err(u, ref, nr):
+        return math.sqrt(sum(float(np.sum((x - y) ** 2)) for x, y in zip(host(u), ref))) / nr
+
+    errs, fired = [], []
+    for k in range(steps):
+        plain.coarse_step()
+        corr.coarse_step(net, scales)
+        guard.coarse_step(net, scales)
+        judge.fine_steps(2)
+        ref = host(judge.restricted_fine())
+        nr = math.sqrt(sum(float(np.sum(x ** 2)) for x in ref))
+        e = (err(plain.coarse.u, ref, nr), err(corr.coarse.u, ref, nr),
+             err(guard.coarse.u, ref, nr))
+        errs.append(e)
+        if (k + 1) % check_every == 0 and e[2] > e[0]:
+            guard.sync_coarse_to_fine()   # fall back on the fine solve
+            fired.append(k)
+    for r in (plain, corr):
+        r.coarse.close()
+    judge.close()
+    return errs, fired

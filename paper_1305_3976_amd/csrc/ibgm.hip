@@ -595,7 +595,7 @@ static dim3 cell_grid(const Grid &g) {
 }
 
 template <typename T, int DIM, typename V = T>
-static void launch_explicit(ib_ctx *c, bool first) {
+static ExplicitArgs<T, DIM, V> explicit_args(ib_ctx *c, bool first) {
   ExplicitArgs<T, DIM, V> a{};
   for (int i = 0; i < 3; i++) {
     a.u[i] = (const V *)(i < DIM ? c->buf.u[i] : nullptr);
@@ -618,6 +618,12 @@ static void launch_explicit(ib_ctx *c, bool first) {
   a.advect = !(c->prm.flags & IB_FLAG_NO_ADVECTION);
   a.walls = (c->prm.flags & IB_FLAG_WALLS_Y) ? 1 : 0;
   for (int i = 0; i < 3; i++) a.g_body[i] = i < DIM ? c->prm.body_force[i] : 0.0;
+  return a;
+}
+
+template <typename T, int DIM, typename V = T>
+static void launch_explicit(ib_ctx *c, bool first) {
+  ExplicitArgs<T, DIM, V> a = explicit_args<T, DIM, V>(c, first);
   if constexpr (DIM == 3) {
     if (c->g.n0 % EX == 0 && c->g.n1 % EY == 0 && c->g.ncell < INT32_MAX) {
       // one round of resident workgroups (c->resident3, from ib_init) split
@@ -709,12 +715,12 @@ static void enqueue_step(ib_ctx *c, bool overlap) {
   } else {
     enqueue_lagrangian<T, DIM, V>(c, first);
   }
-  // Steps 3a-3b
-  launch_explicit<T, DIM, V>(c, first);
   // split order of this step
   int order[3];
   const int shift = c->prm.rotate_split ? (int)(n % DIM) : 0;
   for (int s = 0; s < DIM; s++) order[s] = (s + shift) % DIM;
+  // Steps 3a-3b
+  launch_explicit<T, DIM, V>(c, first);
   // Steps 3c-3d (+z): delta form (1 - nu D_aa) d_a = d_{a-1}, u += d_last;
   // the momentum systems are well conditioned (|alpha| well below 1), so
   // their strided recurrences run in the storage precision
@@ -1021,6 +1027,14 @@ extern "C" ib_status ib_restart(ib_ctx *c, int64_t step0) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(IB_E_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
   }
+  return IB_OK;
+}
+
+extern "C" ib_status ib_refresh_divergence(ib_ctx *c) {
+  if (!c) return fail(IB_E_STATE, "null context");
+  seed_divergence(c);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(IB_E_DEVICE, "kernel launch failed: %s", hipGetErrorString(e));
   return IB_OK;
 }
 

@@ -817,6 +817,50 @@ __global__ void __launch_bounds__(256) k_explicit(ExplicitArgs<T, DIM, V> a) {
   }
 }
 
+// ----------------------------------------------- explicit momentum stencil --
+
+// Steps 3a-3b at one cell from three velocity planes held in LDS: returns
+// the Laplacian sum and N(u^n) of component ci (skew form, eq:nonlinear).
+// at(comp, slot, dx, dy) reads component comp on plane slot (sm: k-1,
+// s0: k, sp: k+1) at the in-plane neighbour (dx, dy) of this cell.  The
+// z neighbours of a plane are the slots; channel walls replace a tangential
+// component's y neighbour across the wall by its no-slip ghost -u.
+template <typename C, typename At>
+__device__ __forceinline__ void momentum_terms(const At &at, int ci, int sm, int s0, int sp,
+                                               bool wlo, bool whi, bool advect, C inv_h, C &lap,
+                                               C &N) {
+  constexpr int ox[3] = {1, 0, 0}, oy[3] = {0, 1, 0};
+  const int slm[3] = {s0, s0, sm}, slp[3] = {s0, s0, sp};
+  const C u0 = at(ci, s0, 0, 0);
+  C dv = 0, ad = 0;
+  lap = 0;
+#pragma unroll
+  for (int cj = 0; cj < 3; cj++) {
+    C up = at(ci, slp[cj], ox[cj], oy[cj]);
+    C um = at(ci, slm[cj], -ox[cj], -oy[cj]);
+    if (cj == 1 && ci != 1) {  // no-slip ghosts across a channel wall
+      if (whi) up = -u0;
+      if (wlo) um = -u0;
+    }
+    lap += up - C(2) * u0 + um;
+    if (!advect) continue;
+    if (cj == ci) {
+      const C ap = C(0.5) * (u0 + up), am = C(0.5) * (um + u0);
+      dv += ap * ap - am * am;
+      ad += C(0.5) * (ap * (up - u0) + am * (u0 - um));
+    } else {
+      // u_cj averaged along ci on the edges at this cell and one up along cj
+      const int spm = (ci == 2) ? sm : ((cj == 2) ? sp : s0);
+      const C Ua = C(0.5) * (at(cj, slm[ci], -ox[ci], -oy[ci]) + at(cj, s0, 0, 0));
+      const C Ub = C(0.5) * (at(cj, spm, ox[cj] - ox[ci], oy[cj] - oy[ci]) +
+                             at(cj, slp[cj], ox[cj], oy[cj]));
+      dv += Ub * C(0.5) * (u0 + up) - Ua * C(0.5) * (um + u0);
+      ad += C(0.5) * (Ub * (up - u0) + Ua * (u0 - um));
+    }
+  }
+  N = C(0.5) * (dv + ad) * inv_h;
+}
+
 // 3-D explicit step on a 2.5-D blocking: a workgroup owns an EX x EY tile of
 // (x, y) columns and marches a.ez planes along z; the host sizes ez so the
 // whole grid is one round of resident workgroups (no tail round), which
@@ -940,7 +984,7 @@ __global__ void __launch_bounds__(ENT) k_explicit3(ExplicitArgs<T, 3, V> a) {
     // 2. compute plane k from LDS
     const double ps0 = PS[pc];
     const double psm[3] = {PS[pc - 1], PS[pc - PW], ps_below};
-    const int dpl[3] = {1, EW, 0}, sl_m[3] = {s0, s0, sm}, sl_p[3] = {s0, s0, sp};
+    auto at = [&](int cp, int s, int dx, int dy) { return U[cp][s][c + dx + dy * EW]; };
 #pragma unroll
     for (int ci = 0; ci < 3; ci++) {
       if (wlo && ci == 1) {  // v on the wall face: not advanced
@@ -948,35 +992,8 @@ __global__ void __launch_bounds__(ENT) k_explicit3(ExplicitArgs<T, 3, V> a) {
         (a.nl[1] + kp)[cell] = T(0);
         continue;
       }
-      const C u0 = U[ci][s0][c];
-      C dv = 0, ad = 0, lap = 0;
-#pragma unroll
-      for (int cj = 0; cj < 3; cj++) {
-        C up = U[ci][sl_p[cj]][c + dpl[cj]];
-        C um = U[ci][sl_m[cj]][c - dpl[cj]];
-        if (cj == 1 && ci != 1) {  // no-slip ghosts across a channel wall
-          if (whi) up = -u0;
-          if (wlo) um = -u0;
-        }
-        lap += up - C(2) * u0 + um;
-        if (!a.advect) continue;
-        if (cj == ci) {
-          const C ap = C(0.5) * (u0 + up), am = C(0.5) * (um + u0);
-          dv += ap * ap - am * am;
-          ad += C(0.5) * (ap * (up - u0) + am * (u0 - um));
-        } else {
-          // u_cj averaged along ci on the edges at this cell and one up along cj
-          const C *Uj0 = U[cj][sl_m[ci]];
-          const C *Uj = U[cj][s0];
-          const C *Ujp = U[cj][sl_p[cj]];
-          const C *Ujpm = U[cj][(ci == 2) ? sm : ((cj == 2) ? sp : s0)];
-          const C Ua = C(0.5) * (Uj0[c - dpl[ci]] + Uj[c]);
-          const C Ub = C(0.5) * (Ujpm[c + dpl[cj] - dpl[ci]] + Ujp[c + dpl[cj]]);
-          dv += Ub * C(0.5) * (u0 + up) - Ua * C(0.5) * (um + u0);
-          ad += C(0.5) * (Ub * (up - u0) + Ua * (u0 - um));
-        }
-      }
-      const C N = C(0.5) * (dv + ad) * (C)a.inv_h;
+      C lap, N;
+      momentum_terms<C>(at, ci, sm, s0, sp, wlo, whi, a.advect != 0, (C)a.inv_h, lap, N);
       const C gp = (C)((ps0 - psm[ci]) * a.inv_h);
       const C Nh = a.first ? N : C(1.5) * N - C(0.5) * nlp[ci];
       const C d = (C)a.dt * (-Nh + ((C)a.mu * lap * (C)a.inv_h2 - gp + fc[ci]) * (C)a.inv_rho);

@@ -74,6 +74,7 @@ def _load():
     L.ib_spread_static.argtypes = [ctypes.POINTER(GridParams), _vp, _vp, _vp, ctypes.c_int64,
                                    _vp * 3, ctypes.c_int32, _vp]
     L.ib_interp.argtypes = [_vp, _vp, ctypes.c_int64, _vp * 3, _vp]
+    L.ib_refresh_divergence.argtypes = [_vp]
     L.ib_force.argtypes = [_vp, _vp, _vp]
     L.ib_step_force.argtypes = [_vp, _vp * 3]
     L.ib_line_solve.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
@@ -106,7 +107,7 @@ def _load():
                                     i32, _ip, i32, i32, _vp, _vp]
     L.ib_closure_apply.argtypes = [ctypes.POINTER(_vp), _ip, _vp, f32, _vp]
     for f in ("ib_workspace_size", "ib_init", "ib_step", "ib_restart", "ib_sync", "ib_spread",
-              "ib_spread_static", "ib_interp",
+              "ib_spread_static", "ib_interp", "ib_refresh_divergence",
               "ib_force", "ib_step_force", "ib_line_solve", "ib_destroy", "ib_profile_enable",
               "ib_profile_read", "ib_tune", "ib_tune_read", "ib_graph_create", "ib_graph_launch",
               "ib_graph_destroy") + CLOSURE_EXPORTED:
@@ -122,7 +123,7 @@ CLOSURE_EXPORTED = ("ib_conv3d_pack", "ib_conv3d_fwd", "ib_conv3d_bwd_data",
 lib = _load()
 
 EXPORTED = ("ib_workspace_size", "ib_init", "ib_step", "ib_restart", "ib_sync", "ib_spread",
-            "ib_spread_static", "ib_interp",
+            "ib_spread_static", "ib_interp", "ib_refresh_divergence",
             "ib_force", "ib_step_force", "ib_line_solve", "ib_destroy", "ib_last_error",
             "ib_profile_enable",
             "ib_profile_count", "ib_profile_name", "ib_profile_read", "ib_tune", "ib_tune_read",
@@ -313,6 +314,11 @@ class Simulation:
     def restart(self, step0: int = 0):
         """Continue from whatever the state tensors now hold, as step step0."""
         check(lib.ib_restart(self.ctx, step0))
+        return self
+
+    def refresh_divergence(self):
+        """Recompute div_prev = D.u after the caller changed u between steps."""
+        check(lib.ib_refresh_divergence(self.ctx))
         return self
 
     def sync(self) -> int:

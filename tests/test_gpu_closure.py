@@ -303,3 +303,26 @@ def test_network_forward_full_size_sampled():
     # FP32 sums of exact BF16 products; an activation whose FP32 and FP64
     # sums round to neighbouring BF16 values differs by 2^-8 of itself
     assert rel(np.array(mine), np.array(ref)) <= 1e-3
+
+
+def test_guard_falls_back_on_the_fine_solve():
+    """The fine solve judges the correction and is its fallback: with an
+    untrained network (whose corrections are noise) the audit finds the
+    guarded run behind the plain coarse run and restarts it from the
+    restricted fine state; right after every fallback the guarded run is
+    closer to the fine solve than the plain coarse run, and it ends closer
+    than the unguarded corrected run (64^3 fine, 32^3 coarse)."""
+    case = inputs.closure_family(1, seed=11, n_fine=64)[0]
+    cf = cl.CoarseFine(case, 64)
+    cf.fine_steps(6)
+    scales = cl.estimate_scales(cf)
+    cf.close()
+    net = cl.ConvNet(seed=3)          # untrained
+    errs, fired = cl.guarded_rollout(case, 64, 8, net, scales, check_every=2)
+    print("guarded rollout (plain, corrected, guarded):", errs, "fallbacks at", fired)
+    assert fired, "the audit never fired with an untrained correction"
+    for k in fired:
+        if k + 1 < len(errs):
+            assert errs[k + 1][2] < errs[k + 1][0], (k, errs[k + 1])
+    assert errs[-1][2] < errs[-1][1]
+    assert all(np.isfinite(e).all() for e in np.asarray(errs))

@@ -353,3 +353,39 @@ def test_two_by_two_tiling_at_1024(precision, tol):
     for q, (dx, dy) in enumerate(shifts):
         Xq = s4["X"][:, q * npts:(q + 1) * npts] - np.array([[dx], [dy]])
         assert np.abs(Xq - s1["X"]).max() <= (1e-12 if precision == 0 else 1e-9)
+
+
+@pytest.mark.parametrize("precision,tol", [(0, FP64_TOL), (1, MIXED_TOL)])
+def test_steps_after_changing_u_between_steps(precision, tol):
+    """A caller that changes u between steps (as the learned closure adds its
+    correction) calls ib_refresh_divergence; the following steps then equal
+    the oracle's steps started from that same state (the oracle forms the
+    D.u^n of Step 3f from u at the start of every step)."""
+    w = inputs.config_ellipse_64(steps=10)
+    w.u0 = inputs.random_streamfunction_velocity_2d(64, 4, 0.1, seed=31)
+    g = gpu_sim(w, precision)
+    g.step(10)
+    assert g.sync() == 10
+    # a smooth correction with a divergence of its own
+    h = 1.0 / 64
+    x = np.arange(64) * h
+    Y, Xg = np.meshgrid(x + 0.5 * h, x, indexing="ij")
+    corr = [0.01 * np.sin(2 * np.pi * (Xg + 2 * Y)), 0.01 * np.cos(2 * np.pi * (3 * Xg - Y))]
+    for c in range(2):
+        g.u[c] += torch.as_tensor(corr[c].reshape(g.u[c].shape)).to(g.u[c].dtype).to(g.u[c].device)
+    g.refresh_divergence()
+    st = g.state()
+    S = w.structure
+    P = oracle.make_params(2, w.n, w.h, rho=w.rho, mu=w.mu, dt=w.dt, chi=w.chi)
+    o = oracle.Sim(P, [np.asarray(c, dtype=np.float64) for c in st["u"]], st["X"], S.links, S.w,
+                   p=st["p"], psi=st["psi"],
+                   nl_prev=[np.asarray(c, dtype=np.float64) for c in st["nl_prev"]],
+                   U_prev=st["U_prev"], step=10)
+    g.step(5)
+    assert g.sync() == 15
+    o.advance(5)
+    errs = field_errors(g.state(), o, 2)
+    print("after a change of u, precision", precision, errs)
+    for k, e in errs.items():
+        assert e <= tol, (k, e)
+    g.close()
