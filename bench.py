@@ -89,14 +89,30 @@ def kernel_bytes(name: str, b: int, ncell: int, dim: int) -> float:
         "psi_x_first": 2 * b, "psi_s_first": 2 * b,
         "psi_x_plain": 2 * b, "psi_s_plain": 2 * b,
         "psi_x_pfinal": 5 * b + 16, "psi_s_pfinal": 5 * b + 16,
+        # mean of psi before the last sweep (FP32 work arrays): reads psi
+        "psi_gauge": b,
+        # FP64-state policy: u += d in FP64
+        "add_increment": (8 + b + 8) * dim,
     }.get(name)
     return None if per_cell is None else per_cell * ncell
 
 
-def step_bytes(b: int, ncell: int, dim: int) -> float:
+def model_step_bytes(b: int, ncell: int, dim: int) -> float:
+    """Algorithmic bytes of one step from the byte model of each of its kernels."""
     mom = (dim - 1) * 2 * b * dim + 3 * b * dim
-    psi = (dim + 1) * b + 2 * b + (dim - 2) * 2 * b + 5 * b + 16
+    psi = (dim + 1) * b + 2 * b + (dim - 2) * 2 * b + 5 * b + 16 + b  # (+ the psi gauge)
     return ((4 * dim + 1) * b + 8 + mom + psi) * ncell
+
+
+def step_bytes(kern: dict, b: int, ncell: int, dim: int, steps: int) -> float:
+    """Algorithmic bytes of one step as the timed steps ran it: the byte
+    model of every grid kernel times its launches, over the steps."""
+    tot = 0.0
+    for name, (_, cnt) in kern.items():
+        by = kernel_bytes(name, b, ncell, dim)
+        if by is not None:
+            tot += by * cnt
+    return tot / steps
 
 
 def run_gpu(w, precision, steps, warmup, tune=False, walls=False):
@@ -310,7 +326,7 @@ def run_ensemble(steps, spl_choices=(2, 10), seed=4):
         "ensemble_steps_per_s": round(timed / (ms * 1e-3), 2),
         "gcell_updates_per_s": round(cells * timed / (ms * 1e-3) / 1e9, 3),
         "ms_per_ensemble_step": round(ms / timed, 4),
-        "step_GB_s": round(step_bytes(4, cells, 2) / (ms / timed * 1e-3) / 1e9, 1),
+        "step_GB_s": round(model_step_bytes(4, cells, 2) / (ms / timed * 1e-3) / 1e9, 1),
         "best_variant": best,
         "variants_ms_per_step": {k: round(v / timed, 4) for k, v in variants.items()},
         "eager_ms_per_step": round(eager_ms / timed, 4),
@@ -474,8 +490,9 @@ def main():
         "gcell_updates_per_s": round(ncell * steps_s / 1e9, 3),
         "ms_per_step_profiled": round(ms / args.steps, 4),
         "wall_s_timed_region": round(wall, 3),
-        "step_alg_bytes_GB": round(step_bytes(b, ncell, w.dim) / 1e9, 4),
-        "step_GB_s": round(step_bytes(b, ncell, w.dim) / (ms_plain / args.steps * 1e-3) / 1e9, 1),
+        "step_alg_bytes_GB": round(step_bytes(kern, b, ncell, w.dim, args.steps) / 1e9, 4),
+        "step_GB_s": round(step_bytes(kern, b, ncell, w.dim, args.steps)
+                           / (ms_plain / args.steps * 1e-3) / 1e9, 1),
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
                      "traffic": (round(TRAFFIC_BYTES[dom] / 1e9, 4)
@@ -494,7 +511,8 @@ def main():
         line["fp64"] = {"value": round(s64, 3), "unit": "IB steps/s",
                         "ms_per_step": round(ms64_plain / args.steps, 4),
                         "gcell_updates_per_s": round(ncell * s64 / 1e9, 3),
-                        "step_GB_s": round(step_bytes(8, ncell, w.dim) / (ms64_plain / args.steps * 1e-3) / 1e9, 1),
+                        "step_GB_s": round(step_bytes(kern64, 8, ncell, w.dim, args.steps)
+                                           / (ms64_plain / args.steps * 1e-3) / 1e9, 1),
                         "kernels_avg_us": {k: round(t / c * 1e3, 2) for k, (t, c) in kern64.items()}}
         line["mixed_vs_fp64_speedup"] = round(steps_s / s64, 3)
     if not args.no_poisson:
