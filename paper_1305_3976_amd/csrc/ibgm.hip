@@ -557,14 +557,12 @@ static void launch_spread(ib_ctx *c, const double *X, const double *F, const dou
   });
   Stencils<T> stn{c->st_base, (T *)c->st_wt, (T *)c->st_val};
   const double inv_hd = 1.0 / std::pow(c->prm.h, DIM);
+  // placing the points and listing the touched tiles, one launch
+  const unsigned tb = (unsigned)((c->tg.ntiles + 255) / 256);
   launch(c, KP_SORT, [&] {
-    hipLaunchKernelGGL((k_scatter<T, DIM>), dim3(pb), dim3(256), 0, c->stream, c->tile_of,
-                       c->rank_of, c->t_start, X, F, w, stn, c->g, inv_h, inv_hd, np);
-  });
-  launch(c, KP_SORT, [&] {
-    hipLaunchKernelGGL((k_touch<DIM>), dim3((unsigned)((c->tg.ntiles + 255) / 256)), dim3(256),
-                       0, c->stream, c->t_start, ADD ? nullptr : c->t_flag, c->t_list,
-                       c->t_nlist, c->g, c->tg);
+    hipLaunchKernelGGL((k_scatter_touch<T, DIM>), dim3(pb + tb), dim3(256), 0, c->stream,
+                       c->tile_of, c->rank_of, c->t_start, X, F, w, stn, c->g, inv_h, inv_hd,
+                       np, (int)pb, ADD ? nullptr : c->t_flag, c->t_list, c->t_nlist, c->tg);
   });
   SpreadArgs<T, DIM> a{};
   a.st = stn;

@@ -305,12 +305,14 @@ __global__ void __launch_bounds__(256) k_force(ForceArgs<DIM> a) {
 // ----------------------------------------------------- Lagrangian: Step 2b --
 //
 // Spreading is an owner-computes gather over cubic tiles of TS cells:
-//  1. k_bin / k_scan_* / k_scatter counting-sort the points by the tile
+//  1. k_bin, the scan of the tile counts (k_scan_*) and scatter_point
+//     counting-sort the points by the tile
 //     of their anchor cell a = floor(X/h - 1/2) - 1 (per axis).  Every MAC
 //     component's 4-point stencil starts at a or a + 1, so a point touches
 //     cells a .. a+4 along each axis.
-//  2. k_touch lists the tiles some stencil reaches (and flags them for the
-//     explicit step); k_spread_tiles then collects, for each listed tile,
+//  2. touch_tile lists the tiles some stencil reaches (and flags them for
+//     the explicit step), in the same launch as scatter_point
+//     (k_scatter_touch); k_spread_tiles then collects, for each listed tile,
 //     every (point, stencil row) of the tiles whose anchors lie within 4
 //     cells below it that lands in the tile, accumulates in LDS and writes
 //     the tile's cells (store mode: f = sum; add mode: f += sum).  No
@@ -352,20 +354,26 @@ __global__ void __launch_bounds__(256) k_bin(const double *X, const int *layer, 
   }
   const int lane = (int)__lane_id();
   uint64_t todo = __ballot(valid);
-  int rank = 0;
+  int within = 0, leader_of = lane, ntile = 0;
   while (todo) {  // one pass per distinct tile among the wave's points
     const int leader = __builtin_ctzll(todo);
     const int tl = __shfl(t, leader);
     const uint64_t same = __ballot(valid && t == tl);
-    int base = 0;
-    if (lane == leader) base = atomicAdd(&count[tl], __popcll(same));
-    base = __shfl(base, leader);
-    if (valid && t == tl) rank = base + __popcll(same & ((1ull << lane) - 1ull));
+    if (valid && t == tl) {
+      within = __popcll(same & ((1ull << lane) - 1ull));
+      leader_of = leader;
+    }
+    if (lane == leader) ntile = __popcll(same);
     todo &= ~same;
   }
+  // the leaders' atomics all in flight at once (one round trip, not one per
+  // distinct tile), then every lane reads its leader's base
+  int base = 0;
+  if (ntile) base = atomicAdd(&count[t], ntile);
+  base = __shfl(base, leader_of);
   if (valid) {
     tile_of[k] = t;
-    rank_of[k] = rank;
+    rank_of[k] = base + within;
   }
 }
 
@@ -452,13 +460,12 @@ struct Stencils {
 };
 
 template <typename T, int DIM>
-__global__ void __launch_bounds__(256) k_scatter(const int *tile_of, const int *rank_of,
-                                                  const int *start, const double *X,
-                                                  const double *F, const double *w,
-                                                  Stencils<T> st, Grid g, double inv_h,
-                                                  double inv_hd, int64_t np) {
+__device__ __forceinline__ void scatter_point(int64_t k, const int *tile_of, const int *rank_of,
+                                              const int *start, const double *X,
+                                              const double *F, const double *w,
+                                              Stencils<T> st, Grid g, double inv_h,
+                                              double inv_hd, int64_t np) {
   using C = T;
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= np) return;
   const int64_t d = start[tile_of[k]] + rank_of[k];
   const int32_t nn[3] = {g.n0, g.n1, g.n2};
@@ -493,12 +500,13 @@ __device__ __forceinline__ int source_tiles(int lo, int hi, int n, int list[3]) 
 // tile's flag records whether f holds force there.  A wave reserves the
 // list slots of all its touched tiles with one atomic (consecutive slots in
 // lane order) instead of one atomic per tile on the shared counter.
+// (t: the tile of this thread; every lane of the wave calls it, for the
+// ballot)
 template <int DIM>
-__global__ void __launch_bounds__(256) k_touch(const int *start, int *flag, int *list,
-                                                int *nlist, Grid g, TileGrid tg) {
+__device__ __forceinline__ void touch_tile(int t, const int *start, int *flag, int *list,
+                                           int *nlist, Grid g, TileGrid tg) {
   // tile counts stay below 2^31 (at most (1024/8)^3 tiles, or 128^2 tiles
   // times 65535 layers in 2-D), so the index arithmetic is 32-bit
-  const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
   bool hit = false;
   if (t < tg.ntiles) {  // every lane stays for the ballot below
     const int32_t nn[3] = {g.n0, g.n1, g.n2};
@@ -539,6 +547,25 @@ __global__ void __launch_bounds__(256) k_touch(const int *start, int *flag, int 
   if (lane == leader) base = atomicAdd(nlist, __popcll(m));
   base = __shfl(base, leader);
   if (hit) list[base + __popcll(m & ((1ull << lane) - 1ull))] = (int)t;
+}
+
+// One launch for the two passes that need only the tile starts: workgroups
+// [0, pblocks) place the points (scatter_point), the rest list the touched
+// tiles (touch_tile).
+template <typename T, int DIM>
+__global__ void __launch_bounds__(256) k_scatter_touch(const int *tile_of, const int *rank_of,
+                                                        const int *start, const double *X,
+                                                        const double *F, const double *w,
+                                                        Stencils<T> st, Grid g, double inv_h,
+                                                        double inv_hd, int64_t np, int pblocks,
+                                                        int *flag, int *list, int *nlist,
+                                                        TileGrid tg) {
+  if ((int)blockIdx.x < pblocks)
+    scatter_point<T, DIM>((int64_t)blockIdx.x * blockDim.x + threadIdx.x, tile_of, rank_of, start,
+                          X, F, w, st, g, inv_h, inv_hd, np);
+  else
+    touch_tile<DIM>((int)((blockIdx.x - pblocks) * blockDim.x + threadIdx.x), start, flag, list,
+                    nlist, g, tg);
 }
 
 template <typename T, int DIM>
