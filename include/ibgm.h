@@ -84,6 +84,13 @@ typedef enum {
  * above 256).  Lagrangian points must stay at least 2h from the walls (the
  * 4-point stencils then never reach across them); nothing checks this. */
 #define IB_FLAG_WALLS_Y 2
+/* Deterministic spreading (Step 2b): the points of each spreading tile are
+ * put in point-index order and every grid cell adds its contributions in one
+ * fixed order without atomics, so every step -- and a restart from a saved
+ * state -- is bitwise reproducible run to run.  Slower spreading (each cell
+ * visits every candidate point of its tile); for verification, not speed.
+ * Without it the sums are formed with atomics and their last bits vary. */
+#define IB_FLAG_DETERMINISTIC_SPREAD 4
 
 /* Largest number of immersed points per context: points are sorted by tile
  * with 32-bit counts and ranks. */
@@ -201,8 +208,17 @@ ib_status ib_restart(ib_ctx *ctx, int64_t step0);
 ib_status ib_refresh_divergence(ib_ctx *ctx);
 
 /* Wait for the stream; report the step index and IB_E_NONFINITE if any
- * position became non-finite since init. */
+ * position became non-finite since init, or if the velocity u or the
+ * pressure p now holds a non-finite value (the message names the field; a
+ * scan of the grid fields on the stream, about the cost of reading u and p
+ * once). */
 ib_status ib_sync(ib_ctx *ctx, int64_t *step_index);
+
+/* Grid-field watchdog on demand: wait for the stream, scan u (every
+ * component) and p, and write max |u| over all faces to *max_abs_u (host;
+ * the CFL number of the step is max |u| dt / h).  IB_E_NONFINITE if u or p
+ * holds a non-finite value (*max_abs_u then covers the finite values). */
+ib_status ib_check_fields(ib_ctx *ctx, double *max_abs_u);
 
 /* Step 2b on given buffers: f_out[c] (+)= sum_k F[c][k] w[k] delta_h(x - X_k)
  * for the context's grid.  X, F, w: FP64 device [dim][npts], [npts], npts at
@@ -219,7 +235,8 @@ ib_status ib_spread(ib_ctx *ctx, const double *X, const double *F,
  * hipMalloc.  The same computation as ib_spread (the kernels are shared),
  * without a context: the grid is given by `prm` (validated as for ib_init;
  * dim, n, h and precision are used, precision choosing the grid dtype of
- * f_out), and the point sort and tile tables live in a fixed device array of
+ * f_out; IB_FLAG_DETERMINISTIC_SPREAD in flags is honoured), and the point
+ * sort and tile tables live in a fixed device array of
  * IB_SPREAD_STATIC_MAX_BYTES inside the library instead of a workspace.  That
  * array is one per GPU, reserved when the library's code is loaded on the GPU
  * and held until the process ends; its device address is looked up on the
@@ -228,7 +245,7 @@ ib_status ib_spread(ib_ctx *ctx, const double *X, const double *F,
  *   points [dim][npts], weights [npts], f_out[c] [n2][n1][n0] grid dtype).
  *   One problem only: 2-D needs n[2] = 1 (no batch layers).
  *   hip_stream: hipStream_t to enqueue on (NULL = default stream).
- * The tables take about (39 b + 44) npts + 12 ntiles bytes (b = 8 for
+ * The tables take about (39 b + 48) npts + 12 ntiles bytes (b = 8 for
  * IB_PREC_FP64, 4 otherwise; ntiles = prod ceil(n[a] / 8)), e.g. 24 MB for
  * 65,536 points on a 256^3 FP64 grid; larger calls return IB_E_UNSUPPORTED
  * and enqueue nothing.  The call allocates nothing and clears what must

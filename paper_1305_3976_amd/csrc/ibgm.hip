@@ -101,6 +101,7 @@ struct ib_ctx {
   // spreading tiles
   TileGrid tg;
   int *t_count, *t_start, *t_flag, *t_bsum, *t_list, *t_nlist, *tile_of, *rank_of;
+  int *point_of;  // deterministic spreading: the point in each sorted slot
   int *st_base;
   void *st_wt, *st_val;
   // structure (library allocation)
@@ -417,7 +418,7 @@ static ib_status check_params(const ib_grid_params *p) {
   if (p->step0 < 0) return fail(IB_E_INVALID, "step0 must be >= 0");
   for (int a = 0; a < 3; a++)
     if (!std::isfinite(p->body_force[a])) return fail(IB_E_INVALID, "body_force must be finite");
-  if (p->flags & ~(IB_FLAG_NO_ADVECTION | IB_FLAG_WALLS_Y))
+  if (p->flags & ~(IB_FLAG_NO_ADVECTION | IB_FLAG_WALLS_Y | IB_FLAG_DETERMINISTIC_SPREAD))
     return fail(IB_E_INVALID, "unknown flags 0x%x", p->flags);
   if (p->flags & IB_FLAG_WALLS_Y) {
     const int n1 = p->n[1];
@@ -441,7 +442,8 @@ static TileGrid tile_grid(const ib_grid_params *p) {
 // (FP64 [dim][np]); the per-point stencils in sorted order (start cells, 4
 // weights per component and axis, spread values); the spreading tile tables
 // (counts, flags, touched list, starts, block sums), the point sort (tile,
-// rank); the touched-list length; one status word.
+// rank, and the point of each slot in the deterministic order); the
+// touched-list length; one status word.
 // psi gauge (mixed policies): per layer, gauge_blocks() partial sums and the mean
 static int64_t gauge_layers(const ib_grid_params *p) { return p->dim == 2 ? p->n[2] : 1; }
 static int64_t gauge_blocks(int64_t per_layer) {  // ~4096 values per block, 1..4096 blocks
@@ -464,7 +466,7 @@ static size_t workspace_bytes(const ib_grid_params *p, int64_t np) {
   return 7 * align256(nc * t) + 3 * align256(lag) + align256(sizeof(int) * 9 * npp) +
          align256(t * 36 * npp) + align256(t * 3 * npp) + 3 * align256(sizeof(int) * tg.ntiles) +
          align256(sizeof(int) * (tg.ntiles + 1)) + align256(sizeof(int) * nb) +
-         2 * align256(sizeof(int) * npp) + 256 + 256 + gauge_bytes(p);
+         3 * align256(sizeof(int) * npp) + 256 + 256 + gauge_bytes(p);
 }
 
 extern "C" ib_status ib_workspace_size(const ib_grid_params *prm, int64_t n_points,
@@ -557,12 +559,24 @@ static void launch_spread(ib_ctx *c, const double *X, const double *F, const dou
   });
   Stencils<T> stn{c->st_base, (T *)c->st_wt, (T *)c->st_val};
   const double inv_hd = 1.0 / std::pow(c->prm.h, DIM);
-  // placing the points and listing the touched tiles, one launch
   const unsigned tb = (unsigned)((c->tg.ntiles + 255) / 256);
+  const bool det = (c->prm.flags & IB_FLAG_DETERMINISTIC_SPREAD) != 0;
+  if (det) {  // each tile's points in point-index order
+    launch(c, KP_SORT, [&] {
+      hipLaunchKernelGGL(k_place, dim3(pb), dim3(256), 0, c->stream, c->tile_of, c->rank_of,
+                         c->t_start, c->point_of, np);
+    });
+    launch(c, KP_SORT, [&] {
+      hipLaunchKernelGGL(k_order_tiles, dim3(tb), dim3(256), 0, c->stream, c->t_start,
+                         c->point_of, c->tg.ntiles);
+    });
+  }
+  // placing the points and listing the touched tiles, one launch
   launch(c, KP_SORT, [&] {
     hipLaunchKernelGGL((k_scatter_touch<T, DIM>), dim3(pb + tb), dim3(256), 0, c->stream,
-                       c->tile_of, c->rank_of, c->t_start, X, F, w, stn, c->g, inv_h, inv_hd,
-                       np, (int)pb, ADD ? nullptr : c->t_flag, c->t_list, c->t_nlist, c->tg);
+                       c->tile_of, c->rank_of, c->t_start, det ? c->point_of : nullptr, X, F, w,
+                       stn, c->g, inv_h, inv_hd, np, (int)pb, ADD ? nullptr : c->t_flag,
+                       c->t_list, c->t_nlist, c->tg);
   });
   SpreadArgs<T, DIM> a{};
   a.st = stn;
@@ -579,7 +593,9 @@ static void launch_spread(ib_ctx *c, const double *X, const double *F, const dou
   // more latency; sparse ones keep 256 so small tiles do not idle threads
   const bool dense = np > 4 * c->tg.ntiles;
   launch(c, KP_SPREAD, [&] {
-    if (dense)
+    if (det)
+      hipLaunchKernelGGL((k_spread_det<T, DIM, ADD>), dim3(grid), dim3(256), 0, c->stream, a);
+    else if (dense)
       hipLaunchKernelGGL((k_spread_tiles<T, DIM, ADD, 1024>), dim3(grid), dim3(1024), 0, c->stream, a);
     else
       hipLaunchKernelGGL((k_spread_tiles<T, DIM, ADD, 256>), dim3(grid), dim3(256), 0, c->stream, a);
@@ -951,6 +967,7 @@ extern "C" ib_status ib_init(ib_ctx **out, const ib_grid_params *prm, const ib_b
   c->t_bsum = (int *)w; w += align256(sizeof(int) * ((c->tg.ntiles + SCAN_TILE - 1) / SCAN_TILE));
   c->tile_of = (int *)w; w += pb;
   c->rank_of = (int *)w; w += pb;
+  c->point_of = (int *)w; w += pb;
   c->t_nlist = (int *)w; w += 256;
   c->flag = (int *)w; w += 256;
   c->gauge = (double *)w;  // [layers] means, then [layers][gauge_blocks] partials
@@ -1045,6 +1062,50 @@ extern "C" ib_status ib_step(ib_ctx *c, int32_t nsteps) {
   return IB_OK;
 }
 
+// Clear `bytes` (a multiple of 4) with a fill kernel (no memset node).
+static void launch_zero_words(void *p, size_t bytes, hipStream_t st) {
+  const int64_t n = (int64_t)(bytes / 4);
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096));
+  hipLaunchKernelGGL(k_zero_words, dim3(grid), dim3(256), 0, st, (uint32_t *)p, n);
+}
+
+// Scan the grid fields (k_field_check) on the context's stream and wait:
+// bit 1 of *bad = a velocity component is non-finite, bit 2 = p is; *umax =
+// max |u| over all faces.  Uses bytes 8..23 of the status region.
+static ib_status check_fields(ib_ctx *c, unsigned *bad, double *umax) {
+  unsigned *flags = (unsigned *)((char *)c->flag + 8);
+  unsigned long long *bits = (unsigned long long *)((char *)c->flag + 16);
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((c->g.ncell + 255) / 256, 2048));
+  launch_zero_words(flags, 16, c->stream);
+  const double *p = c->buf.p;
+  if (c->u64 || !c->f32) {
+    const double *u0 = (const double *)c->buf.u[0], *u1 = (const double *)c->buf.u[1],
+                 *u2 = (const double *)(c->dim == 3 ? c->buf.u[2] : c->buf.u[0]);
+    if (c->dim == 3) hipLaunchKernelGGL((k_field_check<double, 3>), dim3(grid), dim3(256), 0, c->stream, u0, u1, u2, p, c->g.ncell, flags, bits);
+    else hipLaunchKernelGGL((k_field_check<double, 2>), dim3(grid), dim3(256), 0, c->stream, u0, u1, u2, p, c->g.ncell, flags, bits);
+  } else {
+    const float *u0 = (const float *)c->buf.u[0], *u1 = (const float *)c->buf.u[1],
+                *u2 = (const float *)(c->dim == 3 ? c->buf.u[2] : c->buf.u[0]);
+    if (c->dim == 3) hipLaunchKernelGGL((k_field_check<float, 3>), dim3(grid), dim3(256), 0, c->stream, u0, u1, u2, p, c->g.ncell, flags, bits);
+    else hipLaunchKernelGGL((k_field_check<float, 2>), dim3(grid), dim3(256), 0, c->stream, u0, u1, u2, p, c->g.ncell, flags, bits);
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  unsigned long long host[2] = {0, 0};
+  HIP_TRY(hipMemcpy(host, (char *)c->flag + 8, 16, hipMemcpyDeviceToHost));
+  *bad = (unsigned)(host[0] & 0xffffffffu);
+  double m;
+  std::memcpy(&m, &host[1], sizeof(double));
+  *umax = m;
+  return IB_OK;
+}
+
+static ib_status nonfinite_fields(const ib_ctx *c, unsigned bad) {
+  return fail(IB_E_NONFINITE, "%s%s%s became non-finite (step <= %lld)",
+              (bad & 1u) ? "the velocity u" : "", (bad & 3u) == 3u ? " and " : "",
+              (bad & 2u) ? "the pressure p" : "", (long long)c->step);
+}
+
 extern "C" ib_status ib_sync(ib_ctx *c, int64_t *step_index) {
   if (!c) return fail(IB_E_STATE, "null context");
   HIP_TRY(hipStreamSynchronize(c->stream));
@@ -1053,6 +1114,21 @@ extern "C" ib_status ib_sync(ib_ctx *c, int64_t *step_index) {
   HIP_TRY(hipMemcpy(&flag, c->flag, sizeof(int), hipMemcpyDeviceToHost));
   if (flag) return fail(IB_E_NONFINITE, "a Lagrangian position became non-finite (step <= %lld)",
                         (long long)c->step);
+  unsigned bad = 0;
+  double umax = 0.0;
+  ib_status s = check_fields(c, &bad, &umax);
+  if (s != IB_OK) return s;
+  if (bad) return nonfinite_fields(c, bad);
+  return IB_OK;
+}
+
+extern "C" ib_status ib_check_fields(ib_ctx *c, double *max_abs_u) {
+  if (!c) return fail(IB_E_STATE, "null context");
+  if (!max_abs_u) return fail(IB_E_INVALID, "null output");
+  unsigned bad = 0;
+  ib_status s = check_fields(c, &bad, max_abs_u);
+  if (s != IB_OK) return s;
+  if (bad) return nonfinite_fields(c, bad);
   return IB_OK;
 }
 
@@ -1137,6 +1213,7 @@ static size_t carve_spread_tables(ib_ctx *c, const ib_grid_params *p, int64_t np
   void *t_bsum = take(align256(sizeof(int) * (size_t)((tg.ntiles + SCAN_TILE - 1) / SCAN_TILE)));
   void *tile_of = take(pb);
   void *rank_of = take(pb);
+  void *point_of = take(pb);
   void *t_nlist = take(256);
   if (c) {
     c->tg = tg;
@@ -1149,15 +1226,10 @@ static size_t carve_spread_tables(ib_ctx *c, const ib_grid_params *p, int64_t np
     c->t_bsum = (int *)t_bsum;
     c->tile_of = (int *)tile_of;
     c->rank_of = (int *)rank_of;
+    c->point_of = (int *)point_of;
     c->t_nlist = (int *)t_nlist;
   }
   return off;
-}
-
-static void launch_zero_words(void *p, size_t bytes, hipStream_t st) {
-  const int64_t n = (int64_t)(bytes / 4);
-  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096));
-  hipLaunchKernelGGL(k_zero_words, dim3(grid), dim3(256), 0, st, (uint32_t *)p, n);
 }
 
 extern "C" ib_status ib_spread_static(const ib_grid_params *prm, const double *X, const double *F,

@@ -460,14 +460,17 @@ struct Stencils {
 };
 
 template <typename T, int DIM>
-__device__ __forceinline__ void scatter_point(int64_t k, const int *tile_of, const int *rank_of,
-                                              const int *start, const double *X,
-                                              const double *F, const double *w,
+__device__ __forceinline__ void scatter_point(int64_t i, const int *tile_of, const int *rank_of,
+                                              const int *start, const int *point_of,
+                                              const double *X, const double *F, const double *w,
                                               Stencils<T> st, Grid g, double inv_h,
                                               double inv_hd, int64_t np) {
   using C = T;
-  if (k >= np) return;
-  const int64_t d = start[tile_of[k]] + rank_of[k];
+  if (i >= np) return;
+  // i is a point (slot start[tile] + rank) or, with point_of (the
+  // deterministic order), a slot whose point point_of[i] is
+  const int64_t k = point_of ? point_of[i] : i;
+  const int64_t d = point_of ? i : start[tile_of[k]] + rank_of[k];
   const int32_t nn[3] = {g.n0, g.n1, g.n2};
   double xk[DIM];
   for (int ax = 0; ax < DIM; ax++) xk[ax] = X[ax * np + k];
@@ -554,18 +557,46 @@ __device__ __forceinline__ void touch_tile(int t, const int *start, int *flag, i
 // tiles (touch_tile).
 template <typename T, int DIM>
 __global__ void __launch_bounds__(256) k_scatter_touch(const int *tile_of, const int *rank_of,
-                                                        const int *start, const double *X,
-                                                        const double *F, const double *w,
-                                                        Stencils<T> st, Grid g, double inv_h,
-                                                        double inv_hd, int64_t np, int pblocks,
-                                                        int *flag, int *list, int *nlist,
-                                                        TileGrid tg) {
+                                                        const int *start, const int *point_of,
+                                                        const double *X, const double *F,
+                                                        const double *w, Stencils<T> st, Grid g,
+                                                        double inv_h, double inv_hd, int64_t np,
+                                                        int pblocks, int *flag, int *list,
+                                                        int *nlist, TileGrid tg) {
   if ((int)blockIdx.x < pblocks)
     scatter_point<T, DIM>((int64_t)blockIdx.x * blockDim.x + threadIdx.x, tile_of, rank_of, start,
-                          X, F, w, st, g, inv_h, inv_hd, np);
+                          point_of, X, F, w, st, g, inv_h, inv_hd, np);
   else
     touch_tile<DIM>((int)((blockIdx.x - pblocks) * blockDim.x + threadIdx.x), start, flag, list,
                     nlist, g, tg);
+}
+
+// Deterministic order (IB_FLAG_DETERMINISTIC_SPREAD).  The ranks k_bin
+// hands out within a tile depend on the order in which waves reach the tile
+// counters; here every point is first placed at its slot (point_of), then
+// each tile's points are put in point-index order (one thread per tile,
+// insertion sort of the tile's few points), so the sorted order -- and the
+// order in which k_spread_det adds them -- no longer depends on scheduling.
+__global__ void __launch_bounds__(256) k_place(const int *tile_of, const int *rank_of,
+                                               const int *start, int *point_of, int64_t np) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < np) point_of[start[tile_of[k]] + rank_of[k]] = (int)k;
+}
+
+__global__ void __launch_bounds__(256) k_order_tiles(const int *start, int *point_of,
+                                                     int64_t ntiles) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntiles) return;
+  const int b = start[t], e = start[t + 1];
+  for (int i = b + 1; i < e; i++) {
+    const int v = point_of[i];
+    int j = i - 1;
+    while (j >= b && point_of[j] > v) {
+      point_of[j + 1] = point_of[j];
+      j--;
+    }
+    point_of[j + 1] = v;
+  }
 }
 
 template <typename T, int DIM>
@@ -714,6 +745,107 @@ __global__ void __launch_bounds__(NT) k_spread_tiles(SpreadArgs<T, DIM> a) {
       for (int c = 0; c < DIM; c++) {
         if (ADD) a.f[c][idx] = (T)((A)a.f[c][idx] + acc[c][i]);
         else a.f[c][idx] = (T)acc[c][i];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Deterministic spreading: the same tiles and candidates as k_spread_tiles,
+// but no atomics -- each thread owns cells of the tile and adds, in the fixed
+// candidate order (source tiles in a fixed order, points in slot order), the
+// stencil weight every candidate puts on its cell, in FP64 registers.  Every
+// cell's sum is then formed in one order, whatever the scheduling.  (Each
+// cell visits every candidate: a mode for verification and bitwise restarts,
+// not for speed.)
+template <typename T, int DIM, bool ADD>
+__global__ void __launch_bounds__(256) k_spread_det(SpreadArgs<T, DIM> a) {
+  using C = T;
+  constexpr int CELLS = DIM == 3 ? TS * TS * TS : TS * TS;
+  constexpr int PER = (CELLS + 255) / 256;
+  __shared__ int c_start[27], c_pref[28], s_list[3][3], s_len[3], s_cnt[27];
+  const int32_t nn[3] = {a.g.n0, a.g.n1, a.g.n2};
+  int ntodo = *a.nlist;
+  ntodo = ntodo < a.tg.ntiles ? ntodo : (int)a.tg.ntiles;
+  for (int e = blockIdx.x; e < ntodo; e += gridDim.x) {
+    const int64_t t = a.list[e];
+    const int tc[3] = {(int)(t % a.tg.nt[0]), (int)((t / a.tg.nt[0]) % a.tg.nt[1]),
+                       (int)(t / ((int64_t)a.tg.nt[0] * a.tg.nt[1]))};
+    int lo[3], hi[3];
+    for (int ax = 0; ax < 3; ax++) {
+      lo[ax] = ax < DIM ? tc[ax] * TS : tc[ax];
+      hi[ax] = ax < DIM ? min(nn[ax], lo[ax] + TS) : lo[ax] + 1;
+    }
+    if (threadIdx.x < 3) {
+      const int ax = threadIdx.x;
+      if (ax >= DIM) {
+        s_list[ax][0] = tc[ax];
+        s_len[ax] = 1;
+      } else {
+        int l3[3];
+        const int len = source_tiles(lo[ax], hi[ax], nn[ax], l3);
+        for (int q = 0; q < len; q++) s_list[ax][q] = l3[q];
+        s_len[ax] = len;
+      }
+    }
+    __syncthreads();
+    const int ncomb = s_len[0] * s_len[1] * s_len[2];
+    if (threadIdx.x < ncomb) {
+      const int m = threadIdx.x;
+      const int i0 = m % s_len[0], i1 = (m / s_len[0]) % s_len[1], i2 = m / (s_len[0] * s_len[1]);
+      const int64_t tt = s_list[0][i0] + (int64_t)a.tg.nt[0] *
+                                             (s_list[1][i1] + (int64_t)a.tg.nt[1] * s_list[2][i2]);
+      const int s0 = a.start[tt];
+      c_start[m] = s0;
+      s_cnt[m] = a.start[tt + 1] - s0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int pref = 0;
+      for (int m = 0; m < ncomb; m++) {
+        c_pref[m] = pref;
+        pref += s_cnt[m];
+      }
+      c_pref[ncomb] = pref;
+    }
+    __syncthreads();
+    const int npts = c_pref[ncomb];
+    const int64_t np = a.np;
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+      const int i = threadIdx.x + q * 256;
+      if (i >= CELLS) break;
+      const int g3[3] = {lo[0] + i % TS, lo[1] + (i / TS) % TS, DIM == 3 ? lo[2] + i / (TS * TS) : lo[2]};
+      if (g3[0] >= hi[0] || g3[1] >= hi[1] || g3[2] >= hi[2]) continue;
+      double acc[DIM];
+      for (int c = 0; c < DIM; c++) acc[c] = 0.0;
+      int slot = 0;
+      for (int pi = 0; pi < npts; pi++) {
+        while (c_pref[slot + 1] <= pi) slot++;
+        const int64_t k = c_start[slot] + (pi - c_pref[slot]);
+        for (int c = 0; c < DIM; c++) {
+          // offset of this cell in the point's stencil along each axis
+          int off[3] = {0, 0, 0};
+          bool in = true;
+          for (int ax = 0; ax < DIM; ax++) {
+            int o = g3[ax] - a.st.base[(c * 3 + ax) * np + k];
+            o += o < 0 ? nn[ax] : 0;  // base < n, cell < n: one wrap at most
+            in &= o < 4;
+            off[ax] = o;
+          }
+          if (!in) continue;
+          // the product in k_spread_tiles' order: (value z-weight) y-weight,
+          // then times the x-weight
+          C rw = a.st.val[c * np + k];
+          if (DIM == 3) rw = rw * a.st.wt[((c * 3 + 2) * 4 + off[2]) * np + k];
+          rw = rw * a.st.wt[((c * 3 + 1) * 4 + off[1]) * np + k];
+          acc[c] += (double)(rw * a.st.wt[((c * 3 + 0) * 4 + off[0]) * np + k]);
+        }
+      }
+      const int64_t idx = g3[0] + (int64_t)nn[0] * (g3[1] + (int64_t)nn[1] * g3[2]);
+      for (int c = 0; c < DIM; c++) {
+        if (ADD) a.f[c][idx] = (T)((double)a.f[c][idx] + acc[c]);
+        else a.f[c][idx] = (T)acc[c];
       }
     }
     __syncthreads();
@@ -1839,6 +1971,36 @@ __global__ void __launch_bounds__(256) k_layer_mean(const double *partial, int n
     __syncthreads();
   }
   if (threadIdx.x == 0) mean[blockIdx.x] = red[0] / (double)per_layer;
+}
+
+// Grid-field watchdog: over every cell, bit 1 of *flags if a velocity
+// component is non-finite, bit 2 if p is, and the largest |u| over all
+// faces as the bit pattern of a non-negative double in *umax_bits (integer
+// maximum = floating maximum for non-negative values).  Grid-stride; one
+// atomic of each kind per wave.
+template <typename V, int DIM>
+__global__ void __launch_bounds__(256) k_field_check(const V *u0, const V *u1, const V *u2,
+                                                     const double *p, int64_t ncell,
+                                                     unsigned *flags,
+                                                     unsigned long long *umax_bits) {
+  double m = 0.0;
+  unsigned f = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ncell;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double a = (double)u0[i], b = (double)u1[i], c = DIM == 3 ? (double)u2[i] : 0.0;
+    if (!isfinite(a) || !isfinite(b) || !isfinite(c)) f |= 1u;
+    if (!isfinite(p[i])) f |= 2u;
+    m = fmax(m, fmax(fabs(a), fmax(fabs(b), fabs(c))));  // (fmax drops NaN)
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    m = fmax(m, __shfl_xor(m, off));
+    f |= (unsigned)__shfl_xor((int)f, off);
+  }
+  if (__lane_id() == 0) {
+    if (f) atomicOr(flags, f);
+    atomicMax(umax_bits, (unsigned long long)__double_as_longlong(m));
+  }
 }
 
 // Clear n 32-bit words (grid-stride): the fill kernel that clears counters

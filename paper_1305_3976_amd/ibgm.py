@@ -23,6 +23,7 @@ IB_F64, IB_F32 = 0, 1
 IB_PREC_FP64, IB_PREC_MIXED, IB_PREC_MIXED_STATE64 = 0, 1, 2
 IB_FLAG_NO_ADVECTION = 1
 IB_FLAG_WALLS_Y = 2
+IB_FLAG_DETERMINISTIC_SPREAD = 4
 IB_GRAPH_BRANCHES = 1
 
 _vp = ctypes.c_void_p
@@ -75,6 +76,7 @@ def _load():
                                    _vp * 3, ctypes.c_int32, _vp]
     L.ib_interp.argtypes = [_vp, _vp, ctypes.c_int64, _vp * 3, _vp]
     L.ib_refresh_divergence.argtypes = [_vp]
+    L.ib_check_fields.argtypes = [_vp, ctypes.POINTER(ctypes.c_double)]
     L.ib_force.argtypes = [_vp, _vp, _vp]
     L.ib_step_force.argtypes = [_vp, _vp * 3]
     L.ib_line_solve.argtypes = [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
@@ -107,7 +109,7 @@ def _load():
                                     i32, _ip, i32, i32, _vp, _vp]
     L.ib_closure_apply.argtypes = [ctypes.POINTER(_vp), _ip, _vp, f32, _vp]
     for f in ("ib_workspace_size", "ib_init", "ib_step", "ib_restart", "ib_sync", "ib_spread",
-              "ib_spread_static", "ib_interp", "ib_refresh_divergence",
+              "ib_spread_static", "ib_interp", "ib_refresh_divergence", "ib_check_fields",
               "ib_force", "ib_step_force", "ib_line_solve", "ib_destroy", "ib_profile_enable",
               "ib_profile_read", "ib_tune", "ib_tune_read", "ib_graph_create", "ib_graph_launch",
               "ib_graph_destroy") + CLOSURE_EXPORTED:
@@ -123,7 +125,7 @@ CLOSURE_EXPORTED = ("ib_conv3d_pack", "ib_conv3d_fwd", "ib_conv3d_bwd_data",
 lib = _load()
 
 EXPORTED = ("ib_workspace_size", "ib_init", "ib_step", "ib_restart", "ib_sync", "ib_spread",
-            "ib_spread_static", "ib_interp", "ib_refresh_divergence",
+            "ib_spread_static", "ib_interp", "ib_refresh_divergence", "ib_check_fields",
             "ib_force", "ib_step_force", "ib_line_solve", "ib_destroy", "ib_last_error",
             "ib_profile_enable",
             "ib_profile_count", "ib_profile_name", "ib_profile_read", "ib_tune", "ib_tune_read",
@@ -197,6 +199,7 @@ class Config:
     layer_dt: tuple = None  # 2-D batches: time step of each layer
     walls_y: bool = False   # channel: no-slip walls at y = 0 and y = n[1] h
     body_force: tuple = (0.0, 0.0, 0.0)  # uniform force density added to f
+    deterministic_spread: bool = False  # bitwise-reproducible spreading (slower)
 
     def params(self, step0: int = 0) -> GridParams:
         P = GridParams()
@@ -210,7 +213,8 @@ class Config:
         P.precision = self.precision
         P.rotate_split = 1 if self.rotate_split else 0
         P.flags = ((IB_FLAG_NO_ADVECTION if self.no_advection else 0)
-                   | (IB_FLAG_WALLS_Y if self.walls_y else 0))
+                   | (IB_FLAG_WALLS_Y if self.walls_y else 0)
+                   | (IB_FLAG_DETERMINISTIC_SPREAD if self.deterministic_spread else 0))
         P.step0 = step0
         for a in range(3):
             P.body_force[a] = float(self.body_force[a]) if a < len(self.body_force) else 0.0
@@ -320,6 +324,13 @@ class Simulation:
         """Recompute div_prev = D.u after the caller changed u between steps."""
         check(lib.ib_refresh_divergence(self.ctx))
         return self
+
+    def max_velocity(self) -> float:
+        """Grid-field watchdog: max |u| over all faces (raises IBError with
+        IB_E_NONFINITE if u or p holds a non-finite value)."""
+        m = ctypes.c_double()
+        check(lib.ib_check_fields(self.ctx, ctypes.byref(m)))
+        return m.value
 
     def sync(self) -> int:
         n = ctypes.c_int64()

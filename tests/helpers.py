@@ -44,11 +44,12 @@ def oracle_sim(w, rotate=True, no_advection=False, walls_y=False, body_force=(0.
 
 
 def gpu_sim(w, precision, rotate=True, no_advection=False, walls_y=False,
-            body_force=(0.0, 0.0, 0.0)):
+            body_force=(0.0, 0.0, 0.0), deterministic=False):
     from paper_1305_3976_amd import ibgm
     cfg = ibgm.Config(w.dim, w.n, w.h, rho=w.rho, mu=w.mu, dt=w.dt, chi=w.chi,
                       precision=precision, rotate_split=rotate, no_advection=no_advection,
-                      walls_y=walls_y, body_force=body_force)
+                      walls_y=walls_y, body_force=body_force,
+                      deterministic_spread=deterministic)
     return ibgm.Simulation(cfg, w.u0, w.structure)
 
 

@@ -104,6 +104,33 @@ def test_restart_from_saved_state():
         s_.close()
 
 
+@pytest.mark.parametrize("precision", [0, 1, 2])
+def test_grid_field_watchdog(precision):
+    """ib_sync also scans u and p: a non-finite velocity or pressure is
+    reported (IB_E_NONFINITE, the message naming the field), and
+    ib_check_fields returns max |u| over all faces."""
+    from paper_1305_3976_amd import ibgm
+    w = inputs.config_ellipse_64(steps=3)
+    w.u0 = inputs.random_streamfunction_velocity_2d(64, 4, 0.1, seed=5)
+    g = gpu_sim(w, precision)
+    g.step(3)
+    g.sync()
+    ref = max(float(g.u[c].abs().max()) for c in range(2))
+    assert g.max_velocity() == ref
+    g.u[1].view(-1)[77] = float("inf")
+    with pytest.raises(ibgm.IBError) as ei:
+        g.sync()
+    assert ei.value.status == ibgm.IB_E_NONFINITE and "velocity" in str(ei.value)
+    g.close()
+    g = gpu_sim(w, precision)
+    g.p.view(-1)[5] = float("nan")
+    with pytest.raises(ibgm.IBError) as ei:
+        g.max_velocity()
+    assert ei.value.status == ibgm.IB_E_NONFINITE and "pressure" in str(ei.value)
+    assert "velocity" not in str(ei.value)
+    g.close()
+
+
 def test_nonfinite_position_is_reported():
     from paper_1305_3976_amd import ibgm
     w = inputs.config_ellipse_64(steps=2)
