@@ -51,6 +51,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="approximate CPU budget of the oracle sample")
+    ap.add_argument("--config2-steps", type=int, default=1000,
+                    help="steps of the 512^2 ellipse run compared with the FP64 oracle in "
+                         "every precision (part of the CPU leg; 0 = skip)")
     ap.add_argument("--ensemble-steps", type=int, default=500,
                     help="steps of the batched 2-D ensemble (0 = skip it)")
     ap.add_argument("--closure", choices=("full", "small", "off"), default="full",
@@ -395,6 +398,57 @@ def oracle_sample(w, budget_s):
     return sim, n, el, oracle.num_threads()
 
 
+def config2_errors(steps: int):
+    """The 512^2 ellipse workload (2048 points, sigma = 10, a seeded smooth
+    flow, dt = 0.01/512) after `steps` steps: every GPU policy against the
+    FP64 oracle, per field (relative discrete l2 and max |gpu - oracle| /
+    max |oracle|).  The oracle run is started in a thread (it is C with
+    OpenMP and releases the interpreter) so it overlaps the GPU rows."""
+    import threading
+    import oracle
+    from paper_1305_3976_amd import inputs
+    w = inputs.config_ellipse_512(steps=steps)
+    P = oracle.make_params(w.dim, w.n, w.h, rho=w.rho, mu=w.mu, dt=w.dt, chi=w.chi)
+    S = w.structure
+    sim = oracle.Sim(P, [np.asarray(c, dtype=np.float64) for c in w.u0], S.X, S.links, S.w)
+    box = {}
+
+    def run():
+        t0 = time.perf_counter()
+        sim.advance(steps)
+        box["s"] = time.perf_counter() - t0
+
+    th = threading.Thread(target=run, daemon=True)
+    th.start()
+    return w, sim, th, box
+
+
+def config2_finish(w, sim, th, box, steps):
+    from paper_1305_3976_amd import ibgm
+    th.join()
+    out = {"workload": "ellipse2d_512: 512^2, mu=0.01, dt=0.01/512, 2048-point ellipse "
+                       "sigma=10, seeded smooth flow", "steps": steps,
+           "oracle_s": round(box.get("s", float("nan")), 1), "errors": {}}
+    rel = lambda a, b: float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+    mx = lambda a, b: float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-30))
+    for prec, tag in ((0, "fp64"), (1, "mixed"), (2, "mixed_state64")):
+        cfg = ibgm.Config(w.dim, w.n, w.h, rho=w.rho, mu=w.mu, dt=w.dt, chi=w.chi,
+                          precision=prec)
+        g = ibgm.Simulation(cfg, w.u0, w.structure)
+        g.step(steps)
+        g.sync()
+        st = g.state()
+        g.close()
+        e = {}
+        for c in range(w.dim):
+            e["u%d" % c] = [rel(st["u"][c], sim.u[c]), mx(st["u"][c], sim.u[c])]
+        e["p"] = [rel(st["p"], sim.p), mx(st["p"], sim.p)]
+        e["X"] = [rel(st["X"], sim.X), mx(st["X"], sim.X)]
+        out["errors"][tag] = e
+    out["errors_note"] = "[relative l2, max abs / max |oracle|] per field"
+    return out
+
+
 def gpu_errors(w, precision, nsteps, ref):
     from paper_1305_3976_amd import ibgm
     cfg = ibgm.Config(w.dim, w.n, w.h, rho=w.rho, mu=w.mu, dt=w.dt, chi=w.chi,
@@ -439,6 +493,10 @@ def main():
                                                    fp64=not args.no_fp64)}), flush=True)
         return
     copy_gbs = device_copy_rate()
+    # the long 512^2 comparison: its oracle run starts now, beside the GPU rows
+    c2 = None
+    if not args.no_cpu_baseline and args.config2_steps > 0:
+        c2 = config2_errors(args.config2_steps)
     from paper_1305_3976_amd import inputs
     w = inputs.config_shell_256(steps=args.steps, n=args.n, npts=args.points)
     ncell = w.n[0] * w.n[1] * w.n[2]
@@ -530,6 +588,11 @@ def main():
         print("# ensemble: %.1f member-steps/s, %.3f Gcell/s (%s)" % (
             line["ensemble"]["member_steps_per_s"], line["ensemble"]["gcell_updates_per_s"],
             line["ensemble"]["best_variant"]), file=sys.stderr, flush=True)
+    if c2 is not None:  # (joined before the closure, whose host work it would slow)
+        line["config2_%d_steps" % args.config2_steps] = config2_finish(*c2, args.config2_steps)
+        print("# config 2: %d steps compared with the oracle (oracle %.1f s)" % (
+            args.config2_steps, line["config2_%d_steps" % args.config2_steps]["oracle_s"]),
+            file=sys.stderr, flush=True)
     if args.closure != "off":
         from paper_1305_3976_amd import closure_run
         cargs = [] if args.closure == "full" else [

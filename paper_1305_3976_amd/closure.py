@@ -416,19 +416,52 @@ def collect(cases, n_fine, snapshots, every, warmup, pairs: PairSet, scales: Sca
     return scales
 
 
-def train(net: ConvNet, pairs: PairSet, iters: int, batch: int, lr: float = 1e-3,
+def collect_rollouts(cases, n_fine, net: ConvNet, scales: Scales, pairs: PairSet, syncs: int,
+                     horizon: int, every: int, warmup: int, crops: int = 1, seed: int = 2):
+    """Pairs along corrected coarse runs (the states the network meets in
+    service): from each of `syncs` restarts at the restricted fine state,
+    `horizon` coarse intervals, each a plain coarse step whose input and
+    target R(u_f) - u_c make a pair, after which the current network's
+    correction is applied before the next interval; the fine run advances two
+    steps per interval and `every` more between restarts."""
+    rng = np.random.default_rng(seed)
+    nc = n_fine // 2
+    for case in cases:
+        cf = CoarseFine(case, n_fine)
+        cf.fine_steps(warmup)
+        for _ in range(syncs):
+            cf.sync_coarse_to_fine()
+            for _ in range(horizon):
+                cf.coarse_step()
+                cf.fine_steps(2)
+                pairs.add(cf, scales, crops, rng)
+                x = cf.inputs_full(scales)
+                y = net.forward(x, 1, (nc, nc, nc), PERIODIC)
+                apply_correction(cf.coarse.u, y, 1.0 / scales.target)
+                cf.coarse.refresh_divergence()
+            if every:
+                cf.fine_steps(every)
+        cf.fine.sync()
+        cf.close()
+
+
+def train(net: ConvNet, pairs, iters: int, batch: int, lr: float = 1e-3,
           stream=None, lr_decay_to: float = 0.1):
     """Adam over contiguous slot batches (slots are a random permutation of
-    the pairs), cosine-free linear decay of the learning rate.  Returns the
-    loss of every iteration (host floats, read once at the end)."""
-    nb = max(1, pairs.count // batch)
+    the pairs) of one PairSet or of several (same crop shape; batches drawn
+    from all of them in one shuffled plan), linear decay of the learning
+    rate.  Returns the loss of every iteration (host floats, read once at
+    the end)."""
+    sets = list(pairs) if isinstance(pairs, (list, tuple)) else [pairs]
+    plan = [(i, k) for i, ps in enumerate(sets) for k in range(max(1, ps.count // batch))]
     losses = torch.empty(iters, dtype=torch.float32, device=net.device)
-    order = np.random.default_rng(99).permutation(nb)
+    order = np.random.default_rng(99).permutation(len(plan))
     for it in range(iters):
-        k = int(order[it % nb])
-        x, t = pairs.batch(k * batch, batch)
+        i, k = plan[int(order[it % len(plan)])]
+        ps = sets[i]
+        x, t = ps.batch(k * batch, batch)
         frac = it / max(1, iters - 1)
-        l = net.train_step(x, t, batch, pairs.in_dims, pairs.mode,
+        l = net.train_step(x, t, batch, ps.in_dims, ps.mode,
                            lr * (1.0 - (1.0 - lr_decay_to) * frac), stream)
         losses[it:it + 1].copy_(l)
     return losses.cpu().numpy()

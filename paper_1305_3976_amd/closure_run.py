@@ -79,6 +79,15 @@ def main(argv=None):
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--rollout", type=int, default=20, help="coarse steps of the rollout")
+    ap.add_argument("--dagger-syncs", type=int, default=10,
+                    help="restarts per training trajectory for pairs along corrected runs")
+    ap.add_argument("--dagger-horizon", type=int, default=10,
+                    help="corrected coarse intervals after each restart")
+    ap.add_argument("--dagger-iters", type=int, default=2000)
+    ap.add_argument("--check-every", type=int, default=4,
+                    help="coarse intervals between the fine solve's audits (guarded rollout)")
+    ap.add_argument("--late-start", type=int, default=400,
+                    help="fine steps before the second rollout (mid-trajectory start)")
     ap.add_argument("--seed", type=int, default=5)
     a = ap.parse_args(argv)
     t0 = time.time()
@@ -103,8 +112,39 @@ def main(argv=None):
     e0, e1 = cl.evaluate(net, ho, 0, ho.count, batch=a.batch)
     r0, r1 = cl.evaluate(net, tr, 0, min(tr.count, 256), batch=a.batch)
     log("held-out one-interval error ratio %.3f (train %.3f), %.1f s training" % (e1 / e0, r1 / r0, train_s))
+    errs1, _, _ = cl.rollout(cases[-1], a.n_fine, a.rollout, net, scales, a.warmup)
+    log("rollout (one-interval training): plain %.3e -> %.3e, corrected %.3e -> %.3e" % (
+        errs1[0][0], errs1[-1][0], errs1[0][1], errs1[-1][1]))
+    # second phase: pairs along the network's own corrected runs (the states
+    # it meets in service), trained together with the first-phase pairs
+    dag = None
+    if a.dagger_syncs and a.dagger_horizon:
+        t3 = time.time()
+        tr2 = cl.PairSet(ntr * a.dagger_syncs * a.dagger_horizon * a.crops, nc, mode=cl.VALID,
+                         crop=a.crop)
+        span = a.snapshots * a.every
+        gap = max(0, (span - a.dagger_syncs * 2 * a.dagger_horizon) // a.dagger_syncs)
+        cl.collect_rollouts(cases[:ntr], a.n_fine, net, scales, tr2, a.dagger_syncs,
+                            a.dagger_horizon, gap, a.warmup, crops=a.crops)
+        torch.cuda.synchronize()
+        gen2 = time.time() - t3
+        t4 = time.time()
+        losses2 = cl.train(net, [tr, tr2], a.dagger_iters, a.batch, 0.5 * a.lr)
+        train2 = time.time() - t4
+        e0, e1 = cl.evaluate(net, ho, 0, ho.count, batch=a.batch)
+        log("corrected-run pairs: %d in %.1f s, %.1f s training; held-out ratio now %.3f" % (
+            tr2.count, gen2, train2, e1 / e0))
+        dag = {"pairs": tr2.count, "generation_s": round(gen2, 1), "train_s": round(train2, 1),
+               "iters": a.dagger_iters,
+               "loss_first_last": [float(losses2[:50].mean()), float(losses2[-50:].mean())]}
+        del tr2
     errs, t_plain, t_corr = cl.rollout(cases[-1], a.n_fine, a.rollout, net, scales, a.warmup)
     log("rollout: plain %.3e -> %.3e, corrected %.3e -> %.3e" % (errs[0][0], errs[-1][0], errs[0][1], errs[-1][1]))
+    errs_late, _, _ = cl.rollout(cases[-1], a.n_fine, a.rollout, net, scales, a.late_start)
+    gerrs, fired = cl.guarded_rollout(cases[-1], a.n_fine, a.rollout, net, scales,
+                                      check_every=a.check_every, warmup=a.warmup)
+    log("guarded rollout: %d fallback(s); final plain %.3e corrected %.3e guarded %.3e" % (
+        len(fired), gerrs[-1][0], gerrs[-1][1], gerrs[-1][2]))
     # fine step time on the same family member (two fine steps per coarse step)
     cf = cl.CoarseFine(cases[-1], a.n_fine)
     cf.fine_steps(3)
@@ -126,9 +166,26 @@ def main(argv=None):
         "held_out_interval_error_ratio": round(e1 / e0, 4),
         "train_interval_error_ratio": round(r1 / r0, 4),
         "rollout_rel_l2_vs_restricted_fine": {
-            "steps": a.rollout,
+            "steps": a.rollout, "start_fine_step": a.warmup,
             "plain_coarse": [round(e[0], 6) for e in errs],
-            "coarse_plus_closure": [round(e[1], 6) for e in errs]},
+            "coarse_plus_closure": [round(e[1], 6) for e in errs],
+            "coarse_plus_closure_one_interval_training_only": [round(e[1], 6) for e in errs1],
+            "intervals_corrected_below_plain": int(sum(e[1] < e[0] for e in errs))},
+        "rollout_mid_trajectory": {
+            "start_fine_step": a.late_start,
+            "plain_coarse": [round(e[0], 6) for e in errs_late],
+            "coarse_plus_closure": [round(e[1], 6) for e in errs_late],
+            "intervals_corrected_below_plain": int(sum(e[1] < e[0] for e in errs_late))},
+        "guarded_rollout": {
+            "check_every": a.check_every,
+            "note": "the fine solve audits the corrected run every check_every intervals and "
+                    "restarts it from the restricted fine state where it has fallen behind "
+                    "the plain coarse run",
+            "fallback_after_interval": [k + 1 for k in fired],
+            "guarded": [round(e[2], 6) for e in gerrs],
+            "plain_coarse": [round(e[0], 6) for e in gerrs],
+            "coarse_plus_closure_unguarded": [round(e[1], 6) for e in gerrs]},
+        "corrected_run_training": dag,
         "ms_per_interval": {"fine_two_steps": round(2 * t_fine, 4),
                             "coarse_plain": round(t_plain, 4),
                             "coarse_plus_closure": round(t_corr, 4)},
