@@ -2,10 +2,11 @@
 
     python -m paper_1305_3976_amd.build
 
-Two translation units, compiled in parallel for gfx950 only with packed-FP32
+Three translation units, compiled in parallel for gfx950 only with packed-FP32
 instructions disabled, then linked into one shared library:
   csrc/ibgm.hip     the IB-GM step (device code in csrc/kernels.h)
   csrc/closure.hip  the learned-closure kernels (matrix-core convolutions)
+  csrc/probe.hip    the streaming-rate probe (a measurement aid)
 """
 from __future__ import annotations
 
@@ -16,7 +17,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = [os.path.join(HERE, "csrc", "ibgm.hip"), os.path.join(HERE, "csrc", "closure.hip")]
+SOURCES = [os.path.join(HERE, "csrc", "ibgm.hip"), os.path.join(HERE, "csrc", "closure.hip"),
+           os.path.join(HERE, "csrc", "probe.hip")]
 LIB = os.path.join(HERE, "libibgm.so")
 INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(HERE, "_build")

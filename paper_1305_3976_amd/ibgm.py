@@ -108,6 +108,10 @@ def _load():
     L.ib_closure_gather.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(f32), _ip, i32, _ip, _vp,
                                     i32, _ip, i32, i32, _vp, _vp]
     L.ib_closure_apply.argtypes = [ctypes.POINTER(_vp), _ip, _vp, f32, _vp]
+    # streaming-rate probe (include/ibgm_probe.h)
+    L.ib_probe_stream_rate.argtypes = [ctypes.POINTER(_vp), i32, ctypes.POINTER(_vp), i32, i64,
+                                       i32, _vp, ctypes.POINTER(ctypes.c_double)]
+    L.ib_probe_stream_rate.restype = ctypes.c_int
     for f in ("ib_workspace_size", "ib_init", "ib_step", "ib_restart", "ib_sync", "ib_spread",
               "ib_spread_static", "ib_interp", "ib_refresh_divergence", "ib_check_fields",
               "ib_force", "ib_step_force", "ib_line_solve", "ib_destroy", "ib_profile_enable",
@@ -129,7 +133,8 @@ EXPORTED = ("ib_workspace_size", "ib_init", "ib_step", "ib_restart", "ib_sync", 
             "ib_force", "ib_step_force", "ib_line_solve", "ib_destroy", "ib_last_error",
             "ib_profile_enable",
             "ib_profile_count", "ib_profile_name", "ib_profile_read", "ib_tune", "ib_tune_read",
-            "ib_graph_create", "ib_graph_launch", "ib_graph_destroy") + CLOSURE_EXPORTED
+            "ib_graph_create", "ib_graph_launch", "ib_graph_destroy",
+            "ib_probe_stream_rate") + CLOSURE_EXPORTED
 
 
 def check(status: int):
@@ -163,6 +168,22 @@ def spread_static(cfg, X: torch.Tensor, F: torch.Tensor, w: torch.Tensor, out=No
     check(lib.ib_spread_static(ctypes.byref(P), *args, npts, ptrs, 1 if accumulate else 0,
                                _stream_handle(stream)))
     return out
+
+
+def stream_rate(nsrc: int, ndst: int, mib_per_stream: int = 512, reps: int = 5, stream=None):
+    """HBM bytes per second that a plain elementwise kernel reaches reading
+    nsrc and writing ndst FP32 streams of mib_per_stream MiB each
+    (ib_probe_stream_rate): the practical ceiling for streaming kernels."""
+    n = mib_per_stream * 2 ** 20 // 4
+    src = [torch.ones(n, dtype=torch.float32, device="cuda") for _ in range(nsrc)]
+    dst = [torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(ndst)]
+    S = (_vp * max(1, nsrc))(*[t.data_ptr() for t in src])
+    D = (_vp * max(1, ndst))(*[t.data_ptr() for t in dst])
+    rate = ctypes.c_double()
+    check(lib.ib_probe_stream_rate(S, nsrc, D, ndst, n, reps, _stream_handle(stream),
+                                   ctypes.byref(rate)))
+    del src, dst
+    return rate.value
 
 
 def line_solve(t: torch.Tensor, axis: int, diag: float, off: float, stream=None):

@@ -416,3 +416,37 @@ def test_steps_after_changing_u_between_steps(precision, tol):
     for k, e in errs.items():
         assert e <= tol, (k, e)
     g.close()
+
+
+@pytest.fixture(scope="module")
+def ellipse512_long_oracle():
+    w = inputs.config_ellipse_512(steps=1000)
+    return w, oracle_sim(w).advance(w.steps)
+
+
+@pytest.mark.parametrize("precision", [0, 1, 2])
+def test_ellipse512_1000_steps(ellipse512_long_oracle, precision):
+    """The 512^2 workload over 1000 steps (the length its configuration is
+    run for): every field against the oracle, relative l2 and point-wise.
+    FP64 1e-12 (p at the conditioning of the psi solves, (1 + 4N^2) eps64);
+    both mixed policies 1e-5 in u, p, X (psi against the p scale); the
+    point-wise bars 10x the l2 ones."""
+    from helpers import field_maxabs
+    w, o = ellipse512_long_oracle
+    g = gpu_sim(w, precision)
+    g.step(w.steps)
+    assert g.sync() == w.steps
+    st = g.state()
+    l2 = field_errors(st, o, 2)
+    l2["psi"] = psi_vs_p(st["psi"], o.psi, o.p)
+    mx = field_maxabs(st, o, 2)
+    print("ellipse512 1000 steps, precision", precision, l2, mx)
+    cond = (1 + 4 * 512 ** 2) * 2.0 ** -52
+    for k, e in l2.items():
+        lim = (max(FP64_TOL, cond) if k in ("p", "psi") else FP64_TOL) if precision == 0 else MIXED_TOL
+        assert e <= lim, ("l2", k, e, lim)
+    for k, e in mx.items():
+        lim = 10 * ((max(FP64_TOL, cond) if k in ("p", "psi_vs_p") else FP64_TOL)
+                    if precision == 0 else MIXED_TOL)
+        assert e <= lim, ("max", k, e, lim)
+    g.close()
