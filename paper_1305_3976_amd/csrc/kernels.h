@@ -615,11 +615,25 @@ struct SpreadArgs {
 // LDS sums are FP64 (A) also for an FP32 grid: gfx950's LDS takes FP64 atomic
 // adds at about twice the rate of FP32 ones (measured: 711 vs 1271 us for the
 // 933,888-point cylinder at 256^3), and the sum is rounded to FP32 once.
+//
+// The LDS sums are laid out with padded strides: rows of TS + 1 slots,
+// planes of TS (TS + 1), and each component's array offset by 5 slots more.
+// With x fastest and unpadded rows of 8 doubles, cells that differ in y or
+// z fall on the same two banks; the points of a dense sheet handled by one
+// wave differ exactly there (a wave takes neighbouring points along the
+// sheet), so their atomics queued on one bank.  Padded, neighbours in y and
+// z and the three components land on different banks.
+constexpr int SP_ROW = TS + 1;                  // slot stride of a tile row
+constexpr int SP_PLANE = TS * SP_ROW;           // slot stride of a tile plane
+template <int DIM>
+constexpr int sp_comp() { return (DIM == 3 ? TS * SP_PLANE : SP_PLANE) + 5; }
+
 template <typename T, int DIM, bool ADD, int NT = 256, typename A = double>
 __global__ void __launch_bounds__(NT) k_spread_tiles(SpreadArgs<T, DIM> a) {
   using C = T;
   constexpr int CELLS = DIM == 3 ? TS * TS * TS : TS * TS;
-  __shared__ A acc[DIM][CELLS];
+  constexpr int CS = sp_comp<DIM>();
+  __shared__ A acc[DIM * CS];
   __shared__ int c_start[27], c_pref[28], s_list[3][3], s_len[3], s_cnt[27];
   const int32_t nn[3] = {a.g.n0, a.g.n1, a.g.n2};
   int ntodo = *a.nlist;
@@ -645,7 +659,7 @@ __global__ void __launch_bounds__(NT) k_spread_tiles(SpreadArgs<T, DIM> a) {
         s_len[ax] = len;
       }
     }
-    for (int i = threadIdx.x; i < DIM * CELLS; i += blockDim.x) (&acc[0][0])[i] = A(0);
+    for (int i = threadIdx.x; i < DIM * CS; i += blockDim.x) acc[i] = A(0);
     __syncthreads();
     const int ncomb = s_len[0] * s_len[1] * s_len[2];
     if (threadIdx.x < ncomb) {
@@ -728,10 +742,10 @@ __global__ void __launch_bounds__(NT) k_spread_tiles(SpreadArgs<T, DIM> a) {
             const int ly = loc[1][t1];
             if (ly < 0) continue;
             const C rw = val * wz[t2] * wy[t1];
-            const int lrow = (lz * TS + ly) * TS;
+            const int lrow = c * CS + lz * SP_PLANE + ly * SP_ROW;
 #pragma unroll
             for (int t0 = 0; t0 < 4; t0++)
-              if (loc[0][t0] >= 0) atomicAdd(&acc[c][lrow + loc[0][t0]], (A)(rw * wx[t0]));
+              if (loc[0][t0] >= 0) atomicAdd(&acc[lrow + loc[0][t0]], (A)(rw * wx[t0]));
           }
         }
       }
@@ -742,9 +756,10 @@ __global__ void __launch_bounds__(NT) k_spread_tiles(SpreadArgs<T, DIM> a) {
       const int gi = lo[0] + li, gj = lo[1] + lj, gk = lo[2] + lk;
       if (gi >= hi[0] || gj >= hi[1] || gk >= hi[2]) continue;
       const int64_t idx = gi + (int64_t)nn[0] * (gj + (int64_t)nn[1] * gk);
+      const int sl = lk * SP_PLANE + lj * SP_ROW + li;
       for (int c = 0; c < DIM; c++) {
-        if (ADD) a.f[c][idx] = (T)((A)a.f[c][idx] + acc[c][i]);
-        else a.f[c][idx] = (T)acc[c][i];
+        if (ADD) a.f[c][idx] = (T)((A)a.f[c][idx] + acc[c * CS + sl]);
+        else a.f[c][idx] = (T)acc[c * CS + sl];
       }
     }
     __syncthreads();
