@@ -301,12 +301,18 @@ class CoarseFine:
         return self.Ru
 
     def inputs_full(self, scales: Scales, out=None):
+        """The network input over the whole coarse grid (BF16, 16 channels);
+        into `out`, or into a buffer kept for the next call."""
         nc = self.nc
         if out is None:
-            out = torch.empty(nc ** 3 * 16, dtype=torch.bfloat16, device=self.Ru[0].device)
-        org = torch.zeros((1, 3), dtype=torch.int32, device=out.device)
+            if getattr(self, "_x_full", None) is None:
+                self._x_full = torch.empty(nc ** 3 * 16, dtype=torch.bfloat16,
+                                           device=self.Ru[0].device)
+            out = self._x_full
+        if getattr(self, "_org0", None) is None:
+            self._org0 = torch.zeros((1, 3), dtype=torch.int32, device=out.device)
         srcs, sc, ch = self.input_sources(scales)
-        gather(srcs, sc, ch, (nc, nc, nc), org, (nc, nc, nc), False, 16, out)
+        gather(srcs, sc, ch, (nc, nc, nc), self._org0, (nc, nc, nc), False, 16, out)
         return out
 
     def input_sources(self, scales: Scales):
@@ -524,6 +530,31 @@ def rollout(case, n_fine: int, steps: int, net: ConvNet, scales: Scales, warmup:
     plain.coarse.close()
     cf.close()
     return errs, t_plain / steps, t_corr / steps
+
+
+def interval_times(case, n_fine: int, net: ConvNet, scales: Scales, reps: int = 20,
+                   warmup: int = 6):
+    """GPU time per coarse interval, plain and corrected, each over `reps`
+    consecutive intervals enqueued back to back (HIP events on the current
+    stream, no host round trip between intervals -- the way the fine steps
+    are timed), from the restricted fine state after `warmup` fine steps."""
+    cf = CoarseFine(case, n_fine)
+    cf.fine_steps(warmup)
+    cf.sync_coarse_to_fine()
+    out = []
+    for corrected in (False, True):
+        step = (lambda: cf.coarse_step(net, scales)) if corrected else cf.coarse_step
+        step()  # first call allocates the step's buffers
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            step()
+        e1.record()
+        torch.cuda.synchronize()
+        out.append(e0.elapsed_time(e1) / reps)
+    cf.close()
+    return out[0], out[1]
 
 
 # ------------------------------------------------- guarded rollout (judge) --

@@ -5,12 +5,14 @@
 // that connect the network to the IB-GM fields.
 //
 // Convolution as an implicit GEMM.  For one output row of 32 voxels along x
-// and one tap, the product [32 voxels x 16 input channels] x [16 x 32 output
-// channels] is one matrix-core instruction; 27 taps x (ci/16) of them build
-// the 32 x 32 output block.  A workgroup (4 waves) keeps every packed weight
-// fragment of the layer in LDS for its whole life and walks output tiles of
-// 32 x 4 x 4 voxels: it stages the tile's input halo (34 x 6 x 6 voxels, all
-// channels) in LDS, and each wave accumulates the four rows of one z-slice.
+// and one tap, the product [32 output channels x 16 input channels] x [16 x
+// 32 voxels] (the transposed form, so that a lane's accumulators are
+// consecutive channels of one voxel) is one matrix-core instruction; 27 taps
+// x (ci/16) of them build the 32 x 32 output block.  A workgroup (4 waves)
+// keeps every packed weight fragment of the layer in LDS for its whole life
+// and walks output tiles of 32 x 4 x 4 voxels: it stages the tile's input
+// halo (34 x 6 x 6 voxels, all channels) in LDS, and each wave accumulates
+// the four rows of one z-slice.
 // Matrix-core lane layout (32x32x16): lane l supplies A[row l%32][k
 // 8(l/32)..+7] and B[k 8(l/32)..+7][col l%32]; accumulator j of lane l is
 // D[8(j/4) + 4(l/32) + j%4][l%32].
@@ -19,6 +21,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <type_traits>
 
 #include "errors.h"
 #include "ibgm_closure.h"
@@ -52,7 +55,6 @@ struct ConvArgs {
   void *y;            // [B][E2][E1][E0][ystride]
   int B, D0, D1, D2, E0, E1, E2;
   int off, wrap;  // wrap: 0 = zeros outside, 1 = periodic (dims >= TX + 2), 2 = periodic
-  int idx32;      // every input offset fits in 32 bits
   int relu, out_f32, co_store, ystride;
   int nt0, nt1, nt2, ntiles;
 };
@@ -98,69 +100,111 @@ __device__ __forceinline__ TileXYZ tile_xyz(int tile, int nt0, int nt1, int nt2)
   return {r / nt2, t0 * TX, t1 * TY, t2 * TZ};
 }
 
+// Halo chunk metadata of one thread, fixed for the kernel's life: chunk c of
+// a tile's input halo (16 bytes of one voxel's channels) lies at halo voxel
+// (hx, hy, hz), 16-byte part `part` of the voxel, and goes to LDS byte
+// v VS + 16 part.  Packed as hx | hy << 6 | hz << 9 | part << 12 | (LDS
+// byte / 16) << 14 (27 bits); -1 for chunk numbers past the halo.
+template <int CI, int VS>
+__device__ __forceinline__ int halo_meta(int c) {
+  constexpr int CH = CI / 8;
+  if (c >= HX * HY * HZ * CH) return -1;
+  const int v = c / CH, part = c - v * CH;
+  const int hx = v % HX, hy = (v / HX) % HY, hz = v / (HX * HY);
+  return hx | hy << 6 | hz << 9 | part << 12 | ((v * VS + part * 16) >> 4) << 14;
+}
+
+// Load one halo chunk of the tile whose halo starts at input voxel (gx0, gy0,
+// gz0) of batch item b.  WRAP: 0 = zeros outside the input, 1 = periodic with
+// every dimension >= the halo (one compare-and-add), 2 = periodic, any size.
+template <int CI, int WRAP>
+__device__ __forceinline__ uint4 halo_load(const ConvArgs &a, int meta, int b, int gx0, int gy0,
+                                           int gz0) {
+  uint4 val = make_uint4(0, 0, 0, 0);
+  if (meta < 0) return val;
+  int gx = gx0 + (meta & 63), gy = gy0 + ((meta >> 6) & 7), gz = gz0 + ((meta >> 9) & 7);
+  if (WRAP == 1) {
+    gx = wrap1(gx, a.D0), gy = wrap1(gy, a.D1), gz = wrap1(gz, a.D2);
+  } else if (WRAP == 2) {
+    gx = wrapi(gx, a.D0), gy = wrapi(gy, a.D1), gz = wrapi(gz, a.D2);
+  } else if (gx < 0 || gx >= a.D0 || gy < 0 || gy >= a.D1 || gz < 0 || gz >= a.D2) {
+    return val;
+  }
+  const int64_t vox = (((int64_t)b * a.D2 + gz) * a.D1 + gy) * a.D0 + gx;
+  return *reinterpret_cast<const uint4 *>(a.x + vox * CI + ((meta >> 12) & 3) * 8);
+}
+
+// Output channel held in row r of the transposed 32 x 32 product: rows are
+// permuted so that the 16 accumulators of a lane are 16 consecutive channels
+// (lane l, accumulator j: row 8 (j/4) + 4 (l/32) + j%4, channel 16 (l/32) + j).
+__device__ __forceinline__ int row_channel(int r) { return 16 * ((r >> 2) & 1) + 4 * (r >> 3) + (r & 3); }
+
+// Copy the packed weight fragments into LDS as matrix-core A operands: lane l
+// of fragment f takes packed lane 32 (l/32) + row_channel(l%32) (PERM), or
+// lane l itself.  Eight loads of a thread are in flight before their stores.
+template <int N, bool PERM>
+__device__ __forceinline__ void copy_weights(unsigned char *sw, const bf16 *wp) {
+  constexpr int PERW = (N + NT - 1) / NT, BATCH = 8;
+#pragma unroll
+  for (int q0 = 0; q0 < PERW; q0 += BATCH) {
+    uint4 w[BATCH];
+#pragma unroll
+    for (int q = 0; q < BATCH; q++) {
+      const int c = threadIdx.x + (q0 + q) * NT;
+      int src = c;
+      if (PERM) src = (c & ~31) | row_channel(c & 31);
+      w[q] = (q0 + q < PERW && c < N) ? reinterpret_cast<const uint4 *>(wp)[src]
+                                      : make_uint4(0, 0, 0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < BATCH; q++) {
+      const int c = threadIdx.x + (q0 + q) * NT;
+      if (q0 + q < PERW && c < N) reinterpret_cast<uint4 *>(sw)[c] = w[q];
+    }
+  }
+}
+
 // Forward convolution (and, with adjoint packing, the input gradient).
-// Wave w computes the 4 output rows (y = 0..3) of z-slice w of the tile.  For
-// each (tz, tx) it keeps the three weight fragments of ty = 0..2 in registers
-// and walks the 6 halo rows once: a halo row hy feeds output rows hy - ty, so
-// each A fragment read from LDS serves up to three matrix-core products.  A
+// Wave w computes the 4 output rows (y = 0..3) of z-slice w of the tile as
+// the transposed product Y^T = W^T X^T: the weights are the A operand and the
+// halo row the B operand, so each lane ends with 16 consecutive output
+// channels of one voxel and stores them as two 16-byte writes (VEC), or
+// channel by channel (any co_store, y_stride, FP32 output).  For each (tz,
+// tx) a wave keeps the three weight fragments of ty = 0..2 in registers and
+// walks the 6 halo rows once: a halo row hy feeds output rows hy - ty, so
+// each B fragment read from LDS serves up to three matrix-core products.  A
 // tile's halo is fetched with all of a thread's loads in flight before any is
-// stored to LDS.
-template <int CI>
+// stored to LDS, from per-thread chunk coordinates computed once.
+template <int CI, int WRAP, bool VEC>
 __global__ __launch_bounds__(NT) void k_conv(ConvArgs a) {
   constexpr int KS = CI / 16;
   constexpr int VS = CI * 2 + 16;  // padded voxel stride in LDS (bytes)
-  constexpr int CH = CI / 8;
-  constexpr int NCHUNK = HX * HY * HZ * CH;
+  constexpr int NCHUNK = HX * HY * HZ * (CI / 8);
   constexpr int PER = (NCHUNK + NT - 1) / NT;
   __shared__ __align__(16) unsigned char sw[27 * KS * 64 * 16];
   __shared__ __align__(16) unsigned char sh[HX * HY * HZ * VS];
-  for (int c = threadIdx.x; c < 27 * KS * 64; c += NT)
-    reinterpret_cast<uint4 *>(sw)[c] = reinterpret_cast<const uint4 *>(a.wp)[c];
+  copy_weights<27 * KS * 64, true>(sw, a.wp);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 31, grp = lane >> 5;
-  const float bias = (a.bias && col < a.co_store) ? a.bias[col] : 0.f;
-  uint4 pre[PER];
-  auto fetch = [&](int tile) {
-    const TileXYZ t = tile_xyz(tile, a.nt0, a.nt1, a.nt2);
+  float bias[16];
 #pragma unroll
-    for (int q = 0; q < PER; q++) {
-      const int c = threadIdx.x + q * NT;
-      pre[q] = make_uint4(0, 0, 0, 0);
-      if (c < NCHUNK) {
-        const int v = c / CH, part = c - v * CH;
-        const int hx = v % HX, hy = (v / HX) % HY, hz = v / (HX * HY);
-        int gx = t.ox0 + hx + a.off, gy = t.oy0 + hy + a.off, gz = t.oz0 + hz + a.off;
-        bool in = true;
-        if (a.wrap == 1) {
-          gx = wrap1(gx, a.D0), gy = wrap1(gy, a.D1), gz = wrap1(gz, a.D2);
-        } else if (a.wrap) {
-          gx = wrapi(gx, a.D0), gy = wrapi(gy, a.D1), gz = wrapi(gz, a.D2);
-        } else {
-          in = gx >= 0 && gx < a.D0 && gy >= 0 && gy < a.D1 && gz >= 0 && gz < a.D2;
-        }
-        if (in) {
-          if (a.idx32) {
-            const uint32_t vox = ((uint32_t)(t.b * a.D2 + gz) * a.D1 + gy) * a.D0 + gx;
-            pre[q] = *reinterpret_cast<const uint4 *>(a.x + vox * CI + part * 8);
-          } else {
-            const size_t vox = (((size_t)t.b * a.D2 + gz) * a.D1 + gy) * a.D0 + gx;
-            pre[q] = *reinterpret_cast<const uint4 *>(a.x + vox * CI + part * 8);
-          }
-        }
-      }
-    }
-  };
+  for (int j = 0; j < 16; j++) {
+    const int ch = 16 * grp + j;
+    bias[j] = (a.bias && ch < a.co_store) ? a.bias[ch] : 0.f;
+  }
+  int meta[PER];
+#pragma unroll
+  for (int q = 0; q < PER; q++) meta[q] = halo_meta<CI, VS>(threadIdx.x + q * NT);
   for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
-    fetch(tile);      // all of this thread's halo loads in flight at once
+    const TileXYZ t = tile_xyz(tile, a.nt0, a.nt1, a.nt2);
+    uint4 pre[PER];
+#pragma unroll
+    for (int q = 0; q < PER; q++)
+      pre[q] = halo_load<CI, WRAP>(a, meta[q], t.b, t.ox0 + a.off, t.oy0 + a.off, t.oz0 + a.off);
     __syncthreads();  // the previous tile's reads of sh (and the weight copy) are done
 #pragma unroll
-    for (int q = 0; q < PER; q++) {
-      const int c = threadIdx.x + q * NT;
-      if (c < NCHUNK) {
-        const int v = c / CH, part = c - v * CH;
-        *reinterpret_cast<uint4 *>(sh + v * VS + part * 16) = pre[q];
-      }
-    }
+    for (int q = 0; q < PER; q++)
+      if (meta[q] >= 0) *reinterpret_cast<uint4 *>(sh + ((meta[q] >> 14) << 4)) = pre[q];
     __syncthreads();
     f32x16 acc[TY];
 #pragma unroll
@@ -171,107 +215,112 @@ __global__ __launch_bounds__(NT) void k_conv(ConvArgs a) {
     for (int tz = 0; tz < 3; tz++) {
 #pragma unroll 1
       for (int tx = 0; tx < 3; tx++) {
-        bf16x8 bw[3][KS];
+        bf16x8 wa[3][KS];
 #pragma unroll
         for (int ty = 0; ty < 3; ty++)
 #pragma unroll
           for (int ks = 0; ks < KS; ks++)
-            bw[ty][ks] = *reinterpret_cast<const bf16x8 *>(
+            wa[ty][ks] = *reinterpret_cast<const bf16x8 *>(
                 sw + (((9 * tz + 3 * ty + tx) * KS + ks) * 64 + lane) * 16);
         const unsigned char *base = sh + ((wave + tz) * HY * HX + col + tx) * VS + grp * 16;
 #pragma unroll
         for (int hy = 0; hy < HY; hy++) {
 #pragma unroll
           for (int ks = 0; ks < KS; ks++) {
-            const bf16x8 av = *reinterpret_cast<const bf16x8 *>(base + hy * HX * VS + ks * 32);
+            const bf16x8 xb = *reinterpret_cast<const bf16x8 *>(base + hy * HX * VS + ks * 32);
 #pragma unroll
             for (int ty = 0; ty < 3; ty++) {
               const int my = hy - ty;
               if (my >= 0 && my < TY)
-                acc[my] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bw[ty][ks], acc[my], 0, 0, 0);
+                acc[my] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(wa[ty][ks], xb, acc[my], 0, 0, 0);
             }
           }
         }
       }
     }
-    // epilogue: lane holds output channel `col` of 16 voxels per row
-    const TileXYZ t = tile_xyz(tile, a.nt0, a.nt1, a.nt2);
-    const int oz = t.oz0 + wave;
+    // epilogue: lane holds channels 16 grp .. 16 grp + 15 of voxel x = col
+    const int oz = t.oz0 + wave, ox = t.ox0 + col;
 #pragma unroll
     for (int my = 0; my < TY; my++) {
       const int oy = t.oy0 + my;
-      if (oy >= a.E1 || oz >= a.E2 || col >= a.co_store) continue;
-      const size_t rowv = (((size_t)t.b * a.E2 + oz) * a.E1 + oy) * a.E0;
+      if (oy >= a.E1 || oz >= a.E2 || ox >= a.E0) continue;
+      const int64_t vox = (((int64_t)t.b * a.E2 + oz) * a.E1 + oy) * a.E0 + ox;
+      float v[16];
 #pragma unroll
       for (int j = 0; j < 16; j++) {
-        const int ox = t.ox0 + 8 * (j >> 2) + 4 * grp + (j & 3);
-        if (ox >= a.E0) continue;
-        const size_t vox = rowv + ox;
-        float v = acc[my][j] + bias;
-        if (a.relu) v = fmaxf(v, 0.f);
-        if (a.mask && !((float)a.mask[vox * CO + col] > 0.f)) v = 0.f;
-        if (a.out_f32)
-          reinterpret_cast<float *>(a.y)[vox * a.ystride + col] = v;
-        else
-          reinterpret_cast<bf16 *>(a.y)[vox * a.ystride + col] = (bf16)v;
+        v[j] = acc[my][j] + bias[j];
+        if (a.relu) v[j] = fmaxf(v[j], 0.f);
+      }
+      if (VEC) {
+        if (a.mask) {
+          const uint4 *mp = reinterpret_cast<const uint4 *>(a.mask + vox * CO + 16 * grp);
+          const uint4 m2[2] = {mp[0], mp[1]};
+          const bf16 *mb = reinterpret_cast<const bf16 *>(m2);
+#pragma unroll
+          for (int j = 0; j < 16; j++)
+            if (!((float)mb[j] > 0.f)) v[j] = 0.f;
+        }
+        bf16x8 o[2];
+#pragma unroll
+        for (int j = 0; j < 16; j++) o[j >> 3][j & 7] = (bf16)v[j];
+        uint4 *yp = reinterpret_cast<uint4 *>(reinterpret_cast<bf16 *>(a.y) + vox * a.ystride + 16 * grp);
+        yp[0] = *reinterpret_cast<const uint4 *>(&o[0]);
+        yp[1] = *reinterpret_cast<const uint4 *>(&o[1]);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 16; j++) {
+          const int ch = 16 * grp + j;
+          if (ch >= a.co_store) continue;
+          float w = v[j];
+          if (a.mask && !((float)a.mask[vox * CO + ch] > 0.f)) w = 0.f;
+          if (a.out_f32)
+            reinterpret_cast<float *>(a.y)[vox * a.ystride + ch] = w;
+          else
+            reinterpret_cast<bf16 *>(a.y)[vox * a.ystride + ch] = (bf16)w;
+        }
       }
     }
   }
 }
 
 // Narrow output (co <= 16, ci = 32): v_mfma_f32_16x16x32_bf16 computes 16
-// voxels x 16 output channels with all 32 input channels in one instruction
+// output channels x 16 voxels with all 32 input channels in one instruction
 // (lane l supplies A[row l%16][k 8(l/16)..+7] and B[k 8(l/16)..+7][col l%16];
 // accumulator j of lane l is D[4(l/16) + j][l%16]), half the work of the
-// 32-wide instruction for a layer with 3 real outputs.  Same tiles, halo and
-// row reuse as k_conv; each output row is two 16-voxel halves.
+// 32-wide instruction for a layer with 3 real outputs.  The same transposed
+// product, tiles, halo and row reuse as k_conv: the narrow packing is the A
+// operand as it stands, and lane l ends with channels 4 (l/16) .. + 3 of
+// voxel l%16 of each 16-voxel half of a row.
+template <int WRAP>
 __global__ __launch_bounds__(NT) void k_conv_n16(ConvArgs a) {
   constexpr int CI = 32;
   constexpr int VS = CI * 2 + 16;
-  constexpr int CH = CI / 8;
-  constexpr int NCHUNK = HX * HY * HZ * CH;
+  constexpr int NCHUNK = HX * HY * HZ * (CI / 8);
   constexpr int PER = (NCHUNK + NT - 1) / NT;
   __shared__ __align__(16) unsigned char sw[27 * 64 * 16];
   __shared__ __align__(16) unsigned char sh[HX * HY * HZ * VS];
-  for (int c = threadIdx.x; c < 27 * 64; c += NT)
-    reinterpret_cast<uint4 *>(sw)[c] = reinterpret_cast<const uint4 *>(a.wp)[c];
+  copy_weights<27 * 64, false>(sw, a.wp);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = lane & 15, grp = lane >> 4;
-  const float bias = (a.bias && col < a.co_store) ? a.bias[col] : 0.f;
-  uint4 pre[PER];
+  float bias[4];
+#pragma unroll
+  for (int j = 0; j < 4; j++) {
+    const int ch = 4 * grp + j;
+    bias[j] = (a.bias && ch < a.co_store) ? a.bias[ch] : 0.f;
+  }
+  int meta[PER];
+#pragma unroll
+  for (int q = 0; q < PER; q++) meta[q] = halo_meta<CI, VS>(threadIdx.x + q * NT);
   for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
     const TileXYZ t = tile_xyz(tile, a.nt0, a.nt1, a.nt2);
+    uint4 pre[PER];
 #pragma unroll
-    for (int q = 0; q < PER; q++) {
-      const int c = threadIdx.x + q * NT;
-      pre[q] = make_uint4(0, 0, 0, 0);
-      if (c < NCHUNK) {
-        const int v = c / CH, part = c - v * CH;
-        const int hx = v % HX, hy = (v / HX) % HY, hz = v / (HX * HY);
-        int gx = t.ox0 + hx + a.off, gy = t.oy0 + hy + a.off, gz = t.oz0 + hz + a.off;
-        bool in = true;
-        if (a.wrap == 1) {
-          gx = wrap1(gx, a.D0), gy = wrap1(gy, a.D1), gz = wrap1(gz, a.D2);
-        } else if (a.wrap) {
-          gx = wrapi(gx, a.D0), gy = wrapi(gy, a.D1), gz = wrapi(gz, a.D2);
-        } else {
-          in = gx >= 0 && gx < a.D0 && gy >= 0 && gy < a.D1 && gz >= 0 && gz < a.D2;
-        }
-        if (in) {
-          const size_t vox = (((size_t)t.b * a.D2 + gz) * a.D1 + gy) * a.D0 + gx;
-          pre[q] = *reinterpret_cast<const uint4 *>(a.x + vox * CI + part * 8);
-        }
-      }
-    }
+    for (int q = 0; q < PER; q++)
+      pre[q] = halo_load<CI, WRAP>(a, meta[q], t.b, t.ox0 + a.off, t.oy0 + a.off, t.oz0 + a.off);
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < PER; q++) {
-      const int c = threadIdx.x + q * NT;
-      if (c < NCHUNK) {
-        const int v = c / CH, part = c - v * CH;
-        *reinterpret_cast<uint4 *>(sh + v * VS + part * 16) = pre[q];
-      }
-    }
+    for (int q = 0; q < PER; q++)
+      if (meta[q] >= 0) *reinterpret_cast<uint4 *>(sh + ((meta[q] >> 14) << 4)) = pre[q];
     __syncthreads();
     f32x4 acc[TY][2];
 #pragma unroll
@@ -284,21 +333,21 @@ __global__ __launch_bounds__(NT) void k_conv_n16(ConvArgs a) {
     for (int tz = 0; tz < 3; tz++) {
 #pragma unroll 1
       for (int tx = 0; tx < 3; tx++) {
-        bf16x8 bw[3];
+        bf16x8 wa[3];
 #pragma unroll
         for (int ty = 0; ty < 3; ty++)
-          bw[ty] = *reinterpret_cast<const bf16x8 *>(sw + ((9 * tz + 3 * ty + tx) * 64 + lane) * 16);
+          wa[ty] = *reinterpret_cast<const bf16x8 *>(sw + ((9 * tz + 3 * ty + tx) * 64 + lane) * 16);
         const unsigned char *base = sh + ((wave + tz) * HY * HX + col + tx) * VS + grp * 16;
 #pragma unroll
         for (int hy = 0; hy < HY; hy++) {
 #pragma unroll
           for (int h = 0; h < 2; h++) {
-            const bf16x8 av = *reinterpret_cast<const bf16x8 *>(base + (hy * HX + 16 * h) * VS);
+            const bf16x8 xb = *reinterpret_cast<const bf16x8 *>(base + (hy * HX + 16 * h) * VS);
 #pragma unroll
             for (int ty = 0; ty < 3; ty++) {
               const int my = hy - ty;
               if (my >= 0 && my < TY)
-                acc[my][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bw[ty], acc[my][h], 0, 0, 0);
+                acc[my][h] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[ty], xb, acc[my][h], 0, 0, 0);
             }
           }
         }
@@ -308,23 +357,26 @@ __global__ __launch_bounds__(NT) void k_conv_n16(ConvArgs a) {
 #pragma unroll
     for (int my = 0; my < TY; my++) {
       const int oy = t.oy0 + my;
-      if (oy >= a.E1 || oz >= a.E2 || col >= a.co_store) continue;
-      const size_t rowv = (((size_t)t.b * a.E2 + oz) * a.E1 + oy) * a.E0;
+      if (oy >= a.E1 || oz >= a.E2) continue;
+      const int64_t rowv = (((int64_t)t.b * a.E2 + oz) * a.E1 + oy) * a.E0;
 #pragma unroll
-      for (int h = 0; h < 2; h++)
+      for (int h = 0; h < 2; h++) {
+        const int ox = t.ox0 + 16 * h + col;
+        if (ox >= a.E0) continue;
+        const int64_t vox = rowv + ox;
 #pragma unroll
         for (int j = 0; j < 4; j++) {
-          const int ox = t.ox0 + 16 * h + 4 * grp + j;
-          if (ox >= a.E0) continue;
-          const size_t vox = rowv + ox;
-          float v = acc[my][h][j] + bias;
+          const int ch = 4 * grp + j;
+          if (ch >= a.co_store) continue;
+          float v = acc[my][h][j] + bias[j];
           if (a.relu) v = fmaxf(v, 0.f);
-          if (a.mask && !((float)a.mask[vox * CO + col] > 0.f)) v = 0.f;
+          if (a.mask && !((float)a.mask[vox * CO + ch] > 0.f)) v = 0.f;
           if (a.out_f32)
-            reinterpret_cast<float *>(a.y)[vox * a.ystride + col] = v;
+            reinterpret_cast<float *>(a.y)[vox * a.ystride + ch] = v;
           else
-            reinterpret_cast<bf16 *>(a.y)[vox * a.ystride + col] = (bf16)v;
+            reinterpret_cast<bf16 *>(a.y)[vox * a.ystride + ch] = (bf16)v;
         }
+      }
     }
   }
 }
@@ -663,10 +715,25 @@ ib_status launch_conv(const bf16 *x, int32_t batch, const int32_t *in_dims, int3
   a.ntiles = (int)nt;
   const int grid = (int)(nt < WG_CONV ? nt : WG_CONV);
   if (wrap && (a.D0 < HX || a.D1 < HY || a.D2 < HZ)) a.wrap = 2;
-  a.idx32 = (vi * ci_pad < ((int64_t)1 << 31)) ? 1 : 0;
-  if (narrow) k_conv_n16<<<grid, NT, 0, st>>>(a);
-  else if (ci_pad == 16) k_conv<16><<<grid, NT, 0, st>>>(a);
-  else k_conv<32><<<grid, NT, 0, st>>>(a);
+  // 16-byte output stores: 32 BF16 channels per voxel at a stride that keeps
+  // every voxel's record 16-byte aligned (and the mask, when given)
+  const bool vec = !narrow && !out_f32 && co_store == CO && y_stride % 8 == 0 &&
+                   !(reinterpret_cast<uintptr_t>(y) & 15) &&
+                   !(reinterpret_cast<uintptr_t>(mask) & 15);
+  auto go = [&](auto wrap_tag) {
+    constexpr int W = decltype(wrap_tag)::value;
+    if (narrow) k_conv_n16<W><<<grid, NT, 0, st>>>(a);
+    else if (ci_pad == 16) {
+      if (vec) k_conv<16, W, true><<<grid, NT, 0, st>>>(a);
+      else k_conv<16, W, false><<<grid, NT, 0, st>>>(a);
+    } else {
+      if (vec) k_conv<32, W, true><<<grid, NT, 0, st>>>(a);
+      else k_conv<32, W, false><<<grid, NT, 0, st>>>(a);
+    }
+  };
+  if (a.wrap == 1) go(std::integral_constant<int, 1>{});
+  else if (a.wrap == 2) go(std::integral_constant<int, 2>{});
+  else go(std::integral_constant<int, 0>{});
   HIP_CHECK_LAUNCH("conv3d");
   return IB_OK;
 }
