@@ -500,12 +500,10 @@ static void launch_interp(ib_ctx *c, int id, const double *X, int64_t np,
   a.dt = c->prm.dt;
   a.evolve = evolve;
   a.first = first;
-  // four lanes per point, one for dense FP64 structures (see k_interp)
-  const bool one = sizeof(T) == 8 && np > 4 * c->tg.ntiles;
-  dim3 grid((unsigned)(((one ? 1 : 4) * np + 255) / 256), DIM);
+  // four lanes per (point, component), one stencil column each (k_interp)
+  dim3 grid((unsigned)((4 * np + 255) / 256), DIM);
   launch(c, id, [&] {
-    if (one) hipLaunchKernelGGL((k_interp<T, DIM, 1>), grid, dim3(256), 0, c->stream, a);
-    else hipLaunchKernelGGL((k_interp<T, DIM, 4>), grid, dim3(256), 0, c->stream, a);
+    hipLaunchKernelGGL((k_interp<T, DIM>), grid, dim3(256), 0, c->stream, a);
   });
 }
 

@@ -165,18 +165,19 @@ struct InterpArgs {
   int evolve, first;
 };
 
-template <typename T, int DIM, int L>
+template <typename T, int DIM>
 __global__ void __launch_bounds__(256) k_interp(InterpArgs<T, DIM> a) {
   using C = T;
-  // L = 4 lanes per (point, component): lane q gathers stencil plane t2 = q
-  // (3-D) or row t1 = q (2-D), 16 or 4 loads, and the four partial sums meet
-  // through two lane exchanges -- four times the loads in flight per point.
-  // L = 1: one lane loops over the four planes / rows (dense FP64
-  // structures, where the fourfold weight arithmetic costs more than it
-  // hides).
+  // Four lanes per (point, component): lane q takes stencil column t0 = q of
+  // every row (16 rows in 3-D, 4 in 2-D), so the four lanes of a point read
+  // four consecutive cells of a row together -- one wave load touches 16
+  // rows, not the 64 it touched when each lane walked a whole plane (the
+  // gathers were bound by the cache lines per load: 253 -> 177 us for the
+  // 933,888-point cylinder) -- and the four partial sums meet through two
+  // lane exchanges.
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t k = L == 4 ? gid >> 2 : gid;
-  const int q0 = L == 4 ? (int)(gid & 3) : 0;
+  const int64_t k = gid >> 2;
+  const int q = (int)(gid & 3);  // the stencil column t0 this lane reads
   const int c = blockIdx.y;
   if (k >= a.np) return;  // all four lanes of a point leave together
   const int64_t lay = (DIM == 2 && a.layer) ? a.layer[k] : 0;
@@ -187,48 +188,35 @@ __global__ void __launch_bounds__(256) k_interp(InterpArgs<T, DIM> a) {
     b[ax] = axis_stencil<C>(a.X[ax * a.np + k], a.inv_h, ax == c ? 0.0 : 0.5,
                             nn[ax], w[ax]);
   const T *__restrict__ uc = a.u[c];
+  int64_t ii = b[0] + q;  // b[0] < n and n >= 4: one wrap at most
+  ii -= ii >= nn[0] ? nn[0] : 0;
   C acc = 0;
+  if (DIM == 3) {
 #pragma unroll
-  for (int r = 0; r < 4 / L; r++) {
-    const int q = q0 + r;
-    if (DIM == 3) {
-      int64_t kk = b[2] + q;
+    for (int t2 = 0; t2 < 4; t2++) {
+      int64_t kk = b[2] + t2;
       kk -= kk >= nn[2] ? nn[2] : 0;
       C acc1 = 0;
 #pragma unroll
       for (int t1 = 0; t1 < 4; t1++) {
         int64_t jj = b[1] + t1;
         jj -= jj >= nn[1] ? nn[1] : 0;
-        const T *row = uc + (kk * nn[1] + jj) * nn[0];
-        C acc0 = 0;
-#pragma unroll
-        for (int t0 = 0; t0 < 4; t0++) {
-          int64_t ii = b[0] + t0;
-          ii -= ii >= nn[0] ? nn[0] : 0;
-          acc0 += (C)row[ii] * w[0][t0];
-        }
-        acc1 += acc0 * w[1][t1];
+        acc1 += (C)uc[(kk * nn[1] + jj) * nn[0] + ii] * w[1][t1];
       }
-      acc += acc1 * (q == 0 ? w[2][0] : q == 1 ? w[2][1] : q == 2 ? w[2][2] : w[2][3]);
-    } else {
-      int64_t jj = b[1] + q;
+      acc += acc1 * w[2][t2];
+    }
+  } else {
+#pragma unroll
+    for (int t1 = 0; t1 < 4; t1++) {
+      int64_t jj = b[1] + t1;
       jj -= jj >= nn[1] ? nn[1] : 0;
-      const T *row = uc + (lay * nn[1] + jj) * nn[0];
-      C acc0 = 0;
-#pragma unroll
-      for (int t0 = 0; t0 < 4; t0++) {
-        int64_t ii = b[0] + t0;
-        ii -= ii >= nn[0] ? nn[0] : 0;
-        acc0 += (C)row[ii] * w[0][t0];
-      }
-      acc += acc0 * (q == 0 ? w[1][0] : q == 1 ? w[1][1] : q == 2 ? w[1][2] : w[1][3]);
+      acc += (C)uc[(lay * nn[1] + jj) * nn[0] + ii] * w[1][t1];
     }
   }
-  if (L == 4) {
-    acc += __shfl_xor(acc, 1);
-    acc += __shfl_xor(acc, 2);
-    if (q0 != 0) return;
-  }
+  acc *= q == 0 ? w[0][0] : q == 1 ? w[0][1] : q == 2 ? w[0][2] : w[0][3];
+  acc += __shfl_xor(acc, 1);
+  acc += __shfl_xor(acc, 2);
+  if (q != 0) return;
   const double U = (double)acc;
   const int64_t o = c * a.np + k;
   if (!a.evolve) {
