@@ -354,6 +354,14 @@ static const SweepTune *tune_of(const ib_ctx *c, int axis, bool r64) {
   return (c && c->tuned) ? &c->tune[axis][r64 ? 1 : 0] : nullptr;
 }
 
+// Lines per workgroup of the plain x sweep with FP64 recurrences (the psi
+// sweeps), as dispatch_x chooses them.
+static int x_lines_per_block(const ib_ctx *c, int64_t N) {
+  const SweepTune *tu = tune_of(c, 0, true);
+  const int M = (tu && tu->x_m) ? tu->x_m : x_chunk(N);
+  return 256 / next_pow2((int)((N + M - 1) / M));
+}
+
 // Launch one sweep along `axis`; `id_x` / `id_s` name it for profiling (the
 // strided id is id_x + 1).  R is the recurrence type of the strided kernel.
 // Channel walls: the y systems are bounded (a.bc per field); they are
@@ -450,10 +458,19 @@ static int64_t gauge_blocks(int64_t per_layer) {  // ~4096 values per block, 1..
   const int64_t nb = (per_layer + 4095) / 4096;
   return nb < 1 ? 1 : (nb > 4096 ? 4096 : nb);
 }
+// The psi sweep before the last writes one partial sum per workgroup, after
+// a count (block_sum_store): at most n1 n2 workgroups for x lines (four or
+// more lines each), ceil(n0/8) max(n1, n2) for strided ones (n2 = layers in
+// 2-D).
+static int64_t gauge_sweep_parts(const ib_grid_params *p) {
+  const int64_t n0 = p->n[0], n1 = p->n[1], n2 = p->n[2];
+  return 1 + std::max<int64_t>(n1 * n2, ((n0 + 7) / 8) * std::max<int64_t>(n1, n2));
+}
 static size_t gauge_bytes(const ib_grid_params *p) {
   const int64_t L = gauge_layers(p);
   const int64_t per = (int64_t)p->n[0] * p->n[1] * (p->dim == 2 ? 1 : p->n[2]);
-  return align256(sizeof(double) * (size_t)(L * (gauge_blocks(per) + 1)));
+  const int64_t parts = std::max(L * gauge_blocks(per), gauge_sweep_parts(p));
+  return align256(sizeof(double) * (size_t)(L + parts));
 }
 
 static size_t workspace_bytes(const ib_grid_params *p, int64_t np) {
@@ -785,7 +802,18 @@ static void enqueue_step(ib_ctx *c, bool overlap) {
   q.f[0] = (T *)c->divn;
   q.o[0] = (T *)c->buf.psi;
   q.bc[0] = SB_NEUMANN_CELL;  // used by wall sweeps only
+  // FP32 work arrays: the mean of psi (zero in exact arithmetic) is measured
+  // before the last sweep, which removes it.  The sweep before the last (the
+  // middle one in 3-D, the first in 2-D) adds up the values it stores per
+  // workgroup, so no pass of its own reads psi again; in 2-D batches every
+  // workgroup's lines must lie in one layer (strided sweeps: always; x lines:
+  // when the lines per workgroup divide n1), else a separate pass sums psi.
+  bool fused_gauge = c->f32;
+  if (fused_gauge && DIM == 2 && order[0] == 0)
+    fused_gauge = c->g.n1 % x_lines_per_block(c, c->g.n0) == 0;
+  q.gpart = (fused_gauge && DIM == 2) ? c->gauge_part : nullptr;
   sweep<T, SW_PLAIN>(c, KP_PSI_X_FIRST, q, order[0], 1, c->stream);
+  q.gpart = nullptr;
   q.inv_c = c->psi_invc;
   q.invc_layer = nullptr;
   q.f[0] = q.o[0] = (T *)c->buf.psi;
@@ -793,18 +821,21 @@ static void enqueue_step(ib_ctx *c, bool overlap) {
   q.divp = (T *)c->buf.div_prev;
   q.p = c->buf.p;
   q.half_chi_mu = 0.5 * c->prm.chi * c->prm.mu;
-  for (int s = 1; s < DIM - 1; s++) sweep<T, SW_PLAIN>(c, KP_PSI_X_PLAIN, q, order[s], 1, c->stream);
+  for (int s = 1; s < DIM - 1; s++) {
+    q.gpart = fused_gauge ? c->gauge_part : nullptr;
+    sweep<T, SW_PLAIN>(c, KP_PSI_X_PLAIN, q, order[s], 1, c->stream);
+    q.gpart = nullptr;
+  }
   if (c->f32) {
-    // FP32 work arrays: measure the mean of psi (zero in exact arithmetic)
-    // before the last sweep, which removes it
     const int64_t layers = DIM == 2 ? c->g.n2 : 1;
     const int64_t per = c->g.ncell / layers;
     const int64_t nb = gauge_blocks(per);
     launch(c, KP_GAUGE, [&] {
-      hipLaunchKernelGGL((k_layer_partial<T>), dim3((unsigned)nb, (unsigned)layers), dim3(256), 0,
-                         c->stream, (const T *)c->buf.psi, per, c->gauge_part);
-      hipLaunchKernelGGL(k_layer_mean, dim3((unsigned)layers), dim3(256), 0, c->stream,
-                         (const double *)c->gauge_part, (int)nb, per, c->gauge);
+      if (!fused_gauge)
+        hipLaunchKernelGGL((k_layer_partial<T>), dim3((unsigned)nb, (unsigned)layers), dim3(256),
+                           0, c->stream, (const T *)c->buf.psi, per, c->gauge_part);
+      hipLaunchKernelGGL(k_layer_mean, dim3((unsigned)layers), dim3(1024), 0, c->stream,
+                         (const double *)c->gauge_part, fused_gauge ? -1 : (int)nb, per, c->gauge);
     });
     q.gauge = c->gauge;
   }

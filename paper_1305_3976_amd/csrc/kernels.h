@@ -1314,6 +1314,7 @@ struct SweepArgs {
   const double *alpha_layer, *invc_layer;  // 2-D batches: per-layer coefficients
   double half_chi_mu;  // PFINAL
   const double *gauge; // PFINAL: per-layer mean of psi removed before use (or null)
+  double *gpart;       // PLAIN, 3-D: per-workgroup sums of the stored values (or null)
   int32_t bc[3];       // channel y sweeps: boundary kind per field (SB_*)
   Grid g;
   int32_t G;           // threads per line (x kernel: power of two <= 64)
@@ -1334,6 +1335,36 @@ __device__ __forceinline__ void sweep_store(const SweepArgs<T> &a, int fld, int6
     const double dsum = (double)dn + (double)a.divp[idx];
     a.p[idx] = a.p[idx] + x - a.half_chi_mu * dsum;
     a.divp[idx] = dn;
+  }
+}
+
+// Gauge partial sums fused into a plain psi sweep (FP32 work arrays): every
+// workgroup adds the values it stores, as stored, in FP64, and writes the sum
+// to part[1 + linear block index] (blockIdx.z, the field, is 0 for psi);
+// block 0 also writes the block count to part[0], so k_layer_mean needs no
+// count from the host.  In 2-D batches the host uses it only where every
+// workgroup's lines lie in one layer, so a layer's sums are a contiguous
+// run of count / layers.  Every thread of the block calls it, with
+// v = 0 for threads that store nothing; the sums are taken in a fixed order
+// (guarded lane reduction, then the waves in order).
+__device__ __forceinline__ void block_sum_store(double v, double *part) {
+  __shared__ double red[16];  // one per wave, at most 1024 threads
+  const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+  const int nthr = blockDim.x * blockDim.y * blockDim.z;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wn = min(64, nthr - (wave << 6));  // lanes of this wave
+  for (int off = 32; off > 0; off >>= 1) {
+    const double o = __shfl_down(v, off);
+    if (lane + off < wn) v += o;
+  }
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  if (tid == 0) {
+    double sum = 0.0;
+    for (int w = 0; w < (nthr + 63) / 64; w++) sum += red[w];
+    const int64_t blk = blockIdx.x + (int64_t)gridDim.x * blockIdx.y;
+    part[1 + blk] = sum;
+    if (blk == 0) part[0] = (double)((int64_t)gridDim.x * gridDim.y);
   }
 }
 
@@ -1496,6 +1527,14 @@ __global__ void __launch_bounds__(256) k_sweep_x(SweepArgs<T> a) {
         r[q] += cx;
       }
   }
+  if (MODE == SW_PLAIN && a.gpart) {
+    double sum = 0.0;
+    if (live)
+#pragma unroll
+      for (int q = 0; q < M; q++)
+        if (VEC || q < cnt) sum += (double)(T)r[q];
+    block_sum_store(sum, a.gpart);
+  }
   if (!live) return;
   if (VEC) {
     const int64_t o = base + s;
@@ -1624,6 +1663,14 @@ __global__ void __launch_bounds__(LB) k_sweep_s(SweepArgs<T> a, int axis) {
         r[q] += pw * xin;
         pw *= al;
       }
+  }
+  if (MODE == SW_PLAIN && a.gpart) {
+    double sum = 0.0;
+    if (live)
+#pragma unroll
+      for (int q = 0; q < M; q++)
+        if (q < cnt) sum += (double)(T)r[q];
+    block_sum_store(sum, a.gpart);
   }
   if (!live) return;
 #pragma unroll
@@ -1781,6 +1828,14 @@ __global__ void __launch_bounds__(LB) k_sweep_sb(SweepArgs<T> a, int axis) {
     for (int q = 0; q < M; q++) r[q] = (EVEN || q < cnt) ? (R)cf.ld(q) : R(0);
   }
   sb_solve<R, M, EVEN>(r, cnt, al, ic, sA, sB, g, G, TX, tx);
+  if (MODE == SW_PLAIN && a.gpart) {
+    double sum = 0.0;
+    if (live)
+#pragma unroll
+      for (int q = 0; q < M; q++)
+        if (EVEN || q < cnt) sum += (double)(T)r[q];
+    block_sum_store(sum, a.gpart);
+  }
   if (!live) return;
   if (MODE == SW_PLAIN) {
     const auto co = col(a.o[fld]);
@@ -1879,8 +1934,15 @@ __global__ void __launch_bounds__(LB) k_sweep_wall(SweepArgs<T> a) {
     }
   }
   sb_solve<R, M, true>(r, M, al, ic, sA, sB, g, G, TX, tx);
-  if (!live || mirror) return;
   const bool wall0 = face && s == 0;  // element 0 is the wall face
+  if (MODE == SW_PLAIN && a.gpart) {
+    double sum = 0.0;
+    if (live && !mirror)
+#pragma unroll
+      for (int q = 0; q < M; q++) sum += (q == 0 && wall0) ? 0.0 : (double)(T)r[q];
+    block_sum_store(sum, a.gpart);
+  }
+  if (!live || mirror) return;
   if (MODE == SW_PLAIN) {
     const auto co = col(a.o[fld]);
 #pragma unroll
@@ -1962,14 +2024,29 @@ __global__ void __launch_bounds__(256) k_layer_partial(const T *f, int64_t per_l
   if (threadIdx.x == 0) partial[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = red[0];
 }
 
-__global__ void __launch_bounds__(256) k_layer_mean(const double *partial, int nblk,
-                                                    int64_t per_layer, double *mean) {
-  __shared__ double red[256];
-  double s = 0.0;
-  for (int i = threadIdx.x; i < nblk; i += 256) s += partial[(int64_t)blockIdx.x * nblk + i];
-  red[threadIdx.x] = s;
+// One workgroup per layer: the mean of its nblk partial sums over per_layer
+// cells.  Each thread keeps four loads in flight (four running sums, combined
+// in a fixed order), so a few thousand partials take a couple of memory
+// round trips rather than one per partial.
+__global__ void __launch_bounds__(1024) k_layer_mean(const double *partial, int nblk,
+                                                     int64_t per_layer, double *mean) {
+  __shared__ double red[1024];
+  if (nblk < 0) {  // partial sums written by a sweep (block_sum_store), layer by layer
+    nblk = (int)partial[0] / (int)gridDim.x;
+    partial += 1;
+  }
+  const double *pl = partial + (int64_t)blockIdx.x * nblk;
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int i = threadIdx.x; i < nblk; i += 4 * 1024) {
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const int j = i + u * 1024;
+      if (j < nblk) s[u] += pl[j];
+    }
+  }
+  red[threadIdx.x] = (s[0] + s[1]) + (s[2] + s[3]);
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
+  for (int w = 512; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
