@@ -480,8 +480,8 @@ static size_t workspace_bytes(const ib_grid_params *p, int64_t np) {
   const size_t lag = sizeof(double) * (size_t)p->dim * npp;
   const TileGrid tg = tile_grid(p);
   const size_t nb = (size_t)((tg.ntiles + SCAN_TILE - 1) / SCAN_TILE);
-  return 7 * align256(nc * t) + 3 * align256(lag) + align256(sizeof(int) * 9 * npp) +
-         align256(t * 36 * npp) + align256(t * 3 * npp) + 3 * align256(sizeof(int) * tg.ntiles) +
+  return 7 * align256(nc * t) + 3 * align256(lag) + align256(sizeof(int) * 6 * npp) +
+         align256(t * 24 * npp) + align256(t * 3 * npp) + 3 * align256(sizeof(int) * tg.ntiles) +
          align256(sizeof(int) * (tg.ntiles + 1)) + align256(sizeof(int) * nb) +
          3 * align256(sizeof(int) * npp) + 256 + 256 + gauge_bytes(p);
 }
@@ -986,8 +986,8 @@ extern "C" ib_status ib_init(ib_ctx **out, const ib_grid_params *prm, const ib_b
   c->tg = tile_grid(prm);
   const size_t tb = align256(sizeof(int) * c->tg.ntiles);
   const size_t pb = align256(sizeof(int) * np);
-  c->st_base = (int *)w; w += align256(sizeof(int) * 9 * np);
-  c->st_wt = w; w += align256(c->tsz * 36 * np);
+  c->st_base = (int *)w; w += align256(sizeof(int) * 6 * np);
+  c->st_wt = w; w += align256(c->tsz * 24 * np);
   c->st_val = w; w += align256(c->tsz * 3 * np);
   c->t_count = (int *)w; w += tb;
   c->t_flag = (int *)w; w += tb;
@@ -1233,8 +1233,8 @@ static size_t carve_spread_tables(ib_ctx *c, const ib_grid_params *p, int64_t np
     off += bytes;
     return q;
   };
-  void *st_base = take(align256(sizeof(int) * 9 * npp));
-  void *st_wt = take(align256(t * 36 * npp));
+  void *st_base = take(align256(sizeof(int) * 6 * npp));
+  void *st_wt = take(align256(t * 24 * npp));
   void *st_val = take(align256(t * 3 * npp));
   void *t_count = take(tb);
   void *t_list = take(tb);

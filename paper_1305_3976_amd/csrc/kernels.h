@@ -437,15 +437,21 @@ __global__ void __launch_bounds__(256) k_scan_write(int *count, int *start, cons
 }
 
 // Place every point at its sorted slot and precompute its stencil there:
-// for each component c and axis, the wrapped start cell and the 4 weights,
-// and the spread value F_c w / h^d -- computed once per point, read by every
-// tile the point reaches.
+// per axis the two stencils the MAC components use -- face-centred (the
+// component along that axis) and cell-centred (every other component) --
+// each a wrapped start cell and 4 weights, and per component the spread
+// value F_c w / h^d: computed once per point, read by every tile the point
+// reaches.  (One stencil per component and axis would store the
+// cell-centred ones twice in 3-D.)
 template <typename T>
 struct Stencils {
-  int *base;  // [(c*3 + ax) * np + slot]
-  T *wt;      // [((c*3 + ax) * 4 + t) * np + slot]
+  int *base;  // [(s*3 + ax) * np + slot], s = 0 face-centred, 1 cell-centred
+  T *wt;      // [((s*3 + ax) * 4 + t) * np + slot]
   T *val;     // [c * np + slot]
 };
+
+// Row of component c's stencil along axis ax in the tables above.
+__device__ __forceinline__ int st_row(int c, int ax) { return (ax == c ? 0 : 3) + ax; }
 
 template <typename T, int DIM>
 __device__ __forceinline__ void scatter_point(int64_t i, const int *tile_of, const int *rank_of,
@@ -463,14 +469,14 @@ __device__ __forceinline__ void scatter_point(int64_t i, const int *tile_of, con
   double xk[DIM];
   for (int ax = 0; ax < DIM; ax++) xk[ax] = X[ax * np + k];
   const double wk = w[k] * inv_hd;
-  for (int c = 0; c < DIM; c++) {
+  for (int sh = 0; sh < 2; sh++)
     for (int ax = 0; ax < DIM; ax++) {
       C wt[4];
-      st.base[(c * 3 + ax) * np + d] = axis_stencil<C>(xk[ax], inv_h, ax == c ? 0.0 : 0.5, nn[ax], wt);
-      for (int t = 0; t < 4; t++) st.wt[((c * 3 + ax) * 4 + t) * np + d] = wt[t];
+      const int row = sh * 3 + ax;
+      st.base[row * np + d] = axis_stencil<C>(xk[ax], inv_h, sh == 0 ? 0.0 : 0.5, nn[ax], wt);
+      for (int t = 0; t < 4; t++) st.wt[(row * 4 + t) * np + d] = wt[t];
     }
-    st.val[c * np + d] = (T)(F[c * np + k] * wk);
-  }
+  for (int c = 0; c < DIM; c++) st.val[c * np + d] = (T)(F[c * np + k] * wk);
 }
 
 // Tiles whose cells lie within 4 cells above an anchor tile, per axis: the
@@ -695,7 +701,7 @@ __global__ void __launch_bounds__(NT) k_spread_tiles(SpreadArgs<T, DIM> a) {
 #pragma unroll
         for (int ax = 0; ax < 3; ax++) {
           bool hit = false;
-          const int b0 = ax < DIM ? a.st.base[(c * 3 + ax) * np + k] : 0;
+          const int b0 = ax < DIM ? a.st.base[st_row(c, ax) * np + k] : 0;
 #pragma unroll
           for (int t = 0; t < 4; t++) {
             if (ax >= DIM) {  // 2-D: the tile's own layer, one offset
@@ -717,9 +723,9 @@ __global__ void __launch_bounds__(NT) k_spread_tiles(SpreadArgs<T, DIM> a) {
         C wx[4], wy[4], wz[4];
 #pragma unroll
         for (int t = 0; t < 4; t++) {
-          wx[t] = a.st.wt[((c * 3 + 0) * 4 + t) * np + k];
-          wy[t] = a.st.wt[((c * 3 + 1) * 4 + t) * np + k];
-          wz[t] = DIM == 3 ? a.st.wt[((c * 3 + 2) * 4 + t) * np + k] : C(1);
+          wx[t] = a.st.wt[(st_row(c, 0) * 4 + t) * np + k];
+          wy[t] = a.st.wt[(st_row(c, 1) * 4 + t) * np + k];
+          wz[t] = DIM == 3 ? a.st.wt[(st_row(c, 2) * 4 + t) * np + k] : C(1);
         }
 #pragma unroll
         for (int t2 = 0; t2 < (DIM == 3 ? 4 : 1); t2++) {
@@ -831,7 +837,7 @@ __global__ void __launch_bounds__(256) k_spread_det(SpreadArgs<T, DIM> a) {
           int off[3] = {0, 0, 0};
           bool in = true;
           for (int ax = 0; ax < DIM; ax++) {
-            int o = g3[ax] - a.st.base[(c * 3 + ax) * np + k];
+            int o = g3[ax] - a.st.base[st_row(c, ax) * np + k];
             o += o < 0 ? nn[ax] : 0;  // base < n, cell < n: one wrap at most
             in &= o < 4;
             off[ax] = o;
@@ -840,9 +846,9 @@ __global__ void __launch_bounds__(256) k_spread_det(SpreadArgs<T, DIM> a) {
           // the product in k_spread_tiles' order: (value z-weight) y-weight,
           // then times the x-weight
           C rw = a.st.val[c * np + k];
-          if (DIM == 3) rw = rw * a.st.wt[((c * 3 + 2) * 4 + off[2]) * np + k];
-          rw = rw * a.st.wt[((c * 3 + 1) * 4 + off[1]) * np + k];
-          acc[c] += (double)(rw * a.st.wt[((c * 3 + 0) * 4 + off[0]) * np + k]);
+          if (DIM == 3) rw = rw * a.st.wt[(st_row(c, 2) * 4 + off[2]) * np + k];
+          rw = rw * a.st.wt[(st_row(c, 1) * 4 + off[1]) * np + k];
+          acc[c] += (double)(rw * a.st.wt[(st_row(c, 0) * 4 + off[0]) * np + k]);
         }
       }
       const int64_t idx = g3[0] + (int64_t)nn[0] * (g3[1] + (int64_t)nn[1] * g3[2]);
