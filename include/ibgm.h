@@ -245,8 +245,8 @@ ib_status ib_spread(ib_ctx *ctx, const double *X, const double *F,
  *   points [dim][npts], weights [npts], f_out[c] [n2][n1][n0] grid dtype).
  *   One problem only: 2-D needs n[2] = 1 (no batch layers).
  *   hip_stream: hipStream_t to enqueue on (NULL = default stream).
- * The tables take about (27 b + 36) npts + 12 ntiles bytes (b = 8 for
- * IB_PREC_FP64, 4 otherwise; ntiles = prod ceil(n[a] / 8)), e.g. 17 MB for
+ * The tables take about (3 b + 36) npts + 12 ntiles bytes (b = 8 for
+ * IB_PREC_FP64, 4 otherwise; ntiles = prod ceil(n[a] / 8)), e.g. 4 MB for
  * 65,536 points on a 256^3 FP64 grid; larger calls return IB_E_UNSUPPORTED
  * and enqueue nothing.  The call allocates nothing and clears what must
  * start at zero (the tile counts, and f_out unless accumulate) with kernels,

@@ -102,8 +102,8 @@ struct ib_ctx {
   TileGrid tg;
   int *t_count, *t_start, *t_flag, *t_bsum, *t_list, *t_nlist, *tile_of, *rank_of;
   int *point_of;  // deterministic spreading: the point in each sorted slot
-  int *st_base;
-  void *st_wt, *st_val;
+  double *st_x;  // sorted point positions [dim][np]
+  void *st_val;  // sorted spread values [dim][np] (grid dtype)
   // structure (library allocation)
   int32_t *ptr, *nbr;
   double *kap, *l0, *w;
@@ -447,9 +447,9 @@ static TileGrid tile_grid(const ib_grid_params *p) {
 }
 
 // Workspace: delta[3], f[3], div_new (grid dtype); X^{n+1}, X^{n+1/2}, F
-// (FP64 [dim][np]); the per-point stencils in sorted order (start cells, 4
-// weights per component and axis, spread values); the spreading tile tables
-// (counts, flags, touched list, starts, block sums), the point sort (tile,
+// (FP64 [dim][np]); the points in sorted order (positions, spread values);
+// the spreading tile tables (counts, flags, touched list, starts, block
+// sums), the point sort (tile,
 // rank, and the point of each slot in the deterministic order); the
 // touched-list length; one status word.
 // psi gauge (mixed policies): per layer, gauge_blocks() partial sums and the mean
@@ -480,8 +480,8 @@ static size_t workspace_bytes(const ib_grid_params *p, int64_t np) {
   const size_t lag = sizeof(double) * (size_t)p->dim * npp;
   const TileGrid tg = tile_grid(p);
   const size_t nb = (size_t)((tg.ntiles + SCAN_TILE - 1) / SCAN_TILE);
-  return 7 * align256(nc * t) + 3 * align256(lag) + align256(sizeof(int) * 6 * npp) +
-         align256(t * 24 * npp) + align256(t * 3 * npp) + 3 * align256(sizeof(int) * tg.ntiles) +
+  return 7 * align256(nc * t) + 3 * align256(lag) + align256(sizeof(double) * 3 * npp) +
+         align256(t * 3 * npp) + 3 * align256(sizeof(int) * tg.ntiles) +
          align256(sizeof(int) * (tg.ntiles + 1)) + align256(sizeof(int) * nb) +
          3 * align256(sizeof(int) * npp) + 256 + 256 + gauge_bytes(p);
 }
@@ -572,7 +572,7 @@ static void launch_spread(ib_ctx *c, const double *X, const double *F, const dou
     hipLaunchKernelGGL(k_scan_write, dim3(nb), dim3(256), 0, c->stream, c->t_count,
                        c->t_start, c->t_bsum, c->tg.ntiles);
   });
-  Stencils<T> stn{c->st_base, (T *)c->st_wt, (T *)c->st_val};
+  Sorted<T> stn{c->st_x, (T *)c->st_val};
   const double inv_hd = 1.0 / std::pow(c->prm.h, DIM);
   const unsigned tb = (unsigned)((c->tg.ntiles + 255) / 256);
   const bool det = (c->prm.flags & IB_FLAG_DETERMINISTIC_SPREAD) != 0;
@@ -590,11 +590,12 @@ static void launch_spread(ib_ctx *c, const double *X, const double *F, const dou
   launch(c, KP_SORT, [&] {
     hipLaunchKernelGGL((k_scatter_touch<T, DIM>), dim3(pb + tb), dim3(256), 0, c->stream,
                        c->tile_of, c->rank_of, c->t_start, det ? c->point_of : nullptr, X, F, w,
-                       stn, c->g, inv_h, inv_hd, np, (int)pb, ADD ? nullptr : c->t_flag,
+                       stn, c->g, inv_hd, np, (int)pb, ADD ? nullptr : c->t_flag,
                        c->t_list, c->t_nlist, c->tg);
   });
   SpreadArgs<T, DIM> a{};
   a.st = stn;
+  a.inv_h = inv_h;
   for (int i = 0; i < 3; i++) a.f[i] = (T *)(i < DIM ? f[i] : nullptr);
   a.start = c->t_start;
   a.list = c->t_list;
@@ -986,8 +987,7 @@ extern "C" ib_status ib_init(ib_ctx **out, const ib_grid_params *prm, const ib_b
   c->tg = tile_grid(prm);
   const size_t tb = align256(sizeof(int) * c->tg.ntiles);
   const size_t pb = align256(sizeof(int) * np);
-  c->st_base = (int *)w; w += align256(sizeof(int) * 6 * np);
-  c->st_wt = w; w += align256(c->tsz * 24 * np);
+  c->st_x = (double *)w; w += align256(sizeof(double) * 3 * np);
   c->st_val = w; w += align256(c->tsz * 3 * np);
   c->t_count = (int *)w; w += tb;
   c->t_flag = (int *)w; w += tb;
@@ -1233,8 +1233,7 @@ static size_t carve_spread_tables(ib_ctx *c, const ib_grid_params *p, int64_t np
     off += bytes;
     return q;
   };
-  void *st_base = take(align256(sizeof(int) * 6 * npp));
-  void *st_wt = take(align256(t * 24 * npp));
+  void *st_x = take(align256(sizeof(double) * 3 * npp));
   void *st_val = take(align256(t * 3 * npp));
   void *t_count = take(tb);
   void *t_list = take(tb);
@@ -1246,8 +1245,7 @@ static size_t carve_spread_tables(ib_ctx *c, const ib_grid_params *p, int64_t np
   void *t_nlist = take(256);
   if (c) {
     c->tg = tg;
-    c->st_base = (int *)st_base;
-    c->st_wt = st_wt;
+    c->st_x = (double *)st_x;
     c->st_val = st_val;
     c->t_count = (int *)t_count;
     c->t_list = (int *)t_list;

@@ -436,46 +436,32 @@ __global__ void __launch_bounds__(256) k_scan_write(int *count, int *start, cons
   if (b < ntiles && b + 4 >= ntiles) start[ntiles] = run;
 }
 
-// Place every point at its sorted slot and precompute its stencil there:
-// per axis the two stencils the MAC components use -- face-centred (the
-// component along that axis) and cell-centred (every other component) --
-// each a wrapped start cell and 4 weights, and per component the spread
-// value F_c w / h^d: computed once per point, read by every tile the point
-// reaches.  (One stencil per component and axis would store the
-// cell-centred ones twice in 3-D.)
+// Place every point at its sorted slot: its position (FP64) and, per
+// component, the spread value F_c w / h^d.  The spreading kernels compute
+// each stencil from the position where they use it (three square roots per
+// point and component, hidden under the LDS atomics): tables of start cells
+// and weights per point (30 values in 3-D) cost more to write and read back
+// than the arithmetic they save -- the 933,888-point cylinder's sort pass
+// wrote 132 bytes per point for them.  The weights come out bitwise the
+// same, computed in the grid precision from the same FP64 coordinate.
 template <typename T>
-struct Stencils {
-  int *base;  // [(s*3 + ax) * np + slot], s = 0 face-centred, 1 cell-centred
-  T *wt;      // [((s*3 + ax) * 4 + t) * np + slot]
+struct Sorted {
+  double *x;  // [ax * np + slot]
   T *val;     // [c * np + slot]
 };
-
-// Row of component c's stencil along axis ax in the tables above.
-__device__ __forceinline__ int st_row(int c, int ax) { return (ax == c ? 0 : 3) + ax; }
 
 template <typename T, int DIM>
 __device__ __forceinline__ void scatter_point(int64_t i, const int *tile_of, const int *rank_of,
                                               const int *start, const int *point_of,
                                               const double *X, const double *F, const double *w,
-                                              Stencils<T> st, Grid g, double inv_h,
-                                              double inv_hd, int64_t np) {
-  using C = T;
+                                              Sorted<T> st, double inv_hd, int64_t np) {
   if (i >= np) return;
   // i is a point (slot start[tile] + rank) or, with point_of (the
   // deterministic order), a slot whose point point_of[i] is
   const int64_t k = point_of ? point_of[i] : i;
   const int64_t d = point_of ? i : start[tile_of[k]] + rank_of[k];
-  const int32_t nn[3] = {g.n0, g.n1, g.n2};
-  double xk[DIM];
-  for (int ax = 0; ax < DIM; ax++) xk[ax] = X[ax * np + k];
+  for (int ax = 0; ax < DIM; ax++) st.x[ax * np + d] = X[ax * np + k];
   const double wk = w[k] * inv_hd;
-  for (int sh = 0; sh < 2; sh++)
-    for (int ax = 0; ax < DIM; ax++) {
-      C wt[4];
-      const int row = sh * 3 + ax;
-      st.base[row * np + d] = axis_stencil<C>(xk[ax], inv_h, sh == 0 ? 0.0 : 0.5, nn[ax], wt);
-      for (int t = 0; t < 4; t++) st.wt[(row * 4 + t) * np + d] = wt[t];
-    }
   for (int c = 0; c < DIM; c++) st.val[c * np + d] = (T)(F[c * np + k] * wk);
 }
 
@@ -553,13 +539,13 @@ template <typename T, int DIM>
 __global__ void __launch_bounds__(256) k_scatter_touch(const int *tile_of, const int *rank_of,
                                                         const int *start, const int *point_of,
                                                         const double *X, const double *F,
-                                                        const double *w, Stencils<T> st, Grid g,
-                                                        double inv_h, double inv_hd, int64_t np,
+                                                        const double *w, Sorted<T> st, Grid g,
+                                                        double inv_hd, int64_t np,
                                                         int pblocks, int *flag, int *list,
                                                         int *nlist, TileGrid tg) {
   if ((int)blockIdx.x < pblocks)
     scatter_point<T, DIM>((int64_t)blockIdx.x * blockDim.x + threadIdx.x, tile_of, rank_of, start,
-                          point_of, X, F, w, st, g, inv_h, inv_hd, np);
+                          point_of, X, F, w, st, inv_hd, np);
   else
     touch_tile<DIM>((int)((blockIdx.x - pblocks) * blockDim.x + threadIdx.x), start, flag, list,
                     nlist, g, tg);
@@ -595,7 +581,8 @@ __global__ void __launch_bounds__(256) k_order_tiles(const int *start, int *poin
 
 template <typename T, int DIM>
 struct SpreadArgs {
-  Stencils<T> st;  // points in sorted order
+  Sorted<T> st;  // points in sorted order
+  double inv_h;
   T *f[3];
   const int *start, *list, *nlist;
   int64_t np;
@@ -698,10 +685,16 @@ __global__ void __launch_bounds__(NT) k_spread_tiles(SpreadArgs<T, DIM> a) {
         // cells 7, 8, 0, 1, of which 7, 0, 1 lie in tile 0).
         int loc[3][4];
         bool any = true;
+        // component c's stencil along each axis, from the sorted position
+        C wx[4], wy[4], wz[4] = {C(1), C(0), C(0), C(0)};
+        int b3[3] = {0, 0, 0};
+        b3[0] = axis_stencil<C>(a.st.x[k], a.inv_h, c == 0 ? 0.0 : 0.5, nn[0], wx);
+        b3[1] = axis_stencil<C>(a.st.x[np + k], a.inv_h, c == 1 ? 0.0 : 0.5, nn[1], wy);
+        if (DIM == 3) b3[2] = axis_stencil<C>(a.st.x[2 * np + k], a.inv_h, c == 2 ? 0.0 : 0.5, nn[2], wz);
 #pragma unroll
         for (int ax = 0; ax < 3; ax++) {
           bool hit = false;
-          const int b0 = ax < DIM ? a.st.base[st_row(c, ax) * np + k] : 0;
+          const int b0 = b3[ax];
 #pragma unroll
           for (int t = 0; t < 4; t++) {
             if (ax >= DIM) {  // 2-D: the tile's own layer, one offset
@@ -717,16 +710,7 @@ __global__ void __launch_bounds__(NT) k_spread_tiles(SpreadArgs<T, DIM> a) {
           any &= ax >= DIM || hit;
         }
         if (!any) continue;
-        // the 4 weights per axis in registers (loaded together), then the
-        // in-tile part of the stencil, fully unrolled and predicated
         const C val = a.st.val[c * np + k];
-        C wx[4], wy[4], wz[4];
-#pragma unroll
-        for (int t = 0; t < 4; t++) {
-          wx[t] = a.st.wt[(st_row(c, 0) * 4 + t) * np + k];
-          wy[t] = a.st.wt[(st_row(c, 1) * 4 + t) * np + k];
-          wz[t] = DIM == 3 ? a.st.wt[(st_row(c, 2) * 4 + t) * np + k] : C(1);
-        }
 #pragma unroll
         for (int t2 = 0; t2 < (DIM == 3 ? 4 : 1); t2++) {
           const int lz = loc[2][t2];
@@ -835,20 +819,23 @@ __global__ void __launch_bounds__(256) k_spread_det(SpreadArgs<T, DIM> a) {
         for (int c = 0; c < DIM; c++) {
           // offset of this cell in the point's stencil along each axis
           int off[3] = {0, 0, 0};
+          C wt[3][4];
           bool in = true;
           for (int ax = 0; ax < DIM; ax++) {
-            int o = g3[ax] - a.st.base[st_row(c, ax) * np + k];
+            const int b0 = axis_stencil<C>(a.st.x[ax * np + k], a.inv_h, ax == c ? 0.0 : 0.5,
+                                           nn[ax], wt[ax]);
+            int o = g3[ax] - b0;
             o += o < 0 ? nn[ax] : 0;  // base < n, cell < n: one wrap at most
             in &= o < 4;
-            off[ax] = o;
+            off[ax] = in ? o : 0;
           }
           if (!in) continue;
           // the product in k_spread_tiles' order: (value z-weight) y-weight,
           // then times the x-weight
           C rw = a.st.val[c * np + k];
-          if (DIM == 3) rw = rw * a.st.wt[(st_row(c, 2) * 4 + off[2]) * np + k];
-          rw = rw * a.st.wt[(st_row(c, 1) * 4 + off[1]) * np + k];
-          acc[c] += (double)(rw * a.st.wt[(st_row(c, 0) * 4 + off[0]) * np + k]);
+          if (DIM == 3) rw = rw * wt[2][off[2]];
+          rw = rw * wt[1][off[1]];
+          acc[c] += (double)(rw * wt[0][off[0]]);
         }
       }
       const int64_t idx = g3[0] + (int64_t)nn[0] * (g3[1] + (int64_t)nn[1] * g3[2]);

@@ -24,6 +24,7 @@ IB_PREC_FP64, IB_PREC_MIXED, IB_PREC_MIXED_STATE64 = 0, 1, 2
 IB_FLAG_NO_ADVECTION = 1
 IB_FLAG_WALLS_Y = 2
 IB_FLAG_DETERMINISTIC_SPREAD = 4
+IB_SPREAD_STATIC_MAX_BYTES = 32 << 20  # the static array of ib_spread_static
 IB_GRAPH_BRANCHES = 1
 
 _vp = ctypes.c_void_p

@@ -102,3 +102,16 @@ def test_point_count_limit(ib):
                         ctypes.byref(ib.Structure()), None)
     assert st == ib.IB_E_UNSUPPORTED and not ctx.value
     assert b"n_points" in ib.lib.ib_last_error(None)
+
+
+def test_static_array_size_matches_header():
+    """The Python copy of IB_SPREAD_STATIC_MAX_BYTES is the header's value
+    (tests size their refusal cases by it)."""
+    import os
+    import re
+    from paper_1305_3976_amd import ibgm
+    hdr = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                            "include", "ibgm.h")).read()
+    m = re.search(r"#define IB_SPREAD_STATIC_MAX_BYTES \((\d+)u << (\d+)\)", hdr)
+    assert m
+    assert ibgm.IB_SPREAD_STATIC_MAX_BYTES == int(m.group(1)) << int(m.group(2))

@@ -84,7 +84,8 @@ HOST_CHECKS = textwrap.dedent(r'''
     # allocation-free spreading: beyond the static array, batches, null pointers
     ptrs = (ctypes.c_void_p * 3)(0x1000, 0x1000, 0x1000)
     P3 = ibgm.Config(3, (256, 256, 256), 1 / 256, mu=0.01, dt=5e-4).params()
-    expect(L.ib_spread_static(ctypes.byref(P3), fake, fake, fake, ctypes.c_int64(200000), ptrs,
+    expect(L.ib_spread_static(ctypes.byref(P3), fake, fake, fake,
+                              ctypes.c_int64(ibgm.IB_SPREAD_STATIC_MAX_BYTES + 1), ptrs,
                               0, None), 2)
     Q = ibgm.Config(2, (64, 64, 3), 1 / 64, mu=0.01, dt=1e-3).params()
     expect(L.ib_spread_static(ctypes.byref(Q), fake, fake, fake, ctypes.c_int64(10), ptrs, 0,

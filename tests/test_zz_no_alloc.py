@@ -132,7 +132,11 @@ def test_static_rejects_what_it_cannot_hold():
     P = cfg.params()
     fake = ctypes.c_void_p(0x1000)   # never dereferenced: validation fails first
     ptrs = (ctypes.c_void_p * 3)(0x1000, 0x1000, 0x1000)
-    st = ibgm.lib.ib_spread_static(ctypes.byref(P), fake, fake, fake, 200000, ptrs, 0, None)
+    # more points than the static array has bytes: whatever the tables hold
+    # per point (the point sort alone keeps several ints), this is refused on
+    # the host -- a count that fits would enqueue kernels on the fake pointers
+    too_many = ibgm.IB_SPREAD_STATIC_MAX_BYTES + 1
+    st = ibgm.lib.ib_spread_static(ctypes.byref(P), fake, fake, fake, too_many, ptrs, 0, None)
     assert st == ibgm.IB_E_UNSUPPORTED
     assert b"static array" in ibgm.lib.ib_last_error()
     Q = ibgm.Config(2, (64, 64, 3), 1 / 64, mu=0.01, dt=1e-3).params()
