@@ -604,10 +604,16 @@ static void launch_spread(ib_ctx *c, const double *X, const double *F, const dou
   a.g = c->g;
   a.tg = c->tg;
   const unsigned grid = (unsigned)std::min<int64_t>(c->tg.ntiles, 4096);
-  // dense structures (many points per tile of the grid) give each touched
-  // tile thousands of candidates: four times the threads per tile then hide
-  // more latency; sparse ones keep 256 so small tiles do not idle threads
-  const bool dense = np > 4 * c->tg.ntiles;
+  // Threads per touched tile: 1024 for a dense structure (over four points
+  // per tile of the grid) on a grid of at most 8192 tiles (up to 160^3 in
+  // 3-D), where the few touched tiles would leave the GPU half idle with
+  // 256-thread workgroups; 256 otherwise -- on larger grids a dense
+  // structure touches enough tiles, and smaller workgroups contend less for
+  // each tile's LDS sums.  Measured: the 933,888-point cylinder at 256^3
+  // (28 points per tile) 1.354 -> 1.247 ms per step with 256; at 128^3
+  // 0.343 (1024) vs 0.360 ms (256); the closure's 128^3 coarse step 0.269
+  // (1024) vs 0.344 ms (256).
+  const bool dense = np > 4 * c->tg.ntiles && c->tg.ntiles <= 8192;
   launch(c, KP_SPREAD, [&] {
     if (det)
       hipLaunchKernelGGL((k_spread_det<T, DIM, ADD>), dim3(grid), dim3(256), 0, c->stream, a);
