@@ -44,7 +44,8 @@ class Params(ctypes.Structure):
                 ("mu", ctypes.c_double), ("dt", ctypes.c_double),
                 ("chi", ctypes.c_double), ("rotate", ctypes.c_int32),
                 ("no_advection", ctypes.c_int32), ("walls_y", ctypes.c_int32),
-                ("body_force", ctypes.c_double * 3)]
+                ("body_force", ctypes.c_double * 3),
+                ("wall_velocity", ctypes.c_double * 3)]
 
 
 class _Sim(ctypes.Structure):
@@ -102,7 +103,8 @@ def _pi(a: np.ndarray):
 
 
 def make_params(dim, n, h, rho=1.0, mu=0.0, dt=1e-3, chi=0.6, rotate=True,
-                no_advection=False, walls_y=False, body_force=(0.0, 0.0, 0.0)) -> Params:
+                no_advection=False, walls_y=False, body_force=(0.0, 0.0, 0.0),
+                wall_velocity=(0.0, 0.0, 0.0)) -> Params:
     nn = list(n) + [1] * (3 - len(n))
     P = Params()
     P.dim = dim
@@ -114,6 +116,7 @@ def make_params(dim, n, h, rho=1.0, mu=0.0, dt=1e-3, chi=0.6, rotate=True,
     P.walls_y = 1 if walls_y else 0
     for a in range(3):
         P.body_force[a] = float(body_force[a]) if a < len(body_force) else 0.0
+        P.wall_velocity[a] = float(wall_velocity[a]) if a < len(wall_velocity) else 0.0
     return P
 
 

@@ -58,16 +58,18 @@ static double at(const ibo_params *P, const double *q, int64_t i, int64_t j,
 
 /* Velocity component c at integer index (i, j, k).  Periodic, except across
  * the channel's walls (walls_y): a tangential component (c != 1, stored at
- * cell centres in y) takes the no-slip ghost value -u of the cell across the
- * wall; v (c == 1) is stored on the y faces, face 0 is the wall (both walls,
- * periodically) and holds 0, so plain periodic indexing already gives the
- * wall value there. */
+ * cell centres in y) takes the no-slip ghost value of the cell across the
+ * wall, -u at the lower wall (at rest) and 2 U_c - u at the upper wall
+ * moving with U (so the mean of the two values straddling a wall is the
+ * wall's velocity); v (c == 1) is stored on the y faces, face 0 is the wall
+ * (both walls, periodically) and holds 0, so plain periodic indexing
+ * already gives the wall value there. */
 static double vel(const ibo_params *P, int32_t c, const double *q, int64_t i, int64_t j,
                   int64_t k) {
   if (P->walls_y && c != 1) {
     const int64_t n1 = P->n[1];
     if (j < 0) return -at(P, q, i, -1 - j, k);
-    if (j >= n1) return -at(P, q, i, 2 * n1 - 1 - j, k);
+    if (j >= n1) return 2.0 * P->wall_velocity[c] - at(P, q, i, 2 * n1 - 1 - j, k);
   }
   return at(P, q, i, j, k);
 }
@@ -79,6 +81,9 @@ static int valid_params(const ibo_params *P) {
   if (P->dim == 2 && P->n[2] != 1) return 0;
   if (!(P->h > 0) || !(P->rho > 0) || !(P->dt > 0) || !(P->mu >= 0))
     return 0;
+  /* a wall velocity needs the walls, and is tangential */
+  for (int a = 0; a < 3; a++)
+    if (P->wall_velocity[a] != 0.0 && (!P->walls_y || a == 1)) return 0;
   return 1;
 }
 
@@ -616,6 +621,15 @@ int ibo_step(ibo_sim *s) {
       const int32_t bc = (P->walls_y && ax == 1)
                              ? (c == 1 ? IBO_BC_DIRICHLET_FACE : IBO_BC_DIRICHLET_CELL)
                              : IBO_BC_PERIODIC;
+      /* a moving upper wall: the unknown's ghost across it is 2 U_c - u, so
+       * the row next to it carries the known part 2 nu U_c / h^2 on the
+       * right-hand side and the solve keeps its homogeneous condition */
+      if (bc == IBO_BC_DIRICHLET_CELL && P->wall_velocity[c] != 0.0) {
+        const int64_t n0 = P->n[0], n1 = P->n[1];
+        for (int64_t k = 0; k < P->n[2]; k++)
+          for (int64_t i = 0; i < n0; i++)
+            us[c][i + n0 * ((n1 - 1) + n1 * k)] += 2.0 * nu * P->wall_velocity[c] / (h * h);
+      }
       rc = ibo_line_solve_bc(us[c], P->n, ax, 1.0 + 2.0 * nu / (h * h), -nu / (h * h), bc);
     }
   }

@@ -35,6 +35,9 @@ typedef struct {
   int32_t walls_y;    /* 1: no-slip walls at y = 0 and y = n1 h (a channel,
                          periodic in x and z); 0: periodic in y */
   double body_force[3]; /* uniform force density added to f (0: none) */
+  double wall_velocity[3]; /* walls_y: velocity of the upper wall y = n1 h
+                              (tangential: x and z; [1] is 0); the lower wall
+                              is at rest.  0 without walls */
 } ibo_params;
 
 typedef struct {

@@ -62,6 +62,7 @@ static double run_case(int dim, int n0, int n1, int n2, int walls, int noadv, in
   P.no_advection = noadv;
   P.walls_y = walls;
   P.body_force[0] = walls ? 0.5 : 0.1;
+  P.wall_velocity[0] = walls ? 0.3 : 0.0; /* a moving upper wall */
   const int64_t nc = (int64_t)P.n[0] * P.n[1] * P.n[2];
   const double box[3] = {n0 * P.h, n1 * P.h, P.n[2] * P.h};
   const int64_t np = 37;

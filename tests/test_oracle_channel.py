@@ -194,3 +194,59 @@ def test_tethered_ring_holds_in_driven_channel():
             assert np.abs(s.u[1][:, 0, :]).max() == 0.0
     assert moved[2e4] < 0.05 * h
     assert moved[0.0] > 20 * moved[2e4]
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_moving_wall_drives_discrete_couette_flow(dim):
+    """The upper wall moving with U (tangential: x, and z in 3-D), the lower
+    at rest, from rest: the steady state of the discrete scheme is the linear
+    profile u_j = U y_j / L, y_j = (j + 1/2) h -- with the ghost -u below and
+    2U - u above it continues linearly across both walls, so D_yy u = 0 --
+    and v, p, psi stay zero.  A wrong ghost (-u above) would leave the fluid
+    at rest; a y solve without the wall's known term would bend the profile
+    next to the wall."""
+    n = (8, 16, 4 if dim == 3 else 1)
+    h = 1.0 / 16
+    mu, dt, steps = 1.0, 0.01, 400
+    U = (0.7, 0.0, -0.4 if dim == 3 else 0.0)
+    P = oracle.make_params(dim, n, h, mu=mu, dt=dt, walls_y=True, wall_velocity=U)
+    shp = (n[2], n[1], n[0])
+    s = oracle.Sim(P, [np.zeros(shp) for _ in range(dim)], np.full((dim, 1), 0.5), NO_LINKS,
+                   np.zeros(1)).advance(steps)
+    y = (np.arange(n[1]) + 0.5) * h
+    L = n[1] * h
+    for c in (0, 2) if dim == 3 else (0,):
+        want = U[c] * y / L
+        assert np.abs(s.u[c] - want[None, :, None]).max() < 1e-12 * abs(U[c])
+    assert np.abs(s.u[1]).max() < 1e-13
+    assert np.abs(s.p).max() < 1e-11 and np.abs(s.psi).max() < 1e-11
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_couette_profile_is_a_fixed_point(dim):
+    """Started on the linear profile of a moving upper wall, with the
+    advection term on, the scheme leaves it in place to rounding (it is an
+    exact steady solution of every step of the method)."""
+    n = (8, 32, 4 if dim == 3 else 1)
+    h = 1.0 / 32
+    U = (1.3, 0.0, 0.5 if dim == 3 else 0.0)
+    P = oracle.make_params(dim, n, h, mu=0.01, dt=1e-3, walls_y=True, wall_velocity=U)
+    shp = (n[2], n[1], n[0])
+    y = (np.arange(n[1]) + 0.5) * h
+    u0 = [np.broadcast_to((U[c] * y / (n[1] * h))[None, :, None], shp).copy() for c in range(dim)]
+    u0[1][:] = 0.0
+    s = oracle.Sim(P, [a.copy() for a in u0], np.full((dim, 1), 0.5), NO_LINKS,
+                   np.zeros(1)).advance(5)
+    for c in range(dim):
+        assert np.abs(s.u[c] - u0[c]).max() < 1e-14
+    assert np.abs(s.p).max() < 1e-12
+
+
+def test_wall_velocity_needs_tangential_walls():
+    """A wall velocity without walls, or along y, is refused."""
+    S = (np.full((2, 1), 0.5), NO_LINKS, np.zeros(1))
+    for kw in ({"walls_y": False, "wall_velocity": (1.0, 0.0, 0.0)},
+               {"walls_y": True, "wall_velocity": (0.0, 1.0, 0.0)}):
+        P = oracle.make_params(2, (8, 16), 1.0 / 16, mu=0.1, **kw)
+        with pytest.raises(Exception):
+            oracle.Sim(P, [np.zeros((1, 16, 8))] * 2, *S).advance(1)
