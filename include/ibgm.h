@@ -76,7 +76,8 @@ typedef enum {
 /* No-slip walls at y = 0 and y = n[1] h: a channel, periodic in x (and z).
  * The solver is not tied to periodic boundaries and the channel is the
  * paper's example (Sec. "Comparison with Poisson Solvers").  u (and w) take
- * the ghost value -u across a wall, v is zero on the wall faces (y-face row
+ * the ghost value -u across a wall (2 U - u across the upper wall when it
+ * moves with U, ib_grid_params.wall_velocity), v is zero on the wall faces (y-face row
  * j = 0, which is both walls periodically; the caller's initial v must be
  * zero there), psi takes a homogeneous Neumann condition; the y sweeps solve
  * these bounded systems as periodic ones on the odd / even mirror image of
@@ -123,6 +124,12 @@ typedef struct {
                            of the momentum equation (Sec. "Governing
                            Equations"), e.g. the mean pressure gradient that
                            drives a channel; zeros for none; finite */
+  double wall_velocity[3]; /* IB_FLAG_WALLS_Y: velocity of the upper wall
+                           (y = n[1] h), tangential only ([0], and [2] in
+                           3-D; [1] must be 0); the lower wall is at rest.
+                           Across it a tangential component takes the ghost
+                           2 U - u.  A moving wall drives Couette flow.  Zeros
+                           without walls (else IB_E_INVALID); finite */
 } ib_grid_params;
 
 /* Device state, caller-owned, borrowed by the context until ib_destroy.

@@ -426,6 +426,13 @@ static ib_status check_params(const ib_grid_params *p) {
   if (p->step0 < 0) return fail(IB_E_INVALID, "step0 must be >= 0");
   for (int a = 0; a < 3; a++)
     if (!std::isfinite(p->body_force[a])) return fail(IB_E_INVALID, "body_force must be finite");
+  for (int a = 0; a < 3; a++) {
+    if (!std::isfinite(p->wall_velocity[a]))
+      return fail(IB_E_INVALID, "wall_velocity must be finite");
+    if (p->wall_velocity[a] != 0.0 && (!(p->flags & IB_FLAG_WALLS_Y) || a == 1 || a >= p->dim))
+      return fail(IB_E_INVALID,
+                  "wall_velocity needs IB_FLAG_WALLS_Y and is tangential (x, and z in 3-D)");
+  }
   if (p->flags & ~(IB_FLAG_NO_ADVECTION | IB_FLAG_WALLS_Y | IB_FLAG_DETERMINISTIC_SPREAD))
     return fail(IB_E_INVALID, "unknown flags 0x%x", p->flags);
   if (p->flags & IB_FLAG_WALLS_Y) {
@@ -654,6 +661,7 @@ static ExplicitArgs<T, DIM, V> explicit_args(ib_ctx *c, bool first) {
   a.advect = !(c->prm.flags & IB_FLAG_NO_ADVECTION);
   a.walls = (c->prm.flags & IB_FLAG_WALLS_Y) ? 1 : 0;
   for (int i = 0; i < 3; i++) a.g_body[i] = i < DIM ? c->prm.body_force[i] : 0.0;
+  for (int i = 0; i < 3; i++) a.wall_u[i] = i < DIM ? c->prm.wall_velocity[i] : 0.0;
   return a;
 }
 

@@ -893,6 +893,7 @@ struct ExplicitArgs {
   double inv_h, inv_h2, dt, mu, inv_rho;
   int first, advect;
   int walls;  // channel: no-slip walls at y = 0 and y = n1 h
+  double wall_u[3];  // velocity of the upper wall (tangential components)
   double g_body[3];  // uniform body force density added to f
   int ez;  // planes per workgroup of the 3-D plane-marching kernel
 };
@@ -925,10 +926,11 @@ __global__ void __launch_bounds__(256) k_explicit(ExplicitArgs<T, DIM, V> a) {
       i / TS + (int64_t)a.tg.nt[0] * (j / TS + (int64_t)a.tg.nt[1] * (DIM == 3 ? k / TS : k));
   const bool forced = a.flag[tile] != 0;
   const C dt = (C)((DIM == 2 && a.dt_layer) ? a.dt_layer[k] : a.dt);
-  // channel walls: across y = 0 and y = n1 h a tangential component takes
-  // the no-slip ghost value -u; v lives on the y faces, whose row 0 is the
-  // wall (both walls, periodically) and holds 0, so periodic indexing gives
-  // the wall value there and v is not advanced on it
+  // channel walls: across y = 0 a tangential component takes the no-slip
+  // ghost value -u, across y = n1 h the value 2 U - u of a wall moving with
+  // U; v lives on the y faces, whose row 0 is the wall (both walls,
+  // periodically) and holds 0, so periodic indexing gives the wall value
+  // there and v is not advanced on it
   const bool wlo = a.walls && j == 0, whi = a.walls && j + 1 == n1;
 #pragma unroll
   for (int ci = 0; ci < DIM; ci++) {
@@ -944,7 +946,7 @@ __global__ void __launch_bounds__(256) k_explicit(ExplicitArgs<T, DIM, V> a) {
     for (int cj = 0; cj < DIM; cj++) {
       C up = (C)ui[idx + dp[cj]], um = (C)ui[idx + dm[cj]];
       if (cj == 1 && ci != 1) {
-        if (whi) up = -u0;
+        if (whi) up = C(2) * (C)a.wall_u[ci] - u0;
         if (wlo) um = -u0;
       }
       lap += up - C(2) * u0 + um;
@@ -979,11 +981,12 @@ __global__ void __launch_bounds__(256) k_explicit(ExplicitArgs<T, DIM, V> a) {
 // at(comp, slot, dx, dy) reads component comp on plane slot (sm: k-1,
 // s0: k, sp: k+1) at the in-plane neighbour (dx, dy) of this cell.  The
 // z neighbours of a plane are the slots; channel walls replace a tangential
-// component's y neighbour across the wall by its no-slip ghost -u.
+// component's y neighbour across the wall by its no-slip ghost: -u below,
+// 2 uw - u above (uw: the upper wall's velocity along ci).
 template <typename C, typename At>
 __device__ __forceinline__ void momentum_terms(const At &at, int ci, int sm, int s0, int sp,
-                                               bool wlo, bool whi, bool advect, C inv_h, C &lap,
-                                               C &N) {
+                                               bool wlo, bool whi, C uw, bool advect, C inv_h,
+                                               C &lap, C &N) {
   constexpr int ox[3] = {1, 0, 0}, oy[3] = {0, 1, 0};
   const int slm[3] = {s0, s0, sm}, slp[3] = {s0, s0, sp};
   const C u0 = at(ci, s0, 0, 0);
@@ -994,7 +997,7 @@ __device__ __forceinline__ void momentum_terms(const At &at, int ci, int sm, int
     C up = at(ci, slp[cj], ox[cj], oy[cj]);
     C um = at(ci, slm[cj], -ox[cj], -oy[cj]);
     if (cj == 1 && ci != 1) {  // no-slip ghosts across a channel wall
-      if (whi) up = -u0;
+      if (whi) up = C(2) * uw - u0;
       if (wlo) um = -u0;
     }
     lap += up - C(2) * u0 + um;
@@ -1148,7 +1151,8 @@ __global__ void __launch_bounds__(ENT) k_explicit3(ExplicitArgs<T, 3, V> a) {
         continue;
       }
       C lap, N;
-      momentum_terms<C>(at, ci, sm, s0, sp, wlo, whi, a.advect != 0, (C)a.inv_h, lap, N);
+      momentum_terms<C>(at, ci, sm, s0, sp, wlo, whi, (C)a.wall_u[ci], a.advect != 0,
+                        (C)a.inv_h, lap, N);
       const C gp = (C)((ps0 - psm[ci]) * a.inv_h);
       const C Nh = a.first ? N : C(1.5) * N - C(0.5) * nlp[ci];
       const C d = (C)a.dt * (-Nh + ((C)a.mu * lap * (C)a.inv_h2 - gp + fc[ci]) * (C)a.inv_rho);

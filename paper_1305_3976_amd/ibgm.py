@@ -37,7 +37,8 @@ class GridParams(ctypes.Structure):
                 ("chi", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("rotate_split", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("step0", ctypes.c_int64), ("layer_dt", _dp),
-                ("body_force", ctypes.c_double * 3)]
+                ("body_force", ctypes.c_double * 3),
+                ("wall_velocity", ctypes.c_double * 3)]
 
 
 class Buffers(ctypes.Structure):
@@ -221,6 +222,7 @@ class Config:
     layer_dt: tuple = None  # 2-D batches: time step of each layer
     walls_y: bool = False   # channel: no-slip walls at y = 0 and y = n[1] h
     body_force: tuple = (0.0, 0.0, 0.0)  # uniform force density added to f
+    wall_velocity: tuple = (0.0, 0.0, 0.0)  # walls_y: the upper wall's velocity (x, z)
     deterministic_spread: bool = False  # bitwise-reproducible spreading (slower)
 
     def params(self, step0: int = 0) -> GridParams:
@@ -240,6 +242,8 @@ class Config:
         P.step0 = step0
         for a in range(3):
             P.body_force[a] = float(self.body_force[a]) if a < len(self.body_force) else 0.0
+            P.wall_velocity[a] = (float(self.wall_velocity[a]) if a < len(self.wall_velocity)
+                                  else 0.0)
         if self.layer_dt is not None:
             self._ldt = np.ascontiguousarray(self.layer_dt, dtype=np.float64)
             P.layer_dt = self._ldt.ctypes.data_as(_dp)

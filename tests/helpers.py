@@ -34,22 +34,23 @@ def rel_l2(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
 
 
-def oracle_sim(w, rotate=True, no_advection=False, walls_y=False, body_force=(0.0, 0.0, 0.0)):
+def oracle_sim(w, rotate=True, no_advection=False, walls_y=False, body_force=(0.0, 0.0, 0.0),
+               wall_velocity=(0.0, 0.0, 0.0)):
     P = oracle.make_params(w.dim, w.n, w.h, rho=w.rho, mu=w.mu, dt=w.dt, chi=w.chi,
                            rotate=rotate, no_advection=no_advection, walls_y=walls_y,
-                           body_force=body_force)
+                           body_force=body_force, wall_velocity=wall_velocity)
     S = w.structure
     return oracle.Sim(P, [np.asarray(c, dtype=np.float64) for c in w.u0], S.X, S.links, S.w,
                       tether=S.tether)
 
 
 def gpu_sim(w, precision, rotate=True, no_advection=False, walls_y=False,
-            body_force=(0.0, 0.0, 0.0), deterministic=False):
+            body_force=(0.0, 0.0, 0.0), deterministic=False, wall_velocity=(0.0, 0.0, 0.0)):
     from paper_1305_3976_amd import ibgm
     cfg = ibgm.Config(w.dim, w.n, w.h, rho=w.rho, mu=w.mu, dt=w.dt, chi=w.chi,
                       precision=precision, rotate_split=rotate, no_advection=no_advection,
                       walls_y=walls_y, body_force=body_force,
-                      deterministic_spread=deterministic)
+                      deterministic_spread=deterministic, wall_velocity=wall_velocity)
     return ibgm.Simulation(cfg, w.u0, w.structure)
 
 

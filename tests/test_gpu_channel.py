@@ -224,3 +224,97 @@ def test_channel_256_full_size(channel256_oracle, precision):
     check(errs, precision, 256)
     assert np.abs(st["u"][1][:, 0, :]).max() == 0.0
     g.close()
+
+
+# ------------------------------------------------------------ moving wall --
+
+WALL_U2 = (0.6, 0.0, 0.0)
+WALL_U3 = (0.5, 0.0, -0.3)
+
+
+@pytest.fixture(scope="module")
+def oracle_moving_2d():
+    w = channel_2d(100)
+    return w, oracle_sim(w, walls_y=True, wall_velocity=WALL_U2).advance(w.steps)
+
+
+@pytest.mark.parametrize("precision", [0, 1, 2])
+def test_moving_wall_2d_parity(oracle_moving_2d, precision):
+    """The membrane in the 2-D channel with the upper wall moving along x:
+    every field against the oracle."""
+    w, o = oracle_moving_2d
+    g = gpu_sim(w, precision, walls_y=True, wall_velocity=WALL_U2)
+    g.step(w.steps)
+    assert g.sync() == w.steps
+    st = g.state()
+    errs = field_errors(st, o, 2)
+    errs["psi"] = psi_vs_p(st["psi"], o.psi, o.p)
+    print("moving wall 2d precision", precision, errs)
+    check(errs, precision, max(w.n))
+    assert np.abs(st["u"][1][:, 0, :]).max() == 0.0
+    g.close()
+
+
+@pytest.fixture(scope="module")
+def oracle_moving_3d():
+    w = channel_3d(20)
+    return w, oracle_sim(w, walls_y=True, wall_velocity=WALL_U3).advance(w.steps)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_moving_wall_3d_parity(oracle_moving_3d, precision):
+    """The shell in the 3-D channel, the upper wall moving along x and z
+    (the plane-marching explicit kernel's wall rows)."""
+    w, o = oracle_moving_3d
+    g = gpu_sim(w, precision, walls_y=True, wall_velocity=WALL_U3)
+    g.step(w.steps)
+    assert g.sync() == w.steps
+    st = g.state()
+    errs = field_errors(st, o, 3)
+    errs["psi"] = psi_vs_p(st["psi"], o.psi, o.p)
+    print("moving wall 3d precision", precision, errs)
+    check(errs, precision, max(w.n))
+    g.close()
+
+
+@pytest.mark.parametrize("dim,precision", [(2, 0), (2, 1), (3, 0)])
+def test_couette_steady_state(dim, precision):
+    """The upper wall moving with U from rest: the discrete steady state is
+    the linear profile u_j = U y_j / L (exact for the scheme: it continues
+    linearly across both walls); v stays zero."""
+    n = (64, 32, 16 if dim == 3 else 1)
+    h = 1.0 / 64
+    U = (0.8, 0.0, -0.5 if dim == 3 else 0.0)
+    X = np.full((dim, 1), 0.5)
+    S = inputs.Structure(X, (np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0), np.zeros(0)),
+                         np.zeros(1))
+    w = inputs.Workload("couette", dim, n, 1.0, 1.0, 1e-3, 2500, S, inputs.zero_velocity(dim, n))
+    sim = gpu_sim(w, precision, walls_y=True, wall_velocity=U)
+    sim.step(w.steps)
+    sim.sync()
+    st = sim.state()
+    y = (np.arange(n[1]) + 0.5) * h
+    L = n[1] * h
+    tol = 1e-11 if precision == 0 else 2e-6
+    for c in (0, 2) if dim == 3 else (0,):
+        want = U[c] * y / L
+        err = np.abs(st["u"][c] - want[None, :, None]).max() / abs(U[c])
+        print("couette", dim, precision, c, err)
+        assert err < tol
+    assert np.abs(st["u"][1]).max() < tol
+    sim.close()
+
+
+def test_wall_velocity_is_checked():
+    """A wall velocity without the walls, or normal to them, is refused."""
+    from paper_1305_3976_amd import ibgm
+    X = np.array([[0.5], [0.5]])
+    S = inputs.Structure(X, (np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0), np.zeros(0)),
+                         np.ones(1))
+    n = (64, 32, 1)
+    for kw in ({"walls_y": False, "wall_velocity": (1.0, 0.0, 0.0)},
+               {"walls_y": True, "wall_velocity": (0.0, 1.0, 0.0)},
+               {"walls_y": True, "wall_velocity": (0.0, 0.0, 1.0)}):
+        cfg = ibgm.Config(2, n, 1.0 / 64, mu=0.05, **kw)
+        with pytest.raises(ibgm.IBError):
+            ibgm.Simulation(cfg, inputs.zero_velocity(2, n), S)
