@@ -143,6 +143,19 @@ ib_status ib_closure_gather(const float *const *src, const float *scales, const 
 ib_status ib_closure_apply(float *const u[3], const int32_t n[3], const float *y, float scale,
                            void *hip_stream);
 
+/* The network's last layer and the correction in one pass: for the periodic
+ * 3x3x3 convolution of x (BF16, 32 channels, [n2][n1][n0][32]) with weights
+ * in the narrow packing (IB_CONV_PACK_NARROW, co = 3) and bias (FP32 [3] or
+ * NULL), u[c][v] = fma(scale, y[v][c], u[c][v]) for c < 3, where y is what
+ * ib_conv3d_fwd(x, 1, n, 32, packed, bias, IB_CONV_PERIODIC,
+ * IB_CONV_OUT_F32 | IB_CONV_NARROW, y, 3, 3) would write -- the same
+ * arithmetic as that call followed by ib_closure_apply, bit for bit, without
+ * the intermediate output.  u: three distinct FP32 arrays of n[0] n[1] n[2]
+ * values, updated in place; scale must be finite. */
+ib_status ib_closure_conv_apply(const uint16_t *x, const int32_t n[3], const void *packed,
+                                const float *bias, float scale, float *const u[3],
+                                void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -145,6 +145,23 @@ class ConvNet:
                                 mode, OUT_F32 | NARROW, _p(B["y"]), COUT, COUT, st))
         return B["y"]
 
+    def correct(self, x, n, u, scale, stream=None):
+        """The periodic forward pass over a whole grid n = (n0, n1, n2) with
+        its output added in place: u[c] += scale * y[..., c] (three FP32
+        component arrays).  Layers 1 and 2 as in forward(); the last layer
+        adds to u as it goes (ib_closure_conv_apply), the same arithmetic as
+        forward() followed by apply_correction()."""
+        B = self._buffers(1, n, PERIODIC)
+        st = _stream(stream)
+        d = _i3(n)
+        check(lib.ib_conv3d_fwd(_p(x), 1, d, 16, _p(self.P[0]), _p(self.b[0]), PERIODIC, RELU,
+                                _p(B["a1"]), 32, 32, st))
+        check(lib.ib_conv3d_fwd(_p(B["a1"]), 1, d, 32, _p(self.P[1]), _p(self.b[1]), PERIODIC,
+                                RELU, _p(B["a2"]), 32, 32, st))
+        U = (_vp * 3)(*[t.data_ptr() for t in u])
+        check(lib.ib_closure_conv_apply(_p(B["a2"]), d, _p(self.P[2]), _p(self.b[2]),
+                                        float(scale), U, st))
+
     def backward(self, x, target, batch, dims, mode, stream=None):
         """Loss (device scalar) and the gradient of every parameter into
         self.grad, after forward() on the same x."""
@@ -278,8 +295,7 @@ class CoarseFine:
         if net is not None:
             nc = self.nc
             x = self.inputs_full(scales)
-            y = net.forward(x, 1, (nc, nc, nc), PERIODIC)
-            apply_correction(self.coarse.u, y, 1.0 / scales.target)
+            net.correct(x, (nc, nc, nc), self.coarse.u, 1.0 / scales.target)
             # the next step's pressure update averages D.u^{n+1} with D.u^n:
             # recompute the latter from the corrected velocity
             self.coarse.refresh_divergence()
@@ -442,8 +458,7 @@ def collect_rollouts(cases, n_fine, net: ConvNet, scales: Scales, pairs: PairSet
                 cf.fine_steps(2)
                 pairs.add(cf, scales, crops, rng)
                 x = cf.inputs_full(scales)
-                y = net.forward(x, 1, (nc, nc, nc), PERIODIC)
-                apply_correction(cf.coarse.u, y, 1.0 / scales.target)
+                net.correct(x, (nc, nc, nc), cf.coarse.u, 1.0 / scales.target)
                 cf.coarse.refresh_divergence()
             if every:
                 cf.fine_steps(every)

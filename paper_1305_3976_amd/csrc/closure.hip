@@ -57,6 +57,9 @@ struct ConvArgs {
   int off, wrap;  // wrap: 0 = zeros outside, 1 = periodic (dims >= TX + 2), 2 = periodic
   int relu, out_f32, co_store, ystride;
   int nt0, nt1, nt2, ntiles;
+  int qoff_ok;      // a halo's extent, HZ D1 D0 voxels, spans < 2^31 bytes
+  float *add[3];    // k_conv_n16<.., true>: add[c][voxel] += add_scale * output c (c < 3)
+  float add_scale;
 };
 
 // Stage the input halo of the tile at (b, ox0, oy0, oz0) in LDS: voxel v of
@@ -134,6 +137,43 @@ __device__ __forceinline__ uint4 halo_load(const ConvArgs &a, int meta, int b, i
   return *reinterpret_cast<const uint4 *>(a.x + vox * CI + ((meta >> 12) & 3) * 8);
 }
 
+// Byte offset of a thread's halo chunk from the halo's first voxel when the
+// halo lies inside the input (no wrap): fixed for the kernel, since it
+// depends only on the chunk and the input's row and plane sizes.
+template <int CI>
+__device__ __forceinline__ uint32_t halo_qoff(int meta, int D0, int D1) {
+  if (meta < 0) return 0u;
+  const int hx = meta & 63, hy = (meta >> 6) & 7, hz = (meta >> 9) & 7, part = (meta >> 12) & 3;
+  return (uint32_t)(((hz * D1 + hy) * D0 + hx) * (CI * 2) + part * 16);
+}
+
+// Fetch a tile's halo chunks into registers, every load issued before any
+// is used.  A tile whose halo lies inside the input reads chunk q at the
+// halo's base address plus qoff[q] (one add per load); the tiles at the
+// input's faces take halo_load's wrap or zero-fill arithmetic.
+template <int CI, int WRAP, int PER>
+__device__ __forceinline__ void fetch_halo(const ConvArgs &a, const int (&meta)[PER],
+                                           const uint32_t (&qoff)[PER], const TileXYZ &t,
+                                           uint4 (&pre)[PER]) {
+  constexpr int NCHUNK = HX * HY * HZ * (CI / 8);
+  const int gx0 = t.ox0 + a.off, gy0 = t.oy0 + a.off, gz0 = t.oz0 + a.off;
+  const bool inside = a.qoff_ok && gx0 >= 0 && gx0 + HX <= a.D0 && gy0 >= 0 &&
+                      gy0 + HY <= a.D1 && gz0 >= 0 && gz0 + HZ <= a.D2;
+  if (inside) {
+    const char *base = reinterpret_cast<const char *>(a.x) +
+                       ((((int64_t)t.b * a.D2 + gz0) * a.D1 + gy0) * a.D0 + gx0) * (CI * 2);
+#pragma unroll
+    for (int q = 0; q < PER; q++) {
+      pre[q] = make_uint4(0, 0, 0, 0);
+      if ((q + 1) * NT <= NCHUNK || meta[q] >= 0)
+        pre[q] = *reinterpret_cast<const uint4 *>(base + qoff[q]);
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < PER; q++) pre[q] = halo_load<CI, WRAP>(a, meta[q], t.b, gx0, gy0, gz0);
+  }
+}
+
 // Output channel held in row r of the transposed 32 x 32 product: rows are
 // permuted so that the 16 accumulators of a lane are 16 consecutive channels
 // (lane l, accumulator j: row 8 (j/4) + 4 (l/32) + j%4, channel 16 (l/32) + j).
@@ -193,14 +233,16 @@ __global__ __launch_bounds__(NT) void k_conv(ConvArgs a) {
     bias[j] = (a.bias && ch < a.co_store) ? a.bias[ch] : 0.f;
   }
   int meta[PER];
+  uint32_t qoff[PER];
 #pragma unroll
-  for (int q = 0; q < PER; q++) meta[q] = halo_meta<CI, VS>(threadIdx.x + q * NT);
+  for (int q = 0; q < PER; q++) {
+    meta[q] = halo_meta<CI, VS>(threadIdx.x + q * NT);
+    qoff[q] = a.qoff_ok ? halo_qoff<CI>(meta[q], a.D0, a.D1) : 0u;
+  }
   for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
     const TileXYZ t = tile_xyz(tile, a.nt0, a.nt1, a.nt2);
     uint4 pre[PER];
-#pragma unroll
-    for (int q = 0; q < PER; q++)
-      pre[q] = halo_load<CI, WRAP>(a, meta[q], t.b, t.ox0 + a.off, t.oy0 + a.off, t.oz0 + a.off);
+    fetch_halo<CI, WRAP, PER>(a, meta, qoff, t, pre);
     __syncthreads();  // the previous tile's reads of sh (and the weight copy) are done
 #pragma unroll
     for (int q = 0; q < PER; q++)
@@ -290,8 +332,10 @@ __global__ __launch_bounds__(NT) void k_conv(ConvArgs a) {
 // 32-wide instruction for a layer with 3 real outputs.  The same transposed
 // product, tiles, halo and row reuse as k_conv: the narrow packing is the A
 // operand as it stands, and lane l ends with channels 4 (l/16) .. + 3 of
-// voxel l%16 of each 16-voxel half of a row.
-template <int WRAP>
+// voxel l%16 of each 16-voxel half of a row.  ADD: instead of storing the
+// three outputs, add add_scale times each to the FP32 field add[c] at the
+// output voxel (the closure's correction of the velocity components).
+template <int WRAP, bool ADD>
 __global__ __launch_bounds__(NT) void k_conv_n16(ConvArgs a) {
   constexpr int CI = 32;
   constexpr int VS = CI * 2 + 16;
@@ -309,14 +353,16 @@ __global__ __launch_bounds__(NT) void k_conv_n16(ConvArgs a) {
     bias[j] = (a.bias && ch < a.co_store) ? a.bias[ch] : 0.f;
   }
   int meta[PER];
+  uint32_t qoff[PER];
 #pragma unroll
-  for (int q = 0; q < PER; q++) meta[q] = halo_meta<CI, VS>(threadIdx.x + q * NT);
+  for (int q = 0; q < PER; q++) {
+    meta[q] = halo_meta<CI, VS>(threadIdx.x + q * NT);
+    qoff[q] = a.qoff_ok ? halo_qoff<CI>(meta[q], a.D0, a.D1) : 0u;
+  }
   for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
     const TileXYZ t = tile_xyz(tile, a.nt0, a.nt1, a.nt2);
     uint4 pre[PER];
-#pragma unroll
-    for (int q = 0; q < PER; q++)
-      pre[q] = halo_load<CI, WRAP>(a, meta[q], t.b, t.ox0 + a.off, t.oy0 + a.off, t.oz0 + a.off);
+    fetch_halo<CI, WRAP, PER>(a, meta, qoff, t, pre);
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < PER; q++)
@@ -354,6 +400,37 @@ __global__ __launch_bounds__(NT) void k_conv_n16(ConvArgs a) {
       }
     }
     const int oz = t.oz0 + wave;
+    if (ADD) {
+      // the lanes holding channels 0..2 (grp 0) add the outputs to the three
+      // fields: every field value of the tile's rows is read before any is
+      // written, so the reads are in flight together
+      if (grp != 0) continue;
+      float old[TY][2][3];
+      int64_t at[TY][2];
+#pragma unroll
+      for (int my = 0; my < TY; my++)
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+          const int oy = t.oy0 + my, ox = t.ox0 + 16 * h + col;
+          const bool ok = oy < a.E1 && oz < a.E2 && ox < a.E0;
+          at[my][h] = ok ? (((int64_t)t.b * a.E2 + oz) * a.E1 + oy) * a.E0 + ox : -1;
+#pragma unroll
+          for (int j = 0; j < 3; j++) old[my][h][j] = ok ? a.add[j][at[my][h]] : 0.f;
+        }
+#pragma unroll
+      for (int my = 0; my < TY; my++)
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+          if (at[my][h] < 0) continue;
+#pragma unroll
+          for (int j = 0; j < 3; j++) {
+            float v = acc[my][h][j] + bias[j];
+            if (a.relu) v = fmaxf(v, 0.f);
+            a.add[j][at[my][h]] = __fmaf_rn(a.add_scale, v, old[my][h][j]);
+          }
+        }
+      continue;
+    }
 #pragma unroll
     for (int my = 0; my < TY; my++) {
       const int oy = t.oy0 + my;
@@ -598,38 +675,49 @@ __global__ void k_restrict(const T *f, int n0, int n1, int n2, int kind, T *c) {
 }
 
 struct GatherArgs {
-  const float *src[IB_GATHER_MAX_SOURCES];
+  const float *src[IB_GATHER_MAX_SOURCES];  // slots past nsrc repeat src[0]
   float scale[IB_GATHER_MAX_SOURCES];
-  int chan[IB_GATHER_MAX_SOURCES];
-  int nsrc, n0, n1, n2;
+  int chan[IB_GATHER_MAX_SOURCES];          // -1 past nsrc
+  int n0, n1, n2;
   const int *origins;
   int B, d0, d1, d2, out_f32, out_ch;
+  int slice_blocks;  // workgroups per brick slice (d0 d1 voxels)
   void *out;
 };
 
 // out[b][voxel][c] = sum over sources s with chan[s] = c of scale[s] src[s][g]
 // at the periodic grid point g of the brick voxel (0 for channels no source
-// names).
-__global__ void k_gather(GatherArgs a) {
-  const int64_t per = (int64_t)a.d0 * a.d1 * a.d2;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= per * a.B) return;
-  const int b = (int)(i / per);
-  const int64_t r = i - b * per;
-  const int x = (int)(r % a.d0), y = (int)((r / a.d0) % a.d1), z = (int)(r / ((int64_t)a.d0 * a.d1));
-  const int gx = wrapi(a.origins[3 * b + 0] + x, a.n0);
-  const int gy = wrapi(a.origins[3 * b + 1] + y, a.n1);
+// names), the sources added in index order.  Workgroup w covers voxels of
+// one brick slice (z, b) = w / slice_blocks, so only the in-slice position
+// is divided per thread (32-bit); every source is loaded before any is used
+// (a fixed number of loads, the spare slots reading source 0 again), so a
+// thread's loads are in flight together.
+__global__ void __launch_bounds__(256) k_gather(GatherArgs a) {
+  const int slice = (int)blockIdx.x / a.slice_blocks;
+  const int r = ((int)blockIdx.x - slice * a.slice_blocks) * 256 + (int)threadIdx.x;
+  if (r >= a.d0 * a.d1) return;
+  const int b = slice / a.d2, z = slice - b * a.d2;
+  const int y = r / a.d0, x = r - y * a.d0;
+  int gx = wrapi(a.origins[3 * b + 0], a.n0) + x;
+  int gy = wrapi(a.origins[3 * b + 1], a.n1) + y;
   const int gz = wrapi(a.origins[3 * b + 2] + z, a.n2);
+  if (gx >= a.n0) gx %= a.n0;
+  if (gy >= a.n1) gy %= a.n1;
   const int64_t g = ((int64_t)gz * a.n1 + gy) * a.n0 + gx;
+  float val[IB_GATHER_MAX_SOURCES];
+#pragma unroll
+  for (int s = 0; s < IB_GATHER_MAX_SOURCES; s++) val[s] = a.src[s][g];
   float v[16];
 #pragma unroll
   for (int c = 0; c < 16; c++) v[c] = 0.f;
-  for (int s = 0; s < a.nsrc; s++) {
-    const float val = a.src[s][g] * a.scale[s];
+#pragma unroll
+  for (int s = 0; s < IB_GATHER_MAX_SOURCES; s++) {
+    const float t = val[s] * a.scale[s];
 #pragma unroll
     for (int c = 0; c < 16; c++)
-      if (c == a.chan[s]) v[c] += val;
+      if (c == a.chan[s]) v[c] += t;
   }
+  const int64_t i = ((int64_t)slice * a.d1 + y) * a.d0 + x;
   if (a.out_f32) {
     float *o = reinterpret_cast<float *>(a.out) + i * a.out_ch;
 #pragma unroll
@@ -647,9 +735,9 @@ __global__ void k_gather(GatherArgs a) {
 __global__ void k_apply(float *u0, float *u1, float *u2, int64_t nvox, const float *y, float s) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nvox) return;
-  u0[i] += s * y[3 * i + 0];
-  u1[i] += s * y[3 * i + 1];
-  u2[i] += s * y[3 * i + 2];
+  u0[i] = __fmaf_rn(s, y[3 * i + 0], u0[i]);
+  u1[i] = __fmaf_rn(s, y[3 * i + 1], u1[i]);
+  u2[i] = __fmaf_rn(s, y[3 * i + 2], u2[i]);
 }
 
 // ------------------------------------------------------------- host ----
@@ -691,14 +779,15 @@ ib_status check_dims(const int32_t *d, int32_t batch, int grow, int64_t *nvox_in
 ib_status launch_conv(const bf16 *x, int32_t batch, const int32_t *in_dims, int32_t ci_pad,
                       const void *packed, const float *bias, int32_t mode, int relu,
                       int out_f32, const bf16 *mask, void *y, int32_t co_store,
-                      int32_t y_stride, hipStream_t st, bool narrow = false) {
+                      int32_t y_stride, hipStream_t st, bool narrow = false,
+                      float *const *add = nullptr, float add_scale = 0.f) {
   int off, wrap, grow;
   ib_status s = mode_off(mode, &off, &wrap, &grow);
   if (s != IB_OK) return s;
   int64_t vi, vo;
   if ((s = check_dims(in_dims, batch, grow, &vi, &vo)) != IB_OK) return s;
   if (ci_pad != 16 && ci_pad != 32) return fail(IB_E_INVALID, "ci_pad must be 16 or 32");
-  if (!x || !packed || !y) return fail(IB_E_INVALID, "null convolution buffer");
+  if (!x || !packed || !(y || add)) return fail(IB_E_INVALID, "null convolution buffer");
   if (co_store < 1 || co_store > CO || y_stride < co_store)
     return fail(IB_E_INVALID, "need 1 <= co_store <= 32 and y_stride >= co_store");
   if ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(packed)) & 15)
@@ -709,10 +798,15 @@ ib_status launch_conv(const bf16 *x, int32_t batch, const int32_t *in_dims, int3
   a.E0 = a.D0 + grow, a.E1 = a.D1 + grow, a.E2 = a.D2 + grow;
   a.off = off, a.wrap = wrap, a.relu = relu, a.out_f32 = out_f32;
   a.co_store = co_store, a.ystride = y_stride;
+  if (add) {
+    for (int c = 0; c < 3; c++) a.add[c] = add[c];
+    a.add_scale = add_scale;
+  }
   a.nt0 = (a.E0 + TX - 1) / TX, a.nt1 = (a.E1 + TY - 1) / TY, a.nt2 = (a.E2 + TZ - 1) / TZ;
   const int64_t nt = (int64_t)a.nt0 * a.nt1 * a.nt2 * batch;
   if (nt >= INT32_MAX) return fail(IB_E_INVALID, "too many tiles");
   a.ntiles = (int)nt;
+  a.qoff_ok = (int64_t)HZ * a.D1 * a.D0 * (ci_pad * 2) < ((int64_t)1 << 31);
   const int grid = (int)(nt < WG_CONV ? nt : WG_CONV);
   if (wrap && (a.D0 < HX || a.D1 < HY || a.D2 < HZ)) a.wrap = 2;
   // 16-byte output stores: 32 BF16 channels per voxel at a stride that keeps
@@ -722,7 +816,8 @@ ib_status launch_conv(const bf16 *x, int32_t batch, const int32_t *in_dims, int3
                    !(reinterpret_cast<uintptr_t>(mask) & 15);
   auto go = [&](auto wrap_tag) {
     constexpr int W = decltype(wrap_tag)::value;
-    if (narrow) k_conv_n16<W><<<grid, NT, 0, st>>>(a);
+    if (add) k_conv_n16<W, true><<<grid, NT, 0, st>>>(a);
+    else if (narrow) k_conv_n16<W, false><<<grid, NT, 0, st>>>(a);
     else if (ci_pad == 16) {
       if (vec) k_conv<16, W, true><<<grid, NT, 0, st>>>(a);
       else k_conv<16, W, false><<<grid, NT, 0, st>>>(a);
@@ -890,14 +985,17 @@ extern "C" ib_status ib_closure_gather(const float *const *src, const float *sca
     if (chan[s] < 0 || chan[s] >= out_ch) return fail(IB_E_INVALID, "chan[%d] out of range", s);
     a.src[s] = src[s], a.scale[s] = scales[s], a.chan[s] = chan[s];
   }
+  for (int s = nsrc; s < IB_GATHER_MAX_SOURCES; s++) a.src[s] = src[0], a.scale[s] = 0.f, a.chan[s] = -1;
   for (int i = 0; i < 3; i++)
     if (n[i] < 1 || dims[i] < 1 || n[i] > 4096 || dims[i] > 4096) return fail(IB_E_INVALID, "bad n / dims");
   if (!out_f32 && (reinterpret_cast<uintptr_t>(out) & 15)) return fail(IB_E_INVALID, "out must be 16-byte aligned");
-  a.nsrc = nsrc, a.n0 = n[0], a.n1 = n[1], a.n2 = n[2], a.origins = origins;
+  a.n0 = n[0], a.n1 = n[1], a.n2 = n[2], a.origins = origins;
   a.B = batch, a.d0 = dims[0], a.d1 = dims[1], a.d2 = dims[2], a.out_f32 = out_f32 ? 1 : 0;
   a.out_ch = out_ch, a.out = out;
-  const int64_t tot = (int64_t)dims[0] * dims[1] * dims[2] * batch;
-  k_gather<<<(unsigned)((tot + 255) / 256), 256, 0, (hipStream_t)hip_stream>>>(a);
+  a.slice_blocks = (dims[0] * dims[1] + 255) / 256;
+  const int64_t blocks = (int64_t)a.slice_blocks * dims[2] * batch;
+  if (blocks > INT32_MAX) return fail(IB_E_INVALID, "gather batch too large");
+  k_gather<<<(unsigned)blocks, 256, 0, (hipStream_t)hip_stream>>>(a);
   HIP_CHECK_LAUNCH("gather");
   return IB_OK;
 }
@@ -911,4 +1009,16 @@ extern "C" ib_status ib_closure_apply(float *const u[3], const int32_t n[3], con
   k_apply<<<(unsigned)((nv + 255) / 256), 256, 0, (hipStream_t)hip_stream>>>(u[0], u[1], u[2], nv, y, scale);
   HIP_CHECK_LAUNCH("apply");
   return IB_OK;
+}
+
+extern "C" ib_status ib_closure_conv_apply(const uint16_t *x, const int32_t n[3],
+                                           const void *packed, const float *bias, float scale,
+                                           float *const u[3], void *hip_stream) {
+  if (!u || !u[0] || !u[1] || !u[2]) return fail(IB_E_INVALID, "null velocity component");
+  if (u[0] == u[1] || u[0] == u[2] || u[1] == u[2])
+    return fail(IB_E_INVALID, "the three velocity components must be distinct arrays");
+  if (!std::isfinite(scale)) return fail(IB_E_INVALID, "scale is not finite");
+  return launch_conv(reinterpret_cast<const bf16 *>(x), 1, n, 32, packed, bias,
+                     IB_CONV_PERIODIC, 0, 1, nullptr, nullptr, 3, 3, (hipStream_t)hip_stream,
+                     true, u, scale);
 }

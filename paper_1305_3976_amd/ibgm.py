@@ -110,6 +110,7 @@ def _load():
     L.ib_closure_gather.argtypes = [ctypes.POINTER(_vp), ctypes.POINTER(f32), _ip, i32, _ip, _vp,
                                     i32, _ip, i32, i32, _vp, _vp]
     L.ib_closure_apply.argtypes = [ctypes.POINTER(_vp), _ip, _vp, f32, _vp]
+    L.ib_closure_conv_apply.argtypes = [_vp, _ip, _vp, _vp, f32, ctypes.POINTER(_vp), _vp]
     # streaming-rate probe (include/ibgm_probe.h)
     L.ib_probe_stream_rate.argtypes = [ctypes.POINTER(_vp), i32, ctypes.POINTER(_vp), i32, i64,
                                        i32, _vp, ctypes.POINTER(ctypes.c_double)]
@@ -125,7 +126,7 @@ def _load():
 
 CLOSURE_EXPORTED = ("ib_conv3d_pack", "ib_conv3d_fwd", "ib_conv3d_bwd_data",
                     "ib_conv3d_bwd_weight", "ib_mse_grad", "ib_adam_step", "ib_restrict",
-                    "ib_closure_gather", "ib_closure_apply")
+                    "ib_closure_gather", "ib_closure_apply", "ib_closure_conv_apply")
 
 
 lib = _load()

@@ -115,3 +115,40 @@ def test_static_array_size_matches_header():
     m = re.search(r"#define IB_SPREAD_STATIC_MAX_BYTES \((\d+)u << (\d+)\)", hdr)
     assert m
     assert ibgm.IB_SPREAD_STATIC_MAX_BYTES == int(m.group(1)) << int(m.group(2))
+
+
+def test_closure_argument_errors(ib):
+    """The gather and the fused last layer refuse bad arguments on the host
+    (the fake device pointers below are never dereferenced)."""
+    L = ib.lib
+    fake = ctypes.c_void_p(4096)
+    n = (ctypes.c_int32 * 3)(16, 16, 16)
+    U = (ib._vp * 3)(4096, 8192, 12288)
+    assert L.ib_closure_conv_apply(fake, n, fake, None, 0.5, None, None) == ib.IB_E_INVALID
+    same = (ib._vp * 3)(4096, 4096, 12288)
+    assert L.ib_closure_conv_apply(fake, n, fake, None, 0.5, same, None) == ib.IB_E_INVALID
+    assert b"distinct" in L.ib_last_error()
+    assert L.ib_closure_conv_apply(fake, n, fake, None, float("inf"), U, None) == ib.IB_E_INVALID
+    assert L.ib_closure_conv_apply(None, n, fake, None, 0.5, U, None) == ib.IB_E_INVALID
+    bad_n = (ctypes.c_int32 * 3)(16, 0, 16)
+    assert L.ib_closure_conv_apply(fake, bad_n, fake, None, 0.5, U, None) == ib.IB_E_INVALID
+    odd = ctypes.c_void_p(4100)
+    assert L.ib_closure_conv_apply(odd, n, fake, None, 0.5, U, None) == ib.IB_E_INVALID
+    # gather
+    S = (ib._vp * 13)(*([4096] * 13))
+    F = (ctypes.c_float * 13)(*([1.0] * 13))
+    C = (ctypes.c_int32 * 13)(*([0] * 13))
+    d = (ctypes.c_int32 * 3)(8, 8, 8)
+    for nsrc, out_f32, out_ch in [(0, 1, 4), (13, 1, 4), (2, 0, 8), (2, 1, 17)]:
+        assert L.ib_closure_gather(S, F, C, nsrc, n, fake, 1, d, out_f32, out_ch, fake,
+                                   None) == ib.IB_E_INVALID
+    C[1] = 4
+    assert L.ib_closure_gather(S, F, C, 2, n, fake, 1, d, 1, 4, fake, None) == ib.IB_E_INVALID
+    assert b"chan[1]" in L.ib_last_error()
+    C[1] = 0
+    S[1] = None
+    assert L.ib_closure_gather(S, F, C, 2, n, fake, 1, d, 1, 4, fake, None) == ib.IB_E_INVALID
+    S[1] = 4096
+    assert L.ib_closure_gather(S, F, C, 2, n, fake, 0, d, 1, 4, fake, None) == ib.IB_E_INVALID
+    assert L.ib_closure_gather(S, F, C, 2, bad_n, fake, 1, d, 1, 4, fake, None) == ib.IB_E_INVALID
+    assert L.ib_closure_gather(S, F, C, 2, n, fake, 1, d, 0, 16, odd, None) == ib.IB_E_INVALID

@@ -199,6 +199,72 @@ def test_restrict_and_gather(dtype):
                     assert abs(got[b, k, j, i, 1] - 0.5 * S[2][z, y, x]) <= 1e-6
 
 
+@pytest.mark.parametrize("n,dims,batch,org", [
+    ((24, 20, 6), (24, 20, 6), 1, [[0, 0, 0]]),                    # a whole grid, 2 slice blocks
+    ((12, 8, 10), (30, 20, 3), 2, [[-13, 5, 9], [7, -1, -25]]),    # bricks wider than the grid
+])
+def test_gather_network_input(n, dims, batch, org):
+    """The closure's input gather with the full set of 12 sources (three read
+    twice, one channel summing two sources) in FP32 and BF16 output, against
+    the definition summed in FP64 at every voxel: ragged slice blocks,
+    negative origins and bricks that wrap the grid more than once."""
+    rng = np.random.default_rng(53)
+    fields = [rng.standard_normal((n[2], n[1], n[0])).astype(np.float32) for _ in range(9)]
+    srcs = [torch.as_tensor(f).to(DEV) for f in fields]
+    src_ix = [0, 1, 2, 3, 4, 5, 0, 1, 2, 6, 7, 8]
+    scales = [1.5, 1.5, 1.5, 0.25, 0.25, 0.25, 4.0, 4.0, 4.0, -4.0, -4.0, -4.0]
+    chans = [0, 1, 2, 3, 4, 5, 6, 7, 8, 6, 7, 8]
+    orgd = torch.as_tensor(np.array(org, dtype=np.int32)).to(DEV)
+    nv = batch * dims[0] * dims[1] * dims[2]
+    ref = np.zeros((batch, dims[2], dims[1], dims[0], 16))
+    for b in range(batch):
+        z = (org[b][2] + np.arange(dims[2])) % n[2]
+        y = (org[b][1] + np.arange(dims[1])) % n[1]
+        x = (org[b][0] + np.arange(dims[0])) % n[0]
+        for s, c, f in zip(src_ix, chans, scales):
+            ref[b, ..., c] += f * fields[s].astype(np.float64)[np.ix_(z, y, x)]
+    out = torch.empty(nv * 16, dtype=torch.float32, device=DEV)
+    cl.gather([srcs[i] for i in src_ix], scales, chans, n, orgd, dims, True, 16, out)
+    got = out.double().cpu().numpy().reshape(ref.shape)
+    assert np.abs(got - ref).max() <= 1e-6 * np.abs(ref).max()
+    outb = torch.empty(nv * 16, dtype=torch.bfloat16, device=DEV)
+    cl.gather([srcs[i] for i in src_ix], scales, chans, n, orgd, dims, False, 16, outb)
+    gotb = outb.double().cpu().numpy().reshape(ref.shape)
+    # one BF16 rounding of the FP32 sum
+    assert np.all(np.abs(gotb - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-6 * np.abs(ref).max())
+    assert np.all(gotb[..., 9:] == 0)
+
+
+@pytest.mark.parametrize("n", [(40, 12, 8), (20, 5, 4), (33, 7, 6)])
+def test_conv_apply_matches_forward_then_apply(n):
+    """The fused last layer + correction (ib_closure_conv_apply) leaves the
+    velocity components bit for bit where the 16-wide forward convolution
+    followed by ib_closure_apply leaves them, on grids that take either
+    periodic wrap path and ragged tiles."""
+    rng = np.random.default_rng(57)
+    W = (rng.standard_normal((27, 32, 3)) * 0.05).astype(np.float32)
+    P, _ = pack(W, 32, 3, 32, cl.PACK_NARROW)
+    bias = torch.as_tensor(rng.standard_normal(3).astype(np.float32) * 0.1).to(DEV)
+    nv = n[0] * n[1] * n[2]
+    x, _ = bf16_pair((nv * 32,), rng)
+    u0 = [torch.as_tensor(rng.standard_normal((n[2], n[1], n[0])).astype(np.float32)).to(DEV)
+          for _ in range(3)]
+    y = torch.empty(nv * 3, dtype=torch.float32, device=DEV)
+    ibgm.check(ibgm.lib.ib_conv3d_fwd(cl._p(x), 1, cl._i3(n), 32, cl._p(P), cl._p(bias),
+                                      cl.PERIODIC, cl.OUT_F32 | cl.NARROW, cl._p(y), 3, 3,
+                                      cl._stream()))
+    ref = [u.clone() for u in u0]
+    cl.apply_correction(ref, y, 0.37)
+    got = [u.clone() for u in u0]
+    U = (ibgm._vp * 3)(*[t.data_ptr() for t in got])
+    ibgm.check(ibgm.lib.ib_closure_conv_apply(cl._p(x), cl._i3(n), cl._p(P), cl._p(bias), 0.37,
+                                              U, cl._stream()))
+    torch.cuda.synchronize()
+    for g, r, u in zip(got, ref, u0):
+        assert torch.equal(g, r)
+        assert not torch.equal(g, u)
+
+
 @pytest.mark.parametrize("mode", ["periodic", "valid"])
 def test_network_gradient_matches_oracle(mode):
     rng = np.random.default_rng(61)
