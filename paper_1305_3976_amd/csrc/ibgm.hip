@@ -567,18 +567,25 @@ static void launch_spread(ib_ctx *c, const double *X, const double *F, const dou
     hipLaunchKernelGGL((k_bin<DIM>), dim3(pb), dim3(256), 0, c->stream, X, c->p_layer, np,
                        c->g, c->tg, inv_h, c->t_count, c->tile_of, c->rank_of);
   });
-  launch(c, KP_SORT, [&] {
-    hipLaunchKernelGGL(k_scan_sums, dim3(nb), dim3(256), 0, c->stream, c->t_count, c->t_bsum,
-                       c->tg.ntiles);
-  });
-  launch(c, KP_SORT, [&] {
-    hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(256), 0, c->stream, c->t_bsum, (int)nb,
-                       c->t_nlist);
-  });
-  launch(c, KP_SORT, [&] {
-    hipLaunchKernelGGL(k_scan_write, dim3(nb), dim3(256), 0, c->stream, c->t_count,
-                       c->t_start, c->t_bsum, c->tg.ntiles);
-  });
+  if (c->tg.ntiles <= SCAN_ONE_MAX) {
+    launch(c, KP_SORT, [&] {
+      hipLaunchKernelGGL(k_scan_one, dim3(1), dim3(SCAN_ONE_THREADS), 0, c->stream, c->t_count,
+                         c->t_start, c->tg.ntiles, c->t_nlist);
+    });
+  } else {
+    launch(c, KP_SORT, [&] {
+      hipLaunchKernelGGL(k_scan_sums, dim3(nb), dim3(256), 0, c->stream, c->t_count, c->t_bsum,
+                         c->tg.ntiles);
+    });
+    launch(c, KP_SORT, [&] {
+      hipLaunchKernelGGL(k_scan_bsums, dim3(1), dim3(256), 0, c->stream, c->t_bsum, (int)nb,
+                         c->t_nlist);
+    });
+    launch(c, KP_SORT, [&] {
+      hipLaunchKernelGGL(k_scan_write, dim3(nb), dim3(256), 0, c->stream, c->t_count,
+                         c->t_start, c->t_bsum, c->tg.ntiles);
+    });
+  }
   Sorted<T> stn{c->st_x, (T *)c->st_val};
   const double inv_hd = 1.0 / std::pow(c->prm.h, DIM);
   const unsigned tb = (unsigned)((c->tg.ntiles + 255) / 256);

@@ -436,6 +436,76 @@ __global__ void __launch_bounds__(256) k_scan_write(int *count, int *start, cons
   if (b < ntiles && b + 4 >= ntiles) start[ntiles] = run;
 }
 
+// The same scan in one launch of one workgroup (1024 threads) when there are
+// at most SCAN_ONE_MAX tiles (all the grids of the step's workloads): chunks
+// of 4096 counts (one 16-byte load per thread, eight chunks' loads in flight
+// at a time) are scanned one after another across the workgroup -- a lane
+// scan, the wave totals through LDS -- on top of the running total of the
+// chunks before.  Also clears the touched-tile count (as k_scan_bsums does).
+constexpr int SCAN_ONE_THREADS = 1024;
+constexpr int64_t SCAN_ONE_MAX = 65536;
+
+__global__ void __launch_bounds__(1024) k_scan_one(int *count, int *start, int64_t ntiles,
+                                                   int *nlist) {
+  __shared__ int wsum[SCAN_ONE_THREADS / 64];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nchunk = (int)((ntiles + 4095) / 4096);
+  if (tid == 0) *nlist = 0;
+  int total = 0;  // counts of the chunks before (the same in every thread)
+  for (int k0 = 0; k0 < nchunk; k0 += 8) {
+    int4 v[8];
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+      const int64_t i = ((int64_t)(k0 + k) * SCAN_ONE_THREADS + tid) * 4;
+      if (i + 3 < ntiles) {
+        v[k] = *reinterpret_cast<const int4 *>(count + i);
+      } else {
+        v[k].x = i < ntiles ? count[i] : 0;
+        v[k].y = i + 1 < ntiles ? count[i + 1] : 0;
+        v[k].z = i + 2 < ntiles ? count[i + 2] : 0;
+        v[k].w = 0;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 8; k++) {
+      if (k0 + k >= nchunk) break;  // uniform
+      const int s4 = v[k].x + v[k].y + v[k].z + v[k].w;
+      int incl = s4;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const int t = __shfl_up(incl, off);
+        if (lane >= off) incl += t;
+      }
+      if (lane == 63) wsum[wv] = incl;
+      __syncthreads();
+      int before = 0, chunk = 0;
+#pragma unroll
+      for (int w = 0; w < SCAN_ONE_THREADS / 64; w++) {
+        const int t = wsum[w];
+        before += w < wv ? t : 0;
+        chunk += t;
+      }
+      __syncthreads();  // wsum is rewritten by the next chunk
+      const int64_t i = ((int64_t)(k0 + k) * SCAN_ONE_THREADS + tid) * 4;
+      int4 st;
+      st.x = total + before + incl - s4;
+      st.y = st.x + v[k].x;
+      st.z = st.y + v[k].y;
+      st.w = st.z + v[k].z;
+      if (i + 3 < ntiles) {
+        *reinterpret_cast<int4 *>(start + i) = st;
+        *reinterpret_cast<int4 *>(count + i) = make_int4(0, 0, 0, 0);
+      } else {
+        if (i < ntiles) start[i] = st.x, count[i] = 0;
+        if (i + 1 < ntiles) start[i + 1] = st.y, count[i + 1] = 0;
+        if (i + 2 < ntiles) start[i + 2] = st.z, count[i + 2] = 0;
+      }
+      total += chunk;
+    }
+  }
+  if (tid == 0) start[ntiles] = total;
+}
+
 // Place every point at its sorted slot: its position (FP64) and, per
 // component, the spread value F_c w / h^d.  The spreading kernels compute
 // each stencil from the position where they use it (three square roots per

@@ -109,6 +109,21 @@ def test_split_classes_match_oracle(small_oracle, precision, tol):
     ens.close()
 
 
+def test_many_tiles_take_the_multi_pass_scan():
+    """70 members of 256^2 in one context hold 32 x 32 x 70 = 71,680
+    spreading tiles, more than the one-workgroup scan of the tile counts
+    takes (65,536): the scan then runs in three passes.  The first and the
+    last member against the oracle after 11 steps (FP64)."""
+    members, shared = inputs.config_ensemble(nsims=70, seed=21, sizes=(256,), steps=11)
+    ens = ensemble.Ensemble(members, rho=shared["rho"], mu=shared["mu"], precision=0)
+    assert len(ens.sims) == 1
+    ens.run(11, steps_per_launch=10, branches=False)
+    assert ens.sync() == [11]
+    for m in (members[0], members[-1]):
+        check_fp64(m, member_errors(ens, m, oracle_member(m, shared, 11)))
+    ens.close()
+
+
 def all_states(ens):
     return [s.state() for s in ens.sims]
 
