@@ -106,15 +106,19 @@ __device__ __forceinline__ TileXYZ tile_xyz(int tile, int nt0, int nt1, int nt2)
 // Halo chunk metadata of one thread, fixed for the kernel's life: chunk c of
 // a tile's input halo (16 bytes of one voxel's channels) lies at halo voxel
 // (hx, hy, hz), 16-byte part `part` of the voxel, and goes to LDS byte
-// v VS + 16 part.  Packed as hx | hy << 6 | hz << 9 | part << 12 | (LDS
-// byte / 16) << 14 (27 bits); -1 for chunk numbers past the halo.
-template <int CI, int VS>
+// v VS + 16 part (SWZ, two parts per voxel: the parts of voxels with bit 2
+// of v set trade places, so that lanes reading the same part of voxels v and
+// v + 4 meet different LDS banks).  Packed as hx | hy << 6 | hz << 9 |
+// part << 12 | (LDS byte / 16) << 14 (27 bits); -1 for chunk numbers past
+// the halo.
+template <int CI, int VS, bool SWZ = false>
 __device__ __forceinline__ int halo_meta(int c) {
   constexpr int CH = CI / 8;
   if (c >= HX * HY * HZ * CH) return -1;
   const int v = c / CH, part = c - v * CH;
   const int hx = v % HX, hy = (v / HX) % HY, hz = v / (HX * HY);
-  return hx | hy << 6 | hz << 9 | part << 12 | ((v * VS + part * 16) >> 4) << 14;
+  const int slot = SWZ ? part ^ ((v >> 2) & 1) : part;
+  return hx | hy << 6 | hz << 9 | part << 12 | ((v * VS + slot * 16) >> 4) << 14;
 }
 
 // Load one halo chunk of the tile whose halo starts at input voxel (gx0, gy0,
@@ -214,11 +218,16 @@ __device__ __forceinline__ void copy_weights(unsigned char *sw, const bf16 *wp) 
 // walks the 6 halo rows once: a halo row hy feeds output rows hy - ty, so
 // each B fragment read from LDS serves up to three matrix-core products.  A
 // tile's halo is fetched with all of a thread's loads in flight before any is
-// stored to LDS, from per-thread chunk coordinates computed once.
+// stored to LDS, from per-thread chunk coordinates computed once.  With 16
+// input channels the halo is stored unpadded (32-byte voxels, the two halves
+// swizzled against bank conflicts) so that weights and halo fit twice in one
+// CU's LDS: two workgroups per CU, one's halo fetch beside the other's
+// products.
 template <int CI, int WRAP, bool VEC>
-__global__ __launch_bounds__(NT) void k_conv(ConvArgs a) {
+__global__ __launch_bounds__(NT, CI == 16 ? 2 : 1) void k_conv(ConvArgs a) {
   constexpr int KS = CI / 16;
-  constexpr int VS = CI * 2 + 16;  // padded voxel stride in LDS (bytes)
+  constexpr bool SWZ = CI == 16;
+  constexpr int VS = SWZ ? CI * 2 : CI * 2 + 16;  // voxel stride in LDS (bytes)
   constexpr int NCHUNK = HX * HY * HZ * (CI / 8);
   constexpr int PER = (NCHUNK + NT - 1) / NT;
   __shared__ __align__(16) unsigned char sw[27 * KS * 64 * 16];
@@ -236,7 +245,7 @@ __global__ __launch_bounds__(NT) void k_conv(ConvArgs a) {
   uint32_t qoff[PER];
 #pragma unroll
   for (int q = 0; q < PER; q++) {
-    meta[q] = halo_meta<CI, VS>(threadIdx.x + q * NT);
+    meta[q] = halo_meta<CI, VS, SWZ>(threadIdx.x + q * NT);
     qoff[q] = a.qoff_ok ? halo_qoff<CI>(meta[q], a.D0, a.D1) : 0u;
   }
   for (int tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
@@ -264,12 +273,19 @@ __global__ __launch_bounds__(NT) void k_conv(ConvArgs a) {
           for (int ks = 0; ks < KS; ks++)
             wa[ty][ks] = *reinterpret_cast<const bf16x8 *>(
                 sw + (((9 * tz + 3 * ty + tx) * KS + ks) * 64 + lane) * 16);
-        const unsigned char *base = sh + ((wave + tz) * HY * HX + col + tx) * VS + grp * 16;
+        const int vrow = (wave + tz) * HY * HX + col + tx;
+        const unsigned char *base = sh + vrow * VS + grp * 16;
 #pragma unroll
         for (int hy = 0; hy < HY; hy++) {
 #pragma unroll
           for (int ks = 0; ks < KS; ks++) {
-            const bf16x8 xb = *reinterpret_cast<const bf16x8 *>(base + hy * HX * VS + ks * 32);
+            bf16x8 xb;
+            if constexpr (SWZ) {
+              const int vb = vrow + hy * HX;
+              xb = *reinterpret_cast<const bf16x8 *>(sh + vb * VS + ((grp ^ ((vb >> 2) & 1)) << 4));
+            } else {
+              xb = *reinterpret_cast<const bf16x8 *>(base + hy * HX * VS + ks * 32);
+            }
 #pragma unroll
             for (int ty = 0; ty < 3; ty++) {
               const int my = hy - ty;
@@ -807,7 +823,9 @@ ib_status launch_conv(const bf16 *x, int32_t batch, const int32_t *in_dims, int3
   if (nt >= INT32_MAX) return fail(IB_E_INVALID, "too many tiles");
   a.ntiles = (int)nt;
   a.qoff_ok = (int64_t)HZ * a.D1 * a.D0 * (ci_pad * 2) < ((int64_t)1 << 31);
-  const int grid = (int)(nt < WG_CONV ? nt : WG_CONV);
+  // two resident workgroups per CU for the 16-channel kernel (its LDS fits twice)
+  const int64_t wg = (!narrow && ci_pad == 16) ? 2 * WG_CONV : WG_CONV;
+  const int grid = (int)(nt < wg ? nt : wg);
   if (wrap && (a.D0 < HX || a.D1 < HY || a.D2 < HZ)) a.wrap = 2;
   // 16-byte output stores: 32 BF16 channels per voxel at a stride that keeps
   // every voxel's record 16-byte aligned (and the mask, when given)
