@@ -59,6 +59,9 @@ def parse():
     ap.add_argument("--closure", choices=("full", "small", "off"), default="full",
                     help="learned closure: 128^3 coarse vs 256^3 fine (full), 32^3 vs 64^3 "
                          "(small) or skip")
+    ap.add_argument("--closure-oracle-interval", type=int, default=4, metavar="K",
+                    help="compare the closure rollout after interval K with the FP64 oracle's "
+                         "own fine run (0: skip)")
     ap.add_argument("--cylinder", type=int, nargs="*", default=[256, 128], metavar="N",
                     help="grid sizes of the 3-D cylinder row (100 steps each, mixed and "
                          "FP64); none to skip")
@@ -379,6 +382,36 @@ def achievable_rates() -> dict:
     return {k: round(v, 1) for k, v in out.items()}
 
 
+def closure_vs_oracle(keep):
+    """The closure row's error against the FP64 oracle: the oracle's own run of
+    the held-out case on the fine grid (the rollout's restart step plus two
+    fine steps per interval), restricted to the coarse grid, against the
+    corrected and the plain coarse velocities after interval k of the
+    rollout, and against the restricted GPU fine run that the rollout uses as
+    its reference (mixed policy)."""
+    import oracle
+    from oracle import closure as oc
+    case, nf, warm, snap = keep["case"], keep["n_fine"], keep["warmup"], keep["snap"]
+    k = snap["interval"]
+    P = oracle.make_params(3, (nf, nf, nf), 1.0 / nf, rho=1.0, mu=0.01, dt=case.dt_fine)
+    S = case.structure
+    t0 = time.time()
+    sim = oracle.Sim(P, [np.asarray(c, dtype=np.float64) for c in case.u0], S.X, S.links, S.w)
+    sim.advance(warm + 2 * k)
+    el = time.time() - t0
+    ref = [oc.restrict_face(sim.u[c], c) for c in range(3)]
+    nr = math.sqrt(sum(float(np.sum(r ** 2)) for r in ref))
+    rel = lambda us: math.sqrt(sum(float(np.sum((u - r) ** 2)) for u, r in zip(us, ref))) / nr
+    return {"interval": k, "oracle_fine_steps": warm + 2 * k, "oracle_s": round(el, 1),
+            "oracle_threads": oracle.num_threads(),
+            "rel_l2_vs_restricted_oracle": {
+                "coarse_plus_closure": round(rel(snap["corrected"]), 6),
+                "plain_coarse": round(rel(snap["plain"]), 6),
+                "gpu_fine_restricted": float("%.3g" % rel(snap["fine"]))},
+            "note": "velocity after interval k against the FP64 oracle's fine run restricted "
+                    "to the coarse grid (relative discrete l2 over the three components)"}
+
+
 def oracle_sample(w, budget_s):
     import oracle
     P = oracle.make_params(w.dim, w.n, w.h, rho=w.rho, mu=w.mu, dt=w.dt, chi=w.chi)
@@ -608,8 +641,19 @@ def main():
         cargs = [] if args.closure == "full" else [
             "--n-fine", "64", "--traj", "20", "--held", "4", "--snapshots", "12",
             "--iters", "1200", "--crop", "26", "--rollout", "10"]
-        line["closure"] = closure_run.main(cargs)
+        keep = {"interval": args.closure_oracle_interval} if args.closure_oracle_interval else None
+        line["closure"] = closure_run.main(cargs, keep=keep)
         torch.cuda.empty_cache()
+        if keep is not None and keep.get("snap", {}).get("fine") is not None:
+            line["closure"]["error_vs_fp64_oracle"] = chk = closure_vs_oracle(keep)
+            print("# closure vs FP64 oracle after interval %d (oracle %.1f s): corrected %.3e, "
+                  "plain %.3e, GPU fine %.2e" % (
+                      chk["interval"], chk["oracle_s"],
+                      chk["rel_l2_vs_restricted_oracle"]["coarse_plus_closure"],
+                      chk["rel_l2_vs_restricted_oracle"]["plain_coarse"],
+                      chk["rel_l2_vs_restricted_oracle"]["gpu_fine_restricted"]),
+                  file=sys.stderr, flush=True)
+            del keep
     if not args.no_cpu_baseline:
         ref, n, el, thr = oracle_sample(w, args.cpu_seconds)
         line["cpu_baseline"] = {"value": round(n / el, 5), "unit": "IB steps/s", "cores": thr,

@@ -288,8 +288,9 @@ class CoarseFine:
 
     def coarse_step(self, net: ConvNet = None, scales: Scales = None):
         """One coarse step (2 dt), optionally followed by the learned correction."""
-        for k in range(3):
-            self.ub[k].copy_(self.coarse.u[k])
+        # the velocity before the step, for the input's increment channels (one
+        # multi-tensor copy launch for the three components)
+        torch._foreach_copy_(self.ub, list(self.coarse.u))
         self.coarse.step(1)
         self.spread_force()
         if net is not None:
@@ -504,11 +505,15 @@ def evaluate(net: ConvNet, pairs: PairSet, first: int, count: int, batch: int = 
 
 # -------------------------------------------------------------- rollout --
 
-def rollout(case, n_fine: int, steps: int, net: ConvNet, scales: Scales, warmup: int = 6):
+def rollout(case, n_fine: int, steps: int, net: ConvNet, scales: Scales, warmup: int = 6,
+            snap: dict = None):
     """Coarse runs with and without the correction, both restarted from the
     restricted fine state after `warmup` fine steps, against the restricted
     fine run: relative l2 velocity error after each coarse step, and the mean
-    time per coarse step of each (HIP events on the current stream)."""
+    time per coarse step of each (HIP events on the current stream).  With
+    `snap` = {"interval": k}, the three velocities after interval k (FP64
+    host arrays: restricted fine, plain coarse, corrected coarse) are stored
+    in it under "fine", "plain" and "corrected"."""
     cf = CoarseFine(case, n_fine)
     plain = CoarseFine.__new__(CoarseFine)
     plain.__dict__.update(cf.__dict__)
@@ -538,6 +543,8 @@ def rollout(case, n_fine: int, steps: int, net: ConvNet, scales: Scales, warmup:
         t_corr += ev[1].elapsed_time(ev[2])
         h = lambda ts: [t.double().cpu().numpy() for t in ts]
         r, a, b = h(Ru), h(plain.coarse.u), h(cf.coarse.u)
+        if snap is not None and len(errs) + 1 == snap.get("interval"):
+            snap.update(fine=r, plain=a, corrected=b)
         nr = math.sqrt(sum(float(np.sum(x ** 2)) for x in r))
         ea = math.sqrt(sum(float(np.sum((x - y) ** 2)) for x, y in zip(a, r))) / nr
         eb = math.sqrt(sum(float(np.sum((x - y) ** 2)) for x, y in zip(b, r))) / nr

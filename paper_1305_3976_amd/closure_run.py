@@ -65,7 +65,12 @@ def conv_rates(net: cl.ConvNet, nc: int, reps: int = 10):
     return out
 
 
-def main(argv=None):
+def main(argv=None, keep: dict = None):
+    """The closure experiment; returns the bench line's closure row.  With
+    `keep` = {"interval": k}, also leaves in it what a check of the row against
+    an independent fine solve needs: the held-out case ("case"), the fine grid
+    ("n_fine"), the restart step ("warmup") and the velocities after interval
+    k of the main rollout ("snap": see closure.rollout)."""
     ap = argparse.ArgumentParser()
     ap.add_argument("--n-fine", type=int, default=256)
     ap.add_argument("--traj", type=int, default=11, help="trajectories (the last ~10%% held out)")
@@ -138,7 +143,11 @@ def main(argv=None):
                "iters": a.dagger_iters,
                "loss_first_last": [float(losses2[:50].mean()), float(losses2[-50:].mean())]}
         del tr2
-    errs, t_plain, t_corr = cl.rollout(cases[-1], a.n_fine, a.rollout, net, scales, a.warmup)
+    snap = {"interval": keep.get("interval", 4)} if keep is not None else None
+    errs, t_plain, t_corr = cl.rollout(cases[-1], a.n_fine, a.rollout, net, scales, a.warmup,
+                                       snap=snap)
+    if keep is not None:
+        keep.update(case=cases[-1], n_fine=a.n_fine, warmup=a.warmup, snap=snap)
     log("rollout: plain %.3e -> %.3e, corrected %.3e -> %.3e" % (errs[0][0], errs[-1][0], errs[0][1], errs[-1][1]))
     errs_late, _, _ = cl.rollout(cases[-1], a.n_fine, a.rollout, net, scales, a.late_start)
     gerrs, fired = cl.guarded_rollout(cases[-1], a.n_fine, a.rollout, net, scales,
