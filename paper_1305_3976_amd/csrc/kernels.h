@@ -741,7 +741,17 @@ __global__ void __launch_bounds__(NT) k_spread_tiles(SpreadArgs<T, DIM> a) {
     // components (3-D: 754 -> 614 us for the 933,888-point cylinder, 73 ->
     // 66 us for the 65,536-point shell)
     constexpr int PER = DIM;
-    for (int it = threadIdx.x; it < npts * PER; it += blockDim.x) {
+    // 256-thread workgroups deal the items of a block to lanes transposed:
+    // lane l of wave w takes item 4 l + w, so one wave's atomics come from
+    // points four items apart instead of neighbours along a sheet (whose
+    // stencils overlap, and whose atomics on one address queue).  The dense
+    // 1024-thread kernel keeps the items in order (transposed, the 128^3
+    // shell of the closure's coarse step spread slower).
+    const int perm = NT == 256 ? (int)(threadIdx.x % 64) * 4 + (int)(threadIdx.x / 64)
+                               : (int)threadIdx.x;
+    for (int base = 0; base < npts * PER; base += NT) {
+      const int it = base + perm;
+      if (it >= npts * PER) continue;
       const int pi = it / PER;
       int slot = 0;
       while (c_pref[slot + 1] <= pi) slot++;
