@@ -532,7 +532,8 @@ static void launch_interp(ib_ctx *c, int id, const double *X, int64_t np,
 }
 
 template <int DIM>
-static void launch_force(ib_ctx *c, const double *Xh, double *F, bool commit) {
+static void launch_force(ib_ctx *c, const double *Xh, double *F, bool commit,
+                         bool bin = false) {
   ForceArgs<DIM> a{};
   a.ptr = c->ptr;
   a.nbr = c->nbr;
@@ -547,8 +548,13 @@ static void launch_force(ib_ctx *c, const double *Xh, double *F, bool commit) {
   a.ty = c->ty;
   for (int i = 0; i < DIM; i++) a.box[i] = c->prm.n[i] * c->prm.h;
   launch(c, KP_FORCE, [&] {
-    hipLaunchKernelGGL((k_force<DIM>), dim3((unsigned)((c->np + 255) / 256)), dim3(256), 0,
-                       c->stream, a);
+    if (bin)  // also the spreading tiles and ranks of the points at Xh
+      hipLaunchKernelGGL((k_force_bin<DIM>), dim3((unsigned)((c->np + 255) / 256)), dim3(256), 0,
+                         c->stream, a, c->p_layer, c->g, c->tg, 1.0 / c->prm.h, c->t_count,
+                         c->tile_of, c->rank_of);
+    else
+      hipLaunchKernelGGL((k_force<DIM>), dim3((unsigned)((c->np + 255) / 256)), dim3(256), 0,
+                         c->stream, a);
   });
 }
 
@@ -559,14 +565,15 @@ static void launch_force(ib_ctx *c, const double *Xh, double *F, bool commit) {
 // entry point).
 template <typename T, int DIM, bool ADD>
 static void launch_spread(ib_ctx *c, const double *X, const double *F, const double *w,
-                          int64_t np, void *const f[3]) {
+                          int64_t np, void *const f[3], bool binned = false) {
   const double inv_h = 1.0 / c->prm.h;
   const unsigned pb = (unsigned)((np + 255) / 256);
   const unsigned nb = (unsigned)((c->tg.ntiles + SCAN_TILE - 1) / SCAN_TILE);
-  launch(c, KP_SORT, [&] {
-    hipLaunchKernelGGL((k_bin<DIM>), dim3(pb), dim3(256), 0, c->stream, X, c->p_layer, np,
-                       c->g, c->tg, inv_h, c->t_count, c->tile_of, c->rank_of);
-  });
+  if (!binned)  // (binned: k_force_bin has placed the points in their tiles)
+    launch(c, KP_SORT, [&] {
+      hipLaunchKernelGGL((k_bin<DIM>), dim3(pb), dim3(256), 0, c->stream, X, c->p_layer, np,
+                         c->g, c->tg, inv_h, c->t_count, c->tile_of, c->rank_of);
+    });
   if (c->tg.ntiles <= SCAN_ONE_MAX) {
     launch(c, KP_SORT, [&] {
       hipLaunchKernelGGL(k_scan_one, dim3(1), dim3(SCAN_ONE_THREADS), 0, c->stream, c->t_count,
@@ -741,9 +748,9 @@ static void enqueue_lagrangian(ib_ctx *c, bool first) {
   // Steps 1a-1c
   launch_interp<V, DIM>(c, KP_INTERP_EVOLVE, c->buf.X, c->np, c->buf.u, c->buf.U_prev,
                         true, first);
-  // Step 2a (+ commit X^{n+1}) and Step 2b
-  launch_force<DIM>(c, c->Xh, c->F, true);
-  launch_spread<T, DIM, false>(c, c->Xh, c->F, c->w, c->np, c->f);
+  // Step 2a (+ commit X^{n+1}, + the points' spreading tiles) and Step 2b
+  launch_force<DIM>(c, c->Xh, c->F, true, true);
+  launch_spread<T, DIM, false>(c, c->Xh, c->F, c->w, c->np, c->f, true);
 }
 
 // One full IB-GM step (Steps 1a-3f) at step index n.  T: work arrays; V:

@@ -255,8 +255,7 @@ struct ForceArgs {
 };
 
 template <int DIM>
-__global__ void __launch_bounds__(256) k_force(ForceArgs<DIM> a) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void force_point(const ForceArgs<DIM> &a, int64_t k) {
   if (k >= a.np) return;
   double xk[DIM], f[DIM];
   for (int c = 0; c < DIM; c++) {
@@ -288,6 +287,11 @@ __global__ void __launch_bounds__(256) k_force(ForceArgs<DIM> a) {
   for (int c = 0; c < DIM; c++) a.F[c * a.np + k] = f[c];
   if (a.Xn1)
     for (int c = 0; c < DIM; c++) a.X[c * a.np + k] = a.Xn1[c * a.np + k];
+}
+
+template <int DIM>
+__global__ void __launch_bounds__(256) k_force(ForceArgs<DIM> a) {
+  force_point<DIM>(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
 // ----------------------------------------------------- Lagrangian: Step 2b --
@@ -323,11 +327,11 @@ __device__ __forceinline__ int anchor_cell(double x, double inv_h, int n) {
 // taken per wave: lanes that fall in the same tile (neighbouring points
 // usually do) share one atomic on its counter and number themselves in lane
 // order, so a dense structure does not queue its points on one address.
+// (every lane of the wave calls it, for the ballots)
 template <int DIM>
-__global__ void __launch_bounds__(256) k_bin(const double *X, const int *layer, int64_t np,
-                                              Grid g, TileGrid tg, double inv_h, int *count,
-                                              int *tile_of, int *rank_of) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void bin_point(const double *X, const int *layer, int64_t np, Grid g,
+                                          TileGrid tg, double inv_h, int *count, int *tile_of,
+                                          int *rank_of, int64_t k) {
   const bool valid = k < np;
   const int32_t nn[3] = {g.n0, g.n1, g.n2};
   int t = -1;
@@ -363,6 +367,27 @@ __global__ void __launch_bounds__(256) k_bin(const double *X, const int *layer, 
     tile_of[k] = t;
     rank_of[k] = base + within;
   }
+}
+
+template <int DIM>
+__global__ void __launch_bounds__(256) k_bin(const double *X, const int *layer, int64_t np,
+                                              Grid g, TileGrid tg, double inv_h, int *count,
+                                              int *tile_of, int *rank_of) {
+  bin_point<DIM>(X, layer, np, g, tg, inv_h, count, tile_of, rank_of,
+                 (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// Steps 2a and the first pass of 2b in one launch, one thread per point: the
+// link force at X^{n+1/2} (committing X^{n+1}), then the point's spreading
+// tile and rank, from the same X^{n+1/2}.  (The force writes F and X; the
+// binning reads only X^{n+1/2}.)
+template <int DIM>
+__global__ void __launch_bounds__(256) k_force_bin(ForceArgs<DIM> a, const int *layer, Grid g,
+                                                    TileGrid tg, double inv_h, int *count,
+                                                    int *tile_of, int *rank_of) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  force_point<DIM>(a, k);
+  bin_point<DIM>(a.Xh, layer, a.np, g, tg, inv_h, count, tile_of, rank_of, k);
 }
 
 // Exclusive scan of the per-tile counts into start[0..ntiles] in three
