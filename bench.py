@@ -34,7 +34,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # x 2.0 + WRITE_SIZE x 1.0, calibrated on a device copy), taken on the kernel
 # as it is built now; see profiles/hbm_counters_shell3d_256.md.  None when not
 # measured for the current build.
-TRAFFIC_BYTES = {"explicit": 1.0520e9}
+TRAFFIC_BYTES = {"explicit": 1.0553e9}
 
 
 def parse():
